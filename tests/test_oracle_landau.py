@@ -1,0 +1,224 @@
+"""Pins of the FP64 oracle against closed forms, brute force and invariants (CPU only).
+
+Each test is chosen so that a plausible slip in the oracle (a dropped term in
+Delta, a wrong sign of the step, a wrong neighbour, a transposed product, a
+wrong momentum or FFT normalisation) fails at least one of them.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import landau, observables, su3
+from paper_1208_1186_amd import synth
+
+ALPHA = 0.08
+
+
+def unit_links(dims):
+    shp = synth.lattice_shape(dims)
+    return np.broadcast_to(np.eye(3, dtype=np.complex128), shp + (4, 3, 3)).copy()
+
+
+# --------------------------------------------------------------- closed forms
+
+def test_unit_configuration():
+    u = unit_links((4, 4, 4, 4))
+    assert landau.functional(u) == 1.0
+    assert landau.theta(u) == 0.0
+    assert observables.plaquette(u) == pytest.approx(1.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("phi", [0.3, 1.1, 2.9])
+def test_single_link_closed_form(phi):
+    """One non-trivial link U_0(x0) = diag(e^{i phi}, e^{-i phi}, 1), all others 1."""
+    dims = (4, 4, 4, 4)
+    vol = 256
+    u = unit_links(dims)
+    x0 = (1, 2, 3, 2)  # (t, z, y, x)
+    u[x0][0] = np.diag([np.exp(1j * phi), np.exp(-1j * phi), 1.0])
+    assert landau.functional(u) == pytest.approx(1 - (1 - np.cos(phi)) / (6 * vol), abs=1e-15)
+    assert landau.theta(u) == pytest.approx(16 * np.sin(phi) ** 2 / (3 * vol), abs=1e-15)
+    assert observables.plaquette(u) == pytest.approx(1 - (2 / 3) * (1 - np.cos(phi)) / vol, abs=1e-15)
+    d = landau.divergence(u)
+    want = np.diag([-2j * np.sin(phi), 2j * np.sin(phi), 0.0])
+    assert np.max(np.abs(d[x0] - want)) < 1e-15
+    xp = (1, 2, 3, 3)  # x0 + x-hat
+    assert np.max(np.abs(d[xp] + want)) < 1e-15
+    mask = np.ones(d.shape[:4], bool)
+    mask[x0] = mask[xp] = False
+    assert np.max(np.abs(d[mask])) == 0.0
+
+
+def test_laplacian_eigenvalues_pin_momentum():
+    """p^2(n) is the eigenvalue of minus the lattice Laplacian on the plane wave n."""
+    dims = (4, 6, 2, 8)
+    p2 = landau.momentum_sq(dims)
+    nx, ny, nz, nt = dims
+    t, z, y, x = np.meshgrid(np.arange(nt), np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for n in [(1, 0, 0, 0), (2, 3, 1, 5), (3, 1, 0, 7), (0, 0, 1, 4)]:
+        wave = np.exp(2j * np.pi * (n[0] * x / nx + n[1] * y / ny + n[2] * z / nz + n[3] * t / nt))
+        lap = sum(np.roll(wave, -1, 3 - mu) + np.roll(wave, 1, 3 - mu) - 2 * wave for mu in range(4))
+        eig = (-lap / wave).real
+        assert np.max(np.abs(eig - p2[n[3], n[2], n[1], n[0]])) < 1e-13
+    assert p2.max() == pytest.approx(16.0, abs=1e-14)
+
+
+def test_filter_inverts_laplacian():
+    """-Lap(Delta~) = p2max * (Delta - mean Delta) and Delta~ has zero mean."""
+    rng = np.random.default_rng(3)
+    d = rng.standard_normal((6, 4, 2, 8, 3, 3)) + 1j * rng.standard_normal((6, 4, 2, 8, 3, 3))
+    dt = landau.fa_filter(d)
+    lap = sum(np.roll(dt, -1, a) + np.roll(dt, 1, a) - 2 * dt for a in range(4))
+    resid = -lap - 16.0 * (d - d.mean(axis=(0, 1, 2, 3)))
+    assert np.max(np.abs(resid)) < 1e-12
+    assert np.max(np.abs(dt.mean(axis=(0, 1, 2, 3)))) < 1e-15
+
+
+def test_filter_matches_brute_force_dft():
+    """O(V^2) DFT with K built from the explicit mode sum, on 2 x 4 x 2 x 6."""
+    dims = (2, 4, 2, 6)
+    nx, ny, nz, nt = dims
+    rng = np.random.default_rng(4)
+    shp = (nt, nz, ny, nx)
+    d = rng.standard_normal(shp + (3, 3)) + 1j * rng.standard_normal(shp + (3, 3))
+    sites = list(itertools.product(range(nt), range(nz), range(ny), range(nx)))
+    ph = np.array([[np.exp(-2j * np.pi * (n[3] * s[3] / nx + n[2] * s[2] / ny + n[1] * s[1] / nz
+                                          + n[0] * s[0] / nt)) for s in sites] for n in sites])
+    p2 = np.array([sum(2 - 2 * np.cos(2 * np.pi * k / nn) for k, nn in zip(n[::-1], dims)) for n in sites])
+    kern = np.where(p2 > 1e-12, 16.0 / np.where(p2 > 1e-12, p2, 1.0), 0.0)
+    flat = d.reshape(len(sites), 9)
+    want = (np.conj(ph).T @ (kern[:, None] * (ph @ flat))) / len(sites)
+    got = landau.fa_filter(d).reshape(len(sites), 9)
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+def _abelian_field(dims, amp, seed):
+    """Diagonal (Cartan) links diag(e^{ia}, e^{ib}, e^{-i(a+b)}) with small random angles."""
+    rng = np.random.default_rng(seed)
+    shp = synth.lattice_shape(dims)
+    a = amp * rng.standard_normal(shp + (4,))
+    b = amp * rng.standard_normal(shp + (4,))
+    u = np.zeros(shp + (4, 3, 3), np.complex128)
+    u[..., 0, 0] = np.exp(1j * a)
+    u[..., 1, 1] = np.exp(1j * b)
+    u[..., 2, 2] = np.exp(-1j * (a + b))
+    return u
+
+
+def test_free_field_contraction_fourier_accelerated():
+    """Linearised FA contracts every p != 0 mode of the divergence by 1 - 16 alpha: theta ratio 0.0784."""
+    u = _abelian_field((8, 4, 6, 4), 1e-3, 5)
+    th0 = landau.theta(u)
+    u1, *_ = landau.fa_step(u, ALPHA)
+    assert landau.theta(u1) / th0 == pytest.approx((1 - 16 * ALPHA) ** 2, rel=1e-4)
+
+
+def test_plane_wave_contraction_plain_sd():
+    """Without acceleration one step multiplies a plane wave's divergence by 1 - alpha p^2."""
+    dims = (8, 4, 4, 4)
+    shp = synth.lattice_shape(dims)
+    x = np.arange(8)[None, None, None, :] * np.ones(shp)
+    amp = 1e-4
+    a = amp * np.sin(2 * np.pi * x / 8)
+    u = np.zeros(shp + (4, 3, 3), np.complex128)
+    u[..., :, :, :] = np.eye(3)
+    u[..., 0, 0, 0] = np.exp(1j * a)
+    u[..., 0, 1, 1] = np.exp(-1j * a)
+    p2 = 4 * np.sin(np.pi / 8) ** 2
+    th0 = landau.theta(u)
+    _, info = landau.fix(u, tol=0, max_iter=1, alpha=ALPHA, plain_sd=True)
+    assert info["history"][1][0] / th0 == pytest.approx((1 - ALPHA * p2) ** 2, rel=1e-6)
+    _, info = landau.fix(u, tol=0, max_iter=1, alpha=ALPHA)
+    assert info["history"][1][0] / th0 == pytest.approx((1 - 16 * ALPHA) ** 2, rel=1e-6)
+
+
+# ----------------------------------------------------------------- invariants
+
+def test_divergence_structure():
+    u = synth.make_config((4, 4, 6, 2), 1)
+    d = landau.divergence(u)
+    assert np.max(np.abs(d + su3.dag(d))) < 1e-15            # anti-Hermitian
+    assert np.max(np.abs(su3.trace(d))) < 1e-14              # traceless (entries are O(5))
+    assert np.max(np.abs(d.sum(axis=(0, 1, 2, 3)))) < 1e-12  # telescopes to zero
+
+
+def test_gauge_invariants_under_random_transform():
+    u = synth.make_config((4, 4, 4, 6), 2)
+    g = synth.haar_su3(u.shape[:4], np.random.default_rng(9))
+    v = landau.apply_gauge(u, g)
+    assert observables.plaquette(v) == pytest.approx(observables.plaquette(u), abs=1e-13)
+    assert observables.rectangle(v) == pytest.approx(observables.rectangle(u), abs=1e-13)
+    assert abs(observables.polyakov(v) - observables.polyakov(u)) < 1e-13
+    # The singlet correlator is gauge variant: a random transform changes it.
+    assert abs(observables.singlet_correlator(v, 1) - observables.singlet_correlator(u, 1)) > 1e-3
+
+
+def test_first_order_step_increases_F():
+    u = synth.make_config((4, 4, 4, 4), 3)
+    f0 = landau.functional(u)
+    u1, g, d, dt = landau.fa_step(u, ALPHA)
+    assert landau.functional(u1) > f0
+    assert su3.unitarity_error(g) < 1e-14 and su3.det_error(g) < 1e-14
+    # Delta~ keeps the symmetry of Delta (the filter is real and even).
+    assert np.max(np.abs(dt + su3.dag(dt))) < 1e-14
+    assert np.max(np.abs(su3.trace(dt))) < 1e-14
+
+
+def test_fix_8x4_reference_run():
+    """8^4, seed 0, plaquette ~0.59, alpha = 0.08, theta < 1e-15."""
+    u = synth.make_config((8, 8, 8, 8), 0)
+    p0, r0 = observables.plaquette(u), observables.rectangle(u)
+    uf, info = landau.fix(u, tol=1e-15, max_iter=2000, alpha=ALPHA)
+    assert info["converged"] and info["theta"] < 1e-15
+    assert observables.plaquette(uf) == pytest.approx(p0, abs=1e-12)
+    assert observables.rectangle(uf) == pytest.approx(r0, abs=1e-12)
+    assert su3.unitarity_error(uf) < 1e-12 and su3.det_error(uf) < 1e-12
+    hist = np.array(info["history"])
+    active = hist[:-1, 0] > 1e-10
+    assert np.all(np.diff(hist[:, 1])[active] >= -1e-13)       # F non-decreasing
+    # The accumulated transform maps the input onto the result.
+    assert np.max(np.abs(landau.apply_gauge(u, info["gauge"]) - uf)) < 1e-11
+
+
+def test_exact_exponential_variant_converges():
+    u = synth.make_config((4, 4, 4, 4), 4)
+    uf, info = landau.fix(u, tol=1e-15, max_iter=2000, alpha=ALPHA, exact_exp=True)
+    assert info["converged"]
+    assert observables.plaquette(uf) == pytest.approx(observables.plaquette(u), abs=1e-12)
+
+
+def test_pure_gauge_small_angle_recovers_unit_links():
+    for seed in range(8):
+        u = synth.pure_gauge((4, 4, 4, 4), seed, angle=0.1)
+        uf, info = landau.fix(u, tol=1e-15, max_iter=2000, alpha=ALPHA)
+        assert info["converged"]
+        assert info["F"] >= 1 - 1e-12
+
+
+def test_pure_gauge_haar_majority_reaches_vacuum():
+    ok = 0
+    for seed in range(8):
+        u = synth.pure_gauge((4, 4, 4, 4), 100 + seed)
+        uf, info = landau.fix(u, tol=1e-15, max_iter=5000, alpha=ALPHA)
+        ok += info["converged"] and info["F"] >= 1 - 1e-12
+    assert ok >= 5
+
+
+def test_packed_four_field_filter_equivalence():
+    """Filtering Delta01, Delta02, Delta12 and d0 + i d1 equals filtering all 9 entries."""
+    u = synth.make_config((4, 6, 4, 2), 6)
+    d = landau.divergence(u)
+    dt = landau.fa_filter(d)
+    z = np.stack([d[..., 0, 1], d[..., 0, 2], d[..., 1, 2], d[..., 0, 0].imag + 1j * d[..., 1, 1].imag], -1)
+    kern = landau.fa_kernel(landau.dims_of(d))
+    import scipy.fft
+    zt = scipy.fft.ifftn(scipy.fft.fftn(z, axes=(0, 1, 2, 3)) * kern[..., None], axes=(0, 1, 2, 3))
+    rebuilt = np.zeros_like(dt)
+    rebuilt[..., 0, 1], rebuilt[..., 0, 2], rebuilt[..., 1, 2] = zt[..., 0], zt[..., 1], zt[..., 2]
+    rebuilt[..., 1, 0], rebuilt[..., 2, 0], rebuilt[..., 2, 1] = (-np.conj(zt[..., 0]), -np.conj(zt[..., 1]),
+                                                                  -np.conj(zt[..., 2]))
+    rebuilt[..., 0, 0] = 1j * zt[..., 3].real
+    rebuilt[..., 1, 1] = 1j * zt[..., 3].imag
+    rebuilt[..., 2, 2] = -1j * (zt[..., 3].real + zt[..., 3].imag)
+    assert np.max(np.abs(rebuilt - dt)) < 1e-14
