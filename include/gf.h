@@ -1,0 +1,149 @@
+/*
+ * gf.h - C ABI of libgf, Landau gauge fixing of SU(3) lattice gauge fields by
+ * Fourier-accelerated steepest descent on one AMD MI355X (gfx950).
+ *
+ * The problem (paper, Section 1): given links U_mu(x) in SU(3) on a periodic
+ * 4D lattice, find a gauge transform g(x) that maximises the Landau functional
+ *     F = 1/(4*3*V) sum_x sum_mu Re Tr U_mu(x)
+ * by steepest descent with Fourier acceleration (Davies et al. 1988). One
+ * iteration computes the lattice divergence
+ *     Delta(x) = M - M^dag - (1/3) Tr(M - M^dag),  M = sum_mu [U_mu(x-mu) - U_mu(x)],
+ * filters it in momentum space by p2max/p^2 (Section 2.2: every matrix element
+ * is transformed separately; the 4D FFT is split 2D + 2D), forms
+ *     g(x) = reunitarize(1 + (alpha/2) Delta~(x))
+ * and applies U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag. Quality:
+ *     theta = 1/(3V) sum_x Tr[Delta Delta^dag].
+ * Links may be stored with all 18 reals or with the first two rows only
+ * (12 reals; the third row is rebuilt from unitarity, Section 2.2).
+ *
+ * Layouts. dims = {Nx, Ny, Nz, Nt}; site s = x + Nx*(y + Ny*(z + Nz*t)).
+ * "Canonical links" are complex double (re, im interleaved) in the order
+ * [s][mu][row][col], i.e. 4*9 complex per site, mu = 0..3 for x, y, z, t.
+ * "Canonical matrix field" is complex double [s][row][col].
+ *
+ * Ownership. The caller owns every device buffer (links, workspace, outputs);
+ * libgf allocates no device memory. The context is a small host object. All
+ * device work is queued on the caller's stream; calls that return scalars
+ * synchronise that stream. Pointers named d_* are device pointers.
+ *
+ * Errors. Every call returns a gf_status and never throws. GF_EINVAL and
+ * GF_ENOTSUP leave every buffer untouched. GF_ENOTCONV: the iteration limit
+ * was reached; links hold the last iterate and the result is filled in.
+ * GF_ENUMERIC: theta is NaN or infinite. GF_EDEVICE: a HIP call failed
+ * (gf_last_error gives the HIP message).
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gf_ctx gf_ctx;
+
+typedef enum {
+    GF_OK = 0,
+    GF_EINVAL = 1,    /* bad argument (null pointer, bad size, tol <= 0, ...) */
+    GF_ENOTSUP = 2,   /* valid but unsupported (extent not even or not 2^a 3^b, too large) */
+    GF_EDEVICE = 3,   /* HIP runtime error */
+    GF_ENOTCONV = 4,  /* max_iter reached before theta < tol */
+    GF_ENUMERIC = 5,  /* theta not finite */
+    GF_ESTATE = 6     /* call not valid in the context's current state */
+} gf_status;
+
+/* Link storage and arithmetic precision of the bulk iterations. */
+typedef enum {
+    GF_FP64_18 = 0,   /* double, full 3x3 matrix */
+    GF_FP64_12 = 1,   /* double, rows 1-2, row 3 rebuilt on every read */
+    GF_FP32_12 = 2,   /* float, rows 1-2 (re-orthonormalised on write) */
+    GF_FP32_18 = 3,   /* float, full matrix */
+    GF_MIXED = 4      /* FP32-12 until theta < switch_theta, then FP64-18 */
+} gf_precision;
+
+enum {
+    GF_FLAG_EXACT_EXP = 1u << 0,   /* reserved: g = exp((alpha/2) Delta~) instead of first order */
+    GF_FLAG_NO_FA = 1u << 1        /* plain steepest descent: K(p) = 1 instead of p2max/p^2 */
+};
+
+typedef struct {
+    int32_t dims[4];       /* Nx, Ny, Nz, Nt: each even, >= 2, of the form 2^a 3^b, <= 64 */
+    int32_t precision;     /* gf_precision */
+    double alpha;          /* step size (0.08 in the reference workloads) */
+    double switch_theta;   /* GF_MIXED: theta at which FP32 hands over to FP64 (1e-8) */
+    int32_t check_every;   /* host reads theta every this many iterations (>= 1) */
+    uint32_t flags;        /* GF_FLAG_* */
+} gf_params;
+
+typedef struct {
+    int64_t iters;         /* updates applied since gf_init */
+    double theta;          /* quality of the current links */
+    double F;              /* functional of the current links */
+    int32_t phase;         /* 0: FP32 bulk (GF_MIXED only), 1: FP64 */
+    int32_t fallbacks;     /* reserved */
+    double seconds;        /* wall time of the call */
+} gf_result;
+
+/* Bytes of device workspace gf_init needs for these parameters (0 if invalid). */
+size_t gf_workspace_bytes(const gf_params* params);
+
+/*
+ * Create a context. d_links: canonical links (V*36 complex double), read now
+ * and overwritten with the current iterate at the end of every gf_iterate /
+ * gf_fix_until. d_workspace: >= gf_workspace_bytes(params) bytes, 256-byte
+ * aligned, owned by the caller and untouched by it while the context lives.
+ * stream: a hipStream_t (NULL = default stream). Measures theta and F of the
+ * input before returning.
+ */
+gf_status gf_init(gf_ctx** ctx, const gf_params* params, void* d_links,
+                  void* d_workspace, size_t workspace_bytes, void* stream);
+
+/* Apply exactly n >= 0 updates (no stopping test); result holds theta, F after them. */
+gf_status gf_iterate(gf_ctx* ctx, int64_t n, gf_result* result);
+
+/*
+ * Iterate until theta < theta_tol (theta measured before each update), or
+ * until max_iter updates have been applied in this call (GF_ENOTCONV).
+ */
+gf_status gf_fix_until(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf_result* result);
+
+/* theta and F of the current links, in double precision. */
+gf_status gf_quality(gf_ctx* ctx, double* theta, double* F);
+
+/* Write the current links to d_out in canonical layout (d_out may be the input buffer). */
+gf_status gf_get_links(gf_ctx* ctx, void* d_out);
+
+/*
+ * Copy the last n recorded (theta_k, F_k) pairs, k = iters-n+1 .. iters, into
+ * host arrays (n <= 16384 and n <= iters + 1).
+ */
+gf_status gf_history(gf_ctx* ctx, int64_t n, double* h_theta, double* h_F);
+
+/*
+ * Single-stage entry points (used to check each step separately; they do not
+ * advance the iteration count).
+ *   gf_stage_divergence: Delta(x) of the current links -> d_delta (canonical
+ *     matrix field); also refreshes theta and F.
+ *   gf_stage_filter: d_in (canonical anti-Hermitian traceless field) ->
+ *     d_out = (alpha/2) * IFFT[K(p) FFT[d_in]] (canonical matrix field).
+ *   gf_stage_update: U_mu(x) -> g U_mu(x) g(x+mu)^dag with
+ *     g = reunitarize(1 + d_scaled(x)), d_scaled a canonical field that already
+ *     holds (alpha/2) Delta~.
+ */
+gf_status gf_stage_divergence(gf_ctx* ctx, void* d_delta);
+gf_status gf_stage_filter(gf_ctx* ctx, const void* d_in, void* d_out);
+gf_status gf_stage_update(gf_ctx* ctx, const void* d_scaled);
+
+/* Message of the last error on this context (or of the last failed gf_init if ctx is NULL). */
+const char* gf_last_error(const gf_ctx* ctx);
+
+/* Free the host context (the caller frees its own device buffers). */
+void gf_destroy(gf_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H */

@@ -1,0 +1,268 @@
+// Device-side building blocks for libgf: complex arithmetic, SU(3) algebra,
+// link storage access, site geometry and block reductions (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace gf {
+
+// ------------------------------------------------------------------ complex
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// conj(a) * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulcc(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, -(a.re * b.im + a.im * b.re)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+// acc + a*b
+template <typename T>
+__device__ __forceinline__ cx<T> cfma(cx<T> acc, cx<T> a, cx<T> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(-a.im, b.im, acc.re);
+    acc.im = fma(a.re, b.im, acc.im);
+    acc.im = fma(a.im, b.re, acc.im);
+    return acc;
+}
+// acc + a*conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cfmac(cx<T> acc, cx<T> a, cx<T> b) {
+    acc.re = fma(a.re, b.re, acc.re);
+    acc.re = fma(a.im, b.im, acc.re);
+    acc.im = fma(a.im, b.re, acc.im);
+    acc.im = fma(-a.re, b.im, acc.im);
+    return acc;
+}
+
+__device__ __forceinline__ double inv_sqrt(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float inv_sqrt(float x) { return __frsqrt_rn(x); }
+
+// ------------------------------------------------------------------- SU(3)
+template <typename T>
+struct su3 {
+    cx<T> e[3][3];
+};
+
+// Row 3 of an SU(3) matrix from rows 1 and 2: r3 = conj(r1 x r2).
+template <typename T>
+__device__ __forceinline__ void third_row(const cx<T>* r1, const cx<T>* r2, cx<T>* r3) {
+    r3[0] = conj(cmul(r1[1], r2[2]) - cmul(r1[2], r2[1]));
+    r3[1] = conj(cmul(r1[2], r2[0]) - cmul(r1[0], r2[2]));
+    r3[2] = conj(cmul(r1[0], r2[1]) - cmul(r1[1], r2[0]));
+}
+
+// Row Gram-Schmidt onto SU(3): normalise r1, orthogonalise and normalise r2,
+// rebuild r3 from unitarity and det = 1.
+template <typename T>
+__device__ __forceinline__ void reunitarize(su3<T>& m) {
+    T n1 = norm2(m.e[0][0]) + norm2(m.e[0][1]) + norm2(m.e[0][2]);
+    T i1 = inv_sqrt(n1);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[0][j] = cscale(m.e[0][j], i1);
+    cx<T> d = {T(0), T(0)};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) d = cfma(d, conj(m.e[0][j]), m.e[1][j]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[1][j] = m.e[1][j] - cmul(d, m.e[0][j]);
+    T n2 = norm2(m.e[1][0]) + norm2(m.e[1][1]) + norm2(m.e[1][2]);
+    T i2 = inv_sqrt(n2);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m.e[1][j] = cscale(m.e[1][j], i2);
+    third_row(m.e[0], m.e[1], m.e[2]);
+}
+
+// c = a * b
+template <typename T>
+__device__ __forceinline__ su3<T> mul(const su3<T>& a, const su3<T>& b) {
+    su3<T> c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cmul(a.e[i][0], b.e[0][j]);
+            s = cfma(s, a.e[i][1], b.e[1][j]);
+            s = cfma(s, a.e[i][2], b.e[2][j]);
+            c.e[i][j] = s;
+        }
+    return c;
+}
+
+// c = a * b^dagger, rows 0..NR-1 of c only
+template <typename T, int NR = 3>
+__device__ __forceinline__ su3<T> mul_adj(const su3<T>& a, const su3<T>& b) {
+    su3<T> c;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cmulc(a.e[i][0], b.e[j][0]);
+            s = cfmac(s, a.e[i][1], b.e[j][1]);
+            s = cfmac(s, a.e[i][2], b.e[j][2]);
+            c.e[i][j] = s;
+        }
+    return c;
+}
+
+// rows 0..NR-1 of a * b
+template <typename T, int NR>
+__device__ __forceinline__ su3<T> mul_rows(const su3<T>& a, const su3<T>& b) {
+    su3<T> c;
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> s = cmul(a.e[i][0], b.e[0][j]);
+            s = cfma(s, a.e[i][1], b.e[1][j]);
+            s = cfma(s, a.e[i][2], b.e[2][j]);
+            c.e[i][j] = s;
+        }
+    return c;
+}
+
+// g = reunitarize(1 + X), X the anti-Hermitian traceless matrix packed in four
+// complex numbers: X01 = z0, X02 = z1, X12 = z2, X00 = i Re z3, X11 = i Im z3.
+template <typename T>
+__device__ __forceinline__ su3<T> g_from_packed(cx<T> z0, cx<T> z1, cx<T> z2, cx<T> z3) {
+    su3<T> g;
+    g.e[0][0] = {T(1), z3.re};
+    g.e[0][1] = z0;
+    g.e[0][2] = z1;
+    g.e[1][0] = {-z0.re, z0.im};
+    g.e[1][1] = {T(1), z3.im};
+    g.e[1][2] = z2;
+    reunitarize(g);
+    return g;
+}
+
+// ------------------------------------------------------------ link storage
+// Structure-of-arrays links: plane (mu*NE + 3*row + col) holds one complex
+// entry of U_mu for every site, planes pstride elements apart. NE = 9 stores
+// the full matrix, NE = 6 rows 1-2 only.
+template <typename T, int NE>
+struct Links {
+    cx<T>* p;
+    size_t ps;
+
+    __device__ __forceinline__ su3<T> load(int mu, size_t s) const {
+        su3<T> u;
+        const cx<T>* b = p + (size_t)(mu * NE) * ps + s;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = b[(size_t)k * ps];
+        if constexpr (NE == 9) {
+#pragma unroll
+            for (int k = 6; k < 9; ++k) u.e[2][k % 3] = b[(size_t)k * ps];
+        } else {
+            third_row(u.e[0], u.e[1], u.e[2]);
+        }
+        return u;
+    }
+    __device__ __forceinline__ void store(int mu, size_t s, const su3<T>& u) const {
+        cx<T>* b = p + (size_t)(mu * NE) * ps + s;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) b[(size_t)k * ps] = u.e[k / 3][k % 3];
+    }
+};
+
+// --------------------------------------------------------------- geometry
+struct Geom {
+    int n[4];          // Nx, Ny, Nz, Nt
+    int64_t vol;       // sites
+    int64_t stride[4]; // 1, Nx, Nx*Ny, Nx*Ny*Nz
+};
+
+__device__ __forceinline__ void site_coords(const Geom& g, int64_t s, int c[4]) {
+    uint32_t r = (uint32_t)s;
+    c[0] = r % (uint32_t)g.n[0];
+    r /= (uint32_t)g.n[0];
+    c[1] = r % (uint32_t)g.n[1];
+    r /= (uint32_t)g.n[1];
+    c[2] = r % (uint32_t)g.n[2];
+    c[3] = r / (uint32_t)g.n[2];
+}
+
+__device__ __forceinline__ int64_t site_back(const Geom& g, int64_t s, const int c[4], int mu) {
+    return c[mu] == 0 ? s + (int64_t)(g.n[mu] - 1) * g.stride[mu] : s - g.stride[mu];
+}
+__device__ __forceinline__ int64_t site_fwd(const Geom& g, int64_t s, const int c[4], int mu) {
+    return c[mu] == g.n[mu] - 1 ? s - (int64_t)(g.n[mu] - 1) * g.stride[mu] : s + g.stride[mu];
+}
+
+// Blocks are dealt to the 8 XCDs round-robin; give each XCD a contiguous run
+// of logical tiles so that neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7;
+    const int xcd = b & 7, idx = b >> 3;
+    return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Deterministic block sum of two doubles; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+    __shared__ double sa[NT / 64], sb[NT / 64];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) {
+            ta += sa[i];
+            tb += sb[i];
+        }
+        a = ta;
+        b = tb;
+    }
+}
+
+// ------------------------------------------------------- device control block
+constexpr int kHist = 16384;
+
+struct Ctl {
+    double theta;     // quality of the current links
+    double F;         // functional of the current links
+    double tol;       // stop when theta < tol
+    long long iters;  // updates applied
+    int done;         // theta < tol reached: later kernels of the loop return at once
+    int numeric;      // theta was not finite
+    double hist_theta[kHist];
+    double hist_F[kHist];
+};
+
+}  // namespace gf

@@ -1,0 +1,142 @@
+// Mixed-radix (2, 3, 4, 8) Stockham FFT stages over data resident in LDS.
+//
+// A length-N transform (N = 2^a 3^b) is a sequence of radix-R stages. With
+// p the product of the radices already applied and m = N/R, butterfly i of a
+// row reads x[i + j*m] (j < R), multiplies input j by W_{pR}^{j*(i mod p)},
+// takes an R-point DFT and writes output j to y[(i - i mod p)*R + i mod p + j*p].
+// The result comes out in natural order (self-sorting). A stage works in
+// place: every thread first loads all its butterflies into registers, the
+// block synchronises, then every thread writes its outputs.
+//
+// Forward transforms use W_N = exp(-2 pi i / N) and are unnormalised; inverse
+// transforms use the conjugate roots and are unnormalised too.
+#pragma once
+
+#include "gf_device.hpp"
+
+namespace gf {
+
+struct FftPlan {
+    int n;        // transform length
+    int nst;      // number of stages
+    int rad[6];   // radix of each stage
+};
+
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) {  // a * (-i) forward, a * (+i) inverse
+    return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+template <int R, typename T, bool INV>
+__device__ __forceinline__ void dft_small(cx<T>* v) {
+    if constexpr (R == 2) {
+        cx<T> a = v[0], b = v[1];
+        v[0] = a + b;
+        v[1] = a - b;
+    } else if constexpr (R == 3) {
+        // X1,2 = a - (b+c)/2 -/+ i (sqrt(3)/2)(b - c) (forward)
+        const T s3 = T(0.86602540378443864676372317075294);
+        cx<T> a = v[0], t1 = v[1] + v[2], t2 = v[1] - v[2];
+        cx<T> mid = {a.re - T(0.5) * t1.re, a.im - T(0.5) * t1.im};
+        cx<T> rot = {-s3 * t2.im, s3 * t2.re};  // i * s3 * t2
+        v[0] = a + t1;
+        if (INV) {
+            v[1] = mid + rot;
+            v[2] = mid - rot;
+        } else {
+            v[1] = mid - rot;
+            v[2] = mid + rot;
+        }
+    } else if constexpr (R == 4) {
+        cx<T> s02 = v[0] + v[2], d02 = v[0] - v[2];
+        cx<T> s13 = v[1] + v[3], d13 = mul_mi<T, INV>(v[1] - v[3]);
+        v[0] = s02 + s13;
+        v[2] = s02 - s13;
+        v[1] = d02 + d13;
+        v[3] = d02 - d13;
+    } else if constexpr (R == 8) {
+        const T h = T(0.70710678118654752440084436210485);
+        cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+        cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+        dft_small<4, T, INV>(e);
+        dft_small<4, T, INV>(o);
+        // W8^1 = (1 -/+ i)/sqrt2, W8^2 = -/+ i, W8^3 = (-1 -/+ i)/sqrt2
+        cx<T> o1 = INV ? cx<T>{h * (o[1].re - o[1].im), h * (o[1].re + o[1].im)}
+                       : cx<T>{h * (o[1].re + o[1].im), h * (o[1].im - o[1].re)};
+        cx<T> o2 = mul_mi<T, INV>(o[2]);
+        cx<T> o3 = INV ? cx<T>{-h * (o[3].re + o[3].im), h * (o[3].re - o[3].im)}
+                       : cx<T>{h * (o[3].im - o[3].re), -h * (o[3].re + o[3].im)};
+        v[0] = e[0] + o[0];
+        v[4] = e[0] - o[0];
+        v[1] = e[1] + o1;
+        v[5] = e[1] - o1;
+        v[2] = e[2] + o2;
+        v[6] = e[2] - o2;
+        v[3] = e[3] + o3;
+        v[7] = e[3] - o3;
+    }
+}
+
+// One radix-R stage over nrows rows of length N in LDS. Row b starts at
+// (b % n0)*s0 + (b / n0)*s1 and its elements are es apart. Consecutive
+// threads take consecutive rows. EPT bounds the elements each thread holds.
+template <int R, int EPT, typename T, bool INV>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int N, int p, int es, int nrows,
+                                          int n0, int s0, int s1) {
+    constexpr int IMAX = (EPT + R - 1) / R;
+    const int m = N / R;
+    const int items = nrows * m;
+    const int nt = blockDim.x;
+    const int twstep = N / (p * R);
+    cx<T> v[IMAX][R];
+    int obase[IMAX];
+#pragma unroll
+    for (int it = 0; it < IMAX; ++it) {
+        const int w = threadIdx.x + it * nt;
+        if (w < items) {
+            const int b = w % nrows, i = w / nrows;
+            const int base = (b % n0) * s0 + (b / n0) * s1;
+            const int k = i % p;
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[it][j] = buf[base + (i + j * m) * es];
+            obase[it] = base + ((i - k) * R + k) * es;
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                cx<T> t = tw[j * k * twstep];
+                if (INV) t.im = -t.im;
+                v[it][j] = cmul(v[it][j], t);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IMAX; ++it) {
+        const int w = threadIdx.x + it * nt;
+        if (w < items) {
+            dft_small<R, T, INV>(v[it]);
+#pragma unroll
+            for (int j = 0; j < R; ++j) buf[obase[it] + j * p * es] = v[it][j];
+        }
+    }
+    __syncthreads();
+}
+
+template <int EPT, typename T, bool INV>
+__device__ __forceinline__ void fft_rows(cx<T>* buf, const cx<T>* tw, const FftPlan& pl, int es, int nrows,
+                                         int n0, int s0, int s1) {
+    int p = 1;
+    for (int s = 0; s < pl.nst; ++s) {
+        const int r = pl.rad[s];
+        if (r == 2)
+            fft_stage<2, EPT, T, INV>(buf, tw, pl.n, p, es, nrows, n0, s0, s1);
+        else if (r == 3)
+            fft_stage<3, EPT, T, INV>(buf, tw, pl.n, p, es, nrows, n0, s0, s1);
+        else if (r == 4)
+            fft_stage<4, EPT, T, INV>(buf, tw, pl.n, p, es, nrows, n0, s0, s1);
+        else
+            fft_stage<8, EPT, T, INV>(buf, tw, pl.n, p, es, nrows, n0, s0, s1);
+        p *= r;
+    }
+}
+
+}  // namespace gf

@@ -1,0 +1,254 @@
+"""Python binding of libgf (C ABI in include/gf.h).
+
+Argument marshalling only: every step of the gauge-fixing iteration runs in
+the HIP kernels of libgf.so. PyTorch supplies device memory and streams.
+The library is loaded on first use after ``import torch`` so that both share
+one HIP runtime; if it has not been built this raises instead of falling
+back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgf.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gf.h")
+
+GF_OK, GF_EINVAL, GF_ENOTSUP, GF_EDEVICE, GF_ENOTCONV, GF_ENUMERIC, GF_ESTATE = range(7)
+STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ENOTSUP", 3: "GF_EDEVICE", 4: "GF_ENOTCONV",
+                5: "GF_ENUMERIC", 6: "GF_ESTATE"}
+PRECISIONS = {"fp64_18": 0, "fp64_12": 1, "fp32_12": 2, "fp32_18": 3, "mixed": 4}
+FLAG_EXACT_EXP = 1 << 0
+FLAG_NO_FA = 1 << 1
+
+
+class gf_params(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int32 * 4), ("precision", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("switch_theta", ctypes.c_double), ("check_every", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class gf_result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("theta", ctypes.c_double), ("F", ctypes.c_double),
+                ("phase", ctypes.c_int32), ("fallbacks", ctypes.c_int32), ("seconds", ctypes.c_double)]
+
+
+class GfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def _signatures(lib):
+    i32, i64, dbl, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    pp, pr = ctypes.POINTER(gf_params), ctypes.POINTER(gf_result)
+    pd = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "gf_workspace_bytes": (sz, [pp]),
+        "gf_init": (i32, [ctypes.POINTER(_P), pp, _P, _P, sz, _P]),
+        "gf_iterate": (i32, [_P, i64, pr]),
+        "gf_fix_until": (i32, [_P, dbl, i64, pr]),
+        "gf_quality": (i32, [_P, pd, pd]),
+        "gf_get_links": (i32, [_P, _P]),
+        "gf_history": (i32, [_P, i64, pd, pd]),
+        "gf_stage_divergence": (i32, [_P, _P]),
+        "gf_stage_filter": (i32, [_P, _P, _P]),
+        "gf_stage_update": (i32, [_P, _P]),
+        "gf_last_error": (ctypes.c_char_p, [_P]),
+        "gf_destroy": (None, [_P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+def load(require_torch=True):
+    """Load libgf.so (after torch, so the HIP runtime is shared). Raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if require_torch:
+            import torch  # noqa: F401  (loads the HIP runtime libgf links against)
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        _lib = _signatures(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def header_functions(path=HEADER):
+    """Names of the functions declared in include/gf.h."""
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gf_[a-z_]+)\s*\(", text)))
+
+
+def make_params(dims, precision="fp64_18", alpha=0.08, switch_theta=1e-8, check_every=1, flags=0):
+    p = gf_params()
+    for i in range(4):
+        p.dims[i] = int(dims[i])
+    p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    p.alpha = float(alpha)
+    p.switch_theta = float(switch_theta)
+    p.check_every = int(check_every)
+    p.flags = int(flags)
+    return p
+
+
+# ------------------------------------------------------------ C ABI wrappers
+
+def gf_workspace_bytes(params):
+    return load().gf_workspace_bytes(ctypes.byref(params))
+
+
+def gf_init(params, d_links, d_workspace, workspace_bytes, stream=0):
+    ctx = _P()
+    st = load().gf_init(ctypes.byref(ctx), ctypes.byref(params), _P(d_links), _P(d_workspace),
+                        workspace_bytes, _P(stream))
+    if st != GF_OK:
+        raise GfError(st, gf_last_error(None))
+    return ctx
+
+
+def gf_last_error(ctx):
+    msg = load().gf_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def _check(ctx, st, allow=(GF_OK,)):
+    if st not in allow:
+        raise GfError(st, gf_last_error(ctx))
+    return st
+
+
+def gf_iterate(ctx, n):
+    r = gf_result()
+    _check(ctx, load().gf_iterate(ctx, int(n), ctypes.byref(r)))
+    return r
+
+
+def gf_fix_until(ctx, tol, max_iter):
+    r = gf_result()
+    st = _check(ctx, load().gf_fix_until(ctx, float(tol), int(max_iter), ctypes.byref(r)),
+                allow=(GF_OK, GF_ENOTCONV))
+    return st, r
+
+
+def gf_quality(ctx):
+    th, f = ctypes.c_double(), ctypes.c_double()
+    _check(ctx, load().gf_quality(ctx, ctypes.byref(th), ctypes.byref(f)))
+    return th.value, f.value
+
+
+def gf_get_links(ctx, d_out):
+    _check(ctx, load().gf_get_links(ctx, _P(d_out)))
+
+
+def gf_history(ctx, n):
+    import numpy as np
+    th = np.zeros(n)
+    f = np.zeros(n)
+    pd = ctypes.POINTER(ctypes.c_double)
+    _check(ctx, load().gf_history(ctx, int(n), th.ctypes.data_as(pd), f.ctypes.data_as(pd)))
+    return th, f
+
+
+def gf_stage_divergence(ctx, d_delta):
+    _check(ctx, load().gf_stage_divergence(ctx, _P(d_delta)))
+
+
+def gf_stage_filter(ctx, d_in, d_out):
+    _check(ctx, load().gf_stage_filter(ctx, _P(d_in), _P(d_out)))
+
+
+def gf_stage_update(ctx, d_scaled):
+    _check(ctx, load().gf_stage_update(ctx, _P(d_scaled)))
+
+
+def gf_destroy(ctx):
+    if ctx:
+        load().gf_destroy(ctx)
+
+
+# ------------------------------------------------------------- convenience
+
+@dataclass
+class Result:
+    status: int
+    iters: int
+    theta: float
+    F: float
+    phase: int
+    fallbacks: int
+    seconds: float
+
+
+def _res(st, r):
+    return Result(st, r.iters, r.theta, r.F, r.phase, r.fallbacks, r.seconds)
+
+
+class GaugeFixer:
+    """Owns a libgf context over a complex128 CUDA tensor of links (Nt, Nz, Ny, Nx, 4, 3, 3).
+
+    The tensor is updated in place at the end of every iterate / fix_until call.
+    """
+
+    def __init__(self, links, precision="fp64_18", alpha=0.08, check_every=1, switch_theta=1e-8, flags=0,
+                 stream=None):
+        import torch
+        if not links.is_cuda or links.dtype != torch.complex128 or not links.is_contiguous():
+            raise ValueError("links must be a contiguous complex128 CUDA tensor")
+        if links.dim() != 7 or tuple(links.shape[4:]) != (4, 3, 3):
+            raise ValueError("links must have shape (Nt, Nz, Ny, Nx, 4, 3, 3)")
+        nt, nz, ny, nx = links.shape[:4]
+        self.dims = (nx, ny, nz, nt)
+        self.links = links
+        self.params = make_params(self.dims, precision, alpha, switch_theta, check_every, flags)
+        nbytes = gf_workspace_bytes(self.params)
+        if nbytes == 0:
+            lib = load()
+            ctx = _P()
+            st = lib.gf_init(ctypes.byref(ctx), ctypes.byref(self.params), None, None, 0, None)
+            raise GfError(st, gf_last_error(None))
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=links.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(links.device)
+        self.ctx = gf_init(self.params, links.data_ptr(), base + off, nbytes, self.stream.cuda_stream)
+
+    def iterate(self, n):
+        return _res(GF_OK, gf_iterate(self.ctx, n))
+
+    def fix_until(self, tol=1e-15, max_iter=100000):
+        st, r = gf_fix_until(self.ctx, tol, max_iter)
+        return _res(st, r)
+
+    def quality(self):
+        return gf_quality(self.ctx)
+
+    def history(self, n):
+        return gf_history(self.ctx, n)
+
+    def get_links(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(self.links)
+        gf_get_links(self.ctx, out.data_ptr())
+        return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            gf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

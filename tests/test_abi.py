@@ -1,0 +1,77 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared
+function, and rejects bad parameters before touching the device."""
+import ctypes
+
+import pytest
+
+from paper_1208_1186_amd import gf
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return gf.load(require_torch=False)
+
+
+def test_exports_every_declared_function(lib):
+    names = gf.header_functions()
+    assert "gf_init" in names and "gf_fix_until" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def _init(lib, params):
+    ctx = gf._P()
+    st = lib.gf_init(ctypes.byref(ctx), ctypes.byref(params), ctypes.c_void_p(256), ctypes.c_void_p(256),
+                     1 << 40, None)
+    return st, ctx
+
+
+@pytest.mark.parametrize("dims,status", [
+    ((8, 8, 8, 5), gf.GF_ENOTSUP),     # odd extent
+    ((8, 8, 8, 10), gf.GF_ENOTSUP),    # radix 5
+    ((8, 8, 8, 128), gf.GF_ENOTSUP),   # beyond the largest extent
+    ((8, 8, 0, 8), gf.GF_EINVAL),      # empty lattice
+    ((8, 8, 1, 8), gf.GF_EINVAL),      # extent below 2
+])
+def test_bad_dims_rejected_before_device(lib, dims, status):
+    p = gf.make_params(dims)
+    assert lib.gf_workspace_bytes(ctypes.byref(p)) == 0
+    st, ctx = _init(lib, p)
+    assert st == status and not ctx.value
+    assert gf.gf_last_error(None)
+
+
+def test_bad_params_rejected(lib):
+    for kw in [dict(alpha=0.0), dict(alpha=float("nan")), dict(check_every=0), dict(precision=9)]:
+        p = gf.make_params((4, 4, 4, 4), **kw)
+        assert lib.gf_workspace_bytes(ctypes.byref(p)) == 0
+        st, ctx = _init(lib, p)
+        assert st == gf.GF_EINVAL and not ctx.value, kw
+
+
+def test_null_pointers_and_small_workspace(lib):
+    p = gf.make_params((4, 4, 4, 4))
+    need = lib.gf_workspace_bytes(ctypes.byref(p))
+    assert need > 0
+    ctx = gf._P()
+    assert lib.gf_init(ctypes.byref(ctx), ctypes.byref(p), None, ctypes.c_void_p(256), need, None) == gf.GF_EINVAL
+    assert lib.gf_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), need - 1,
+                       None) == gf.GF_EINVAL
+    assert lib.gf_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(264), need,
+                       None) == gf.GF_EINVAL  # misaligned workspace
+    assert lib.gf_init(None, ctypes.byref(p), ctypes.c_void_p(256), ctypes.c_void_p(256), need, None) == gf.GF_EINVAL
+
+
+def test_null_context_calls(lib):
+    r = gf.gf_result()
+    assert lib.gf_iterate(None, 1, ctypes.byref(r)) == gf.GF_EINVAL
+    assert lib.gf_fix_until(None, 1e-15, 1, ctypes.byref(r)) == gf.GF_EINVAL
+    lib.gf_destroy(None)
+
+
+def test_workspace_scales_with_precision(lib):
+    sizes = {}
+    for prec in ["fp64_18", "fp64_12", "fp32_12", "fp32_18"]:
+        sizes[prec] = lib.gf_workspace_bytes(ctypes.byref(gf.make_params((16, 16, 16, 16), prec)))
+    assert sizes["fp64_18"] > sizes["fp64_12"] > sizes["fp32_12"]
+    assert sizes["fp64_18"] > sizes["fp32_18"] > sizes["fp32_12"]

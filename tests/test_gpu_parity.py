@@ -1,0 +1,155 @@
+"""Parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Every input is a seeded synthetic configuration; the oracle sees exactly the
+same complex128 links as the GPU. Tolerances (FP64 path): Delta and the
+updated links to 1e-13 absolute (entries are O(1)-O(10) and each is a short
+sum of products, so rounding differences stay at a few 1e-15); the filtered
+field to 1e-12 of its largest entry (two 2D FFTs of length <= 64 per axis);
+theta and F along a whole trajectory to 1e-10 relative / 1e-13 absolute.
+Float paths are held to float-level bounds stated per test.
+"""
+import numpy as np
+import pytest
+
+from oracle import landau, observables, su3
+from paper_1208_1186_amd import gf, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALPHA = 0.08
+SHAPES = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 8, 2), (12, 6, 4, 8), (8, 8, 8, 8), (16, 8, 6, 4), (48, 4, 6, 2),
+          (4, 2, 2, 64)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gf.load()
+
+
+def to_dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def fixer_for(u, precision="fp64_18", **kw):
+    links = to_dev(u)
+    return gf.GaugeFixer(links, precision, **kw), links
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+def test_divergence_theta_F(dims):
+    print(f"divergence dims={dims}", flush=True)
+    u = synth.make_config(dims, 1)
+    fx, _ = fixer_for(u)
+    th, f = fx.quality()
+    d_want = landau.divergence(u)
+    assert abs(th - landau.theta(u)) <= 1e-12 * landau.theta(u)
+    assert abs(f - landau.functional(u)) <= 1e-14
+    out = torch.empty(u.shape[:4] + (3, 3), dtype=torch.complex128, device="cuda:0")
+    gf.gf_stage_divergence(fx.ctx, out.data_ptr())
+    d_got = out.cpu().numpy()
+    assert np.max(np.abs(d_got - d_want)) < 1e-13
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+def test_filter(dims):
+    print(f"filter dims={dims}", flush=True)
+    u = synth.make_config(dims, 2)
+    d = landau.divergence(u)
+    want = 0.5 * ALPHA * landau.fa_filter(d)
+    fx, _ = fixer_for(u)
+    out = torch.empty_like(to_dev(d))
+    gf.gf_stage_filter(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    got = out.cpu().numpy()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+def test_update(dims):
+    print(f"update dims={dims}", flush=True)
+    u = synth.make_config(dims, 3)
+    dt = landau.fa_filter(landau.divergence(u))
+    want = landau.apply_gauge(u, landau.gauge_from_delta(dt, ALPHA))
+    fx, links = fixer_for(u)
+    gf.gf_stage_update(fx.ctx, to_dev(0.5 * ALPHA * dt).data_ptr())
+    got = links.cpu().numpy()
+    assert np.max(np.abs(got - want)) < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64_18", "fp64_12"])
+def test_trajectory_8x4(precision):
+    """8^4, seed 0, plaquette ~0.59, alpha = 0.08, to theta < 1e-15: same iterates as the oracle."""
+    print(f"trajectory 8^4 {precision}", flush=True)
+    u = synth.make_config((8, 8, 8, 8), 0)
+    uo, info = landau.fix(u, 1e-15, 5000, ALPHA)
+    fx, links = fixer_for(u, precision, check_every=4)
+    res = fx.fix_until(1e-15, 5000)
+    assert res.status == gf.GF_OK and res.theta < 1e-15
+    assert res.iters == info["iters"]
+    hist = np.array(info["history"])
+    th, f = fx.history(res.iters + 1)
+    big = hist[:, 0] > 1e-12
+    assert np.max(np.abs(th[big] - hist[big, 0]) / hist[big, 0]) < 1e-10
+    assert np.max(np.abs(th[~big] - hist[~big, 0])) < 1e-20 + 1e-3 * 1e-12
+    assert np.max(np.abs(f - hist[:, 1])) < 1e-13
+    ug = links.cpu().numpy()
+    assert np.max(np.abs(ug - uo)) < 1e-10
+    assert abs(observables.plaquette(ug) - observables.plaquette(u)) < 1e-12
+    assert abs(res.F - info["F"]) < 1e-12
+    assert su3.unitarity_error(ug) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp32_12", "fp32_18"])
+def test_float_paths_descend_and_keep_invariants(precision):
+    print(f"float path {precision}", flush=True)
+    u = synth.make_config((8, 8, 8, 8), 0)
+    fx, links = fixer_for(u, precision, check_every=8)
+    th0, _ = fx.quality()
+    assert abs(th0 - landau.theta(u)) < 1e-5 * landau.theta(u)
+    res = fx.iterate(40)
+    ug = links.cpu().numpy()
+    assert res.theta < 1e-9                        # float floor is ~1e-12 .. 1e-10
+    assert abs(landau.theta(ug) - res.theta) < 1e-6 * 1e-5 + 1e-12
+    assert abs(observables.plaquette(ug) - observables.plaquette(u)) < 2e-5
+    _, info = landau.fix(u, 1e-15, 5000, ALPHA)
+    assert abs(res.F - info["F"]) < 1e-5
+
+
+def test_iterate_counts_and_notconv():
+    u = synth.make_config((4, 4, 4, 4), 5)
+    fx, _ = fixer_for(u, check_every=3)
+    r = fx.iterate(5)
+    assert r.iters == 5
+    r = fx.fix_until(1e-30, 2)
+    assert r.status == gf.GF_ENOTCONV and r.iters == 7
+    r = fx.iterate(0)
+    assert r.iters == 7
+
+
+def test_nan_input_reports_numeric():
+    u = synth.make_config((4, 4, 4, 4), 6)
+    u[1, 2, 3, 0, 2, 1, 1] = np.nan
+    links = to_dev(u)
+    fx = gf.GaugeFixer(links, "fp64_18")
+    with pytest.raises(gf.GfError) as e:
+        fx.fix_until(1e-15, 10)
+    assert e.value.status == gf.GF_ENUMERIC
+
+
+def test_full_size_32x4_one_step():
+    """32^4 (the benchmark lattice), FP64-18: theta, F and one full update against the oracle."""
+    print("full size 32^4 one step", flush=True)
+    dims = (32, 32, 32, 32)
+    u = synth.make_config(dims, 0)
+    fx, links = fixer_for(u)
+    th, f = fx.quality()
+    d = landau.divergence(u)
+    assert abs(th - landau.theta_of_delta(d)) <= 1e-12 * th
+    assert abs(f - landau.functional(u)) <= 1e-14
+    res = fx.iterate(1)
+    u1 = landau.apply_gauge(u, landau.gauge_from_delta(landau.fa_filter(d), ALPHA))
+    ug = links.cpu().numpy()
+    assert np.max(np.abs(ug - u1)) < 1e-13
+    assert abs(res.theta - landau.theta(u1)) <= 1e-12 * res.theta
