@@ -1,0 +1,225 @@
+#!/usr/bin/env python3
+"""Benchmark: Fourier-accelerated Landau gauge fixing on a 32^4 SU(3) lattice, one MI355X.
+
+A step is one full FA iteration through libgf (forward 2D+2D FFT of the
+packed divergence, p2max/p^2 filter, inverse FFT, g(x) and the gauge update,
+divergence and FP64 theta/F reductions of the new links).
+
+Workload: 32^4, seed 0, near-identity links with plaquette ~0.59 followed by
+a Haar-random gauge transform, alpha = 0.08, FP64 links with all 18 reals.
+Inputs are resident in HBM before the timed region. The JSON line also
+carries FP64-12 and FP32-12 rates, wall time to theta < 1e-15, per-kernel
+HIP-event durations of the timed region, the roofline of the dominant
+kernel, and the FP64 NumPy oracle timed on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "FA iterations/s + HBM GB/s on 32^4 SU(3); wall time to θ<1e-15 vs plain FP64"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name, vol, L, S, nblk):
+    """Algorithmic HBM bytes of one launch: every array the kernel must touch, once."""
+    W = 8  # reals per site of the packed divergence (4 complex fields)
+    links = 4 * L * S * vol
+    field = W * S * vol
+    return {
+        "update": 2 * links + field,           # read U and (alpha/2)Delta~, write U
+        "divergence": links + field,           # read U, write Delta
+        "fft_xy_fwd": 2 * field,
+        "fft_zt_filter": 2 * field,
+        "fft_xy_inv": 2 * field,
+        "finalize": 16 * nblk,
+    }[name]
+
+
+STORAGE = {"fp64_18": (18, 8), "fp64_12": (12, 8), "fp32_12": (12, 4), "fp32_18": (18, 4)}
+
+
+def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events):
+    links = u_dev.clone()
+    fx = gf.GaugeFixer(links, precision, check_every=max(steps, warmup, 1))
+    if warmup:
+        fx.iterate(warmup)
+    torch.cuda.synchronize()
+    if with_events:
+        gf.gf_set_timing(fx.ctx, True)
+    t0 = time.perf_counter()
+    res = fx.iterate(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ktimes = gf.gf_kernel_times(fx.ctx) if with_events else None
+    if with_events:
+        gf.gf_set_timing(fx.ctx, False)
+    nblk = (u_dev.shape[0] * u_dev.shape[1] * u_dev.shape[2] * u_dev.shape[3] + 255) // 256
+    fx.close()
+    del links
+    return dt, res, ktimes, nblk
+
+
+def time_to_theta(gf, torch, u_dev, precision, tol=1e-15):
+    links = u_dev.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fx = gf.GaugeFixer(links, precision, check_every=10)
+    r = fx.fix_until(tol, 100000)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fx.close()
+    return dt, r
+
+
+def cpu_baseline(u, budget_s=12.0):
+    """The FP64 NumPy oracle's FA iterations on the same input, on the host cores."""
+    from oracle import landau
+    workers = int(os.environ.get("ORACLE_FFT_WORKERS", str(min(16, os.cpu_count() or 1))))
+    landau.FFT_WORKERS = workers
+    t0 = time.perf_counter()
+    n = 0
+    cur = u
+    while True:
+        cur, *_ = landau.fa_step(cur, 0.08)
+        landau.theta(cur)
+        landau.functional(cur)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 8:
+            break
+    dt = time.perf_counter() - t0
+    return n / dt, n, dt, workers
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--dims", default="32,32,32,32", help="Nx,Ny,Nz,Nt (default: the 32^4 workload)")
+    ap.add_argument("--precision", default="fp64_18")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and time-to-theta")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the lattice would shard in t-slabs with halo exchange and FFT transposes; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1208_1186_amd import gf, synth
+
+    dims = tuple(int(x) for x in args.dims.split(","))
+    nx, ny, nz, nt = dims
+    vol = nx * ny * nz * nt
+    log(f"generating {dims} seed 0 (host)")
+    t0 = time.perf_counter()
+    u = synth.make_config(dims, 0, synth.EPS_P059)
+    log(f"generated in {time.perf_counter() - t0:.1f}s")
+    dev = torch.device("cuda:0")
+    u_dev = torch.from_numpy(u).to(dev)
+    torch.cuda.synchronize()
+    gf.load()
+
+    if args.copy_probe_mb:
+        nel = args.copy_probe_mb * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mb} MiB read + write, 3 launches")
+        del a, b
+
+    prec = args.precision
+    L, S = STORAGE[prec]
+    log(f"timing {prec}: warmup {args.warmup}, steps {args.steps}")
+    dt, res, ktimes, nblk = timed_rate(gf, torch, u_dev, prec, args.steps, args.warmup, with_events=True)
+    ms_per_step = 1e3 * dt / args.steps
+    rate = args.steps / dt
+    b_alg = (8 * L + 8 * 8) * S  # bytes/site/iteration: links read+written once, packed field 8 passes
+    log(f"{prec}: {rate:.1f} it/s, {ms_per_step:.4f} ms/step, theta={res.theta:.3e}")
+
+    kern = {}
+    for name, (ms, cnt) in ktimes.items():
+        if cnt:
+            avg = ms / cnt
+            by = kernel_bytes(name, vol, L, S, nblk)
+            kern[name] = {"avg_ms": round(avg, 5), "launches": cnt, "alg_bytes": by,
+                          "alg_GBps": round(by / (avg * 1e-3) / 1e9, 1)}
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    dk = kern[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": dk["alg_bytes"], "avg_launch_ms": dk["avg_ms"]}
+    events_ms = sum(v["avg_ms"] * v["launches"] for v in kern.values()) / args.steps
+
+    extras = {}
+    if not args.no_extras:
+        for p2 in ["fp64_12", "fp32_12"]:
+            if p2 == prec:
+                continue
+            d2, r2, _, _ = timed_rate(gf, torch, u_dev, p2, args.steps, args.warmup, with_events=False)
+            L2, S2 = STORAGE[p2]
+            extras[f"{p2}_it_per_s"] = round(args.steps / d2, 1)
+            extras[f"{p2}_model_GBps"] = round((8 * L2 + 64) * S2 * vol * args.steps / d2 / 1e9, 1)
+            log(f"{p2}: {args.steps / d2:.1f} it/s")
+        for p2 in ["fp64_18", "fp64_12"]:
+            tt, rr = time_to_theta(gf, torch, u_dev, p2)
+            extras[f"{p2}_time_to_theta_1e-15_s"] = round(tt, 4)
+            extras[f"{p2}_iters_to_theta_1e-15"] = int(rr.iters)
+            extras[f"{p2}_final_theta"] = rr.theta
+            log(f"{p2}: theta<1e-15 in {rr.iters} iterations, {tt:.3f}s (status {rr.status})")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host")
+        crate, cn, cdt, workers = cpu_baseline(u)
+        cpu = {"value": round(crate, 4), "unit": "FA iterations/s", "cores": workers, "kind": "oracle",
+               "sample": f"first {cn} FA iterations of {nx}x{ny}x{nz}x{nt} seed 0 (FP64 NumPy, scipy.fft "
+                         f"workers={workers}), {cdt:.1f}s"}
+        log(f"oracle: {crate:.3f} it/s over {cn} iterations")
+
+    out = {
+        "metric": METRIC,
+        "value": round(rate, 2),
+        "unit": "FA iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if S == 8 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{nx}x{ny}x{nz}x{nt} SU(3) Landau FA steepest descent, {prec} link storage, "
+                               f"seed 0, plaquette~0.59, Haar gauge transform, alpha 0.08",
+                   "lattice": list(dims), "storage": prec, "alpha": 0.08},
+        "hbm_model_GBps": round(b_alg * vol * rate / 1e9, 1),
+        "hbm_model_bytes_per_site": b_alg,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kern,
+        "event_ms_per_step": round(events_ms, 5),
+        **extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,24 @@ gf_status gf_stage_divergence(gf_ctx* ctx, void* d_delta);
 gf_status gf_stage_filter(gf_ctx* ctx, const void* d_in, void* d_out);
 gf_status gf_stage_update(gf_ctx* ctx, const void* d_scaled);
 
+/*
+ * Per-kernel timing with HIP events recorded on the context's stream around
+ * every kernel launch. gf_set_timing(ctx, 1) resets the totals and starts
+ * recording; gf_kernel_times copies, for kernel ids 0..n-1 (GF_K_*), the summed
+ * duration in milliseconds and the number of launches timed.
+ */
+enum {
+    GF_K_FFT_XY_FWD = 0,  /* forward 2D FFT over (x, y) */
+    GF_K_FFT_ZT = 1,      /* 2D FFT over (z, t), filter, inverse (z, t) */
+    GF_K_FFT_XY_INV = 2,  /* inverse 2D FFT over (x, y) */
+    GF_K_UPDATE = 3,      /* g(x) and U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag */
+    GF_K_DIVERGENCE = 4,  /* Delta(x) and block partial sums of F, theta */
+    GF_K_FINALIZE = 5,    /* fixed-order reduction -> theta, F, stop flag */
+    GF_NKERNELS = 8
+};
+gf_status gf_set_timing(gf_ctx* ctx, int32_t enable);
+gf_status gf_kernel_times(gf_ctx* ctx, int32_t n, double* h_ms_total, int64_t* h_counts);
+
 /* Message of the last error on this context (or of the last failed gf_init if ctx is NULL). */
 const char* gf_last_error(const gf_ctx* ctx);
 

@@ -28,6 +28,9 @@ from .su3 import dag, expm_antihermitian, reunitarize, trace
 
 _EYE3 = np.eye(3, dtype=np.complex128)
 
+# Threads scipy.fft may use (-1: all cores); a thread count, not an algorithm choice.
+FFT_WORKERS = -1
+
 
 def dims_of(u):
     """(Nx, Ny, Nz, Nt) from a field of shape (Nt, Nz, Ny, Nx, ...)."""
@@ -88,9 +91,9 @@ def fa_filter(d, kernel=None):
     """Delta~ = IFFT[K(p) FFT[Delta]] over the four site axes, element by element."""
     if kernel is None:
         kernel = fa_kernel(dims_of(d))
-    spec = scipy.fft.fftn(d, axes=(0, 1, 2, 3), workers=-1)
+    spec = scipy.fft.fftn(d, axes=(0, 1, 2, 3), workers=FFT_WORKERS)
     spec *= kernel[..., None, None]
-    return scipy.fft.ifftn(spec, axes=(0, 1, 2, 3), workers=-1)
+    return scipy.fft.ifftn(spec, axes=(0, 1, 2, 3), workers=FFT_WORKERS)
 
 
 def gauge_from_delta(dt, alpha, exact_exp=False):

@@ -191,6 +191,13 @@ struct gf_ctx {
     FftPlan plan[4];
     Ctl* h_head;  // pinned host copy of the control block's leading scalars
     std::string err;
+    // Optional per-kernel HIP-event timing (gf_set_timing / gf_kernel_times).
+    bool timing = false;
+    std::vector<hipEvent_t> ev;   // 2 per pending measurement
+    std::vector<int> ev_kid;
+    int npend = 0;
+    double kt_ms[GF_NKERNELS] = {};
+    long long kt_n[GF_NKERNELS] = {};
 };
 
 namespace {
@@ -213,6 +220,40 @@ gf_status check_hip(gf_ctx* c, hipError_t e, const char* what) {
         if (_s != GF_OK) return _s;                               \
     } while (0)
 
+constexpr int kEventPairs = 4096;
+
+void tdrain(gf_ctx* c) {
+    for (int i = 0; i < c->npend; ++i) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) == hipSuccess) {
+            c->kt_ms[c->ev_kid[i]] += ms;
+            c->kt_n[c->ev_kid[i]] += 1;
+        }
+    }
+    c->npend = 0;
+}
+
+// Record a start event for kernel kid (no-op unless timing is on).
+void tstart(gf_ctx* c, int kid) {
+    if (!c->timing) return;
+    if (c->ev.empty()) {
+        c->ev.resize(2 * kEventPairs);
+        c->ev_kid.resize(kEventPairs);
+        for (auto& e : c->ev) (void)hipEventCreate(&e);
+    }
+    if (c->npend == kEventPairs) {
+        (void)hipStreamSynchronize(c->st);
+        tdrain(c);
+    }
+    c->ev_kid[c->npend] = kid;
+    (void)hipEventRecord(c->ev[2 * c->npend], c->st);
+}
+void tstop(gf_ctx* c) {
+    if (!c->timing) return;
+    (void)hipEventRecord(c->ev[2 * c->npend + 1], c->st);
+    ++c->npend;
+}
+
 template <typename T, int NE>
 Links<T, NE> links_of(gf_ctx* c) {
     return Links<T, NE>{reinterpret_cast<cx<T>*>(c->links), c->L.ps};
@@ -229,31 +270,43 @@ gf_status launch_fft(gf_ctx* c, int force) {
     const int gridB = 4 * L.n[1] * (L.n[0] / L.bx);
     const double coef = 0.5 * c->p.alpha * ((c->p.flags & GF_FLAG_NO_FA) ? 1.0 : 16.0) / (double)L.vol;
     const int no_fa = (c->p.flags & GF_FLAG_NO_FA) ? 1 : 0;
+    tstart(c, GF_K_FFT_XY_FWD);
     hipLaunchKernelGGL((k_fft_xy<T, kEPT, false>), dim3(gridA), dim3(L.thrA), L.ldsA, c->st, Z, L.ps, L.n[0], L.n[1],
                        nzt, L.G, L.rs, c->plan[0], c->plan[1], tw[0], tw[1], c->ctl, force);
+    tstop(c);
+    tstart(c, GF_K_FFT_ZT);
     hipLaunchKernelGGL((k_fft_zt<T, kEPT>), dim3(gridB), dim3(L.thrB), L.ldsB, c->st, Z, L.ps, L.n[0], L.n[1],
                        L.n[2], L.n[3], L.bx, L.tsp, c->plan[2], c->plan[3], tw[2], tw[3],
                        reinterpret_cast<const T*>(c->sin2), (T)coef, no_fa, c->ctl, force);
+    tstop(c);
+    tstart(c, GF_K_FFT_XY_INV);
     hipLaunchKernelGGL((k_fft_xy<T, kEPT, true>), dim3(gridA), dim3(L.thrA), L.ldsA, c->st, Z, L.ps, L.n[0], L.n[1],
                        nzt, L.G, L.rs, c->plan[0], c->plan[1], tw[0], tw[1], c->ctl, force);
+    tstop(c);
     return check_hip(c, hipGetLastError(), "fft launch");
 }
 
 template <typename T, int NE>
 gf_status launch_measure_t(gf_ctx* c, int force) {
     const Layout& L = c->L;
+    tstart(c, GF_K_DIVERGENCE);
     hipLaunchKernelGGL((k_divergence<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c),
                        reinterpret_cast<cx<T>*>(c->Z), L.ps, c->geom, c->part, c->ctl, force);
+    tstop(c);
+    tstart(c, GF_K_FINALIZE);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, L.nblk, 1.0 / (3.0 * (double)L.vol),
                        1.0 / (12.0 * (double)L.vol), c->ctl, force);
+    tstop(c);
     return check_hip(c, hipGetLastError(), "divergence launch");
 }
 
 template <typename T, int NE>
 gf_status launch_update_t(gf_ctx* c, int count) {
     const Layout& L = c->L;
+    tstart(c, GF_K_UPDATE);
     hipLaunchKernelGGL((k_update<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c),
                        reinterpret_cast<const cx<T>*>(c->Z), L.ps, c->geom, c->ctl, count);
+    tstop(c);
     return check_hip(c, hipGetLastError(), "update launch");
 }
 
@@ -284,6 +337,7 @@ gf_status launch_unpack_t(gf_ctx* c, double* dst) {
 gf_status read_head(gf_ctx* c) {
     GF_TRY_HIP(c, hipMemcpyAsync(c->h_head, c->ctl, kHeadBytes, hipMemcpyDeviceToHost, c->st));
     GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    if (c->npend) tdrain(c);
     return GF_OK;
 }
 
@@ -583,11 +637,36 @@ gf_status gf_stage_update(gf_ctx* c, const void* d_scaled) {
     return check_hip(c, hipStreamSynchronize(c->st), "sync");
 }
 
+gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
+    if (!c) return GF_EINVAL;
+    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    tdrain(c);
+    c->timing = enable != 0;
+    for (int i = 0; i < GF_NKERNELS; ++i) {
+        c->kt_ms[i] = 0.0;
+        c->kt_n[i] = 0;
+    }
+    return GF_OK;
+}
+
+gf_status gf_kernel_times(gf_ctx* c, int32_t n, double* h_ms_total, int64_t* h_counts) {
+    if (!c) return GF_EINVAL;
+    if (!h_ms_total || !h_counts || n < 0 || n > GF_NKERNELS) return fail(c, GF_EINVAL, "bad arguments");
+    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    tdrain(c);
+    for (int i = 0; i < n; ++i) {
+        h_ms_total[i] = c->kt_ms[i];
+        h_counts[i] = c->kt_n[i];
+    }
+    return GF_OK;
+}
+
 const char* gf_last_error(const gf_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
 void gf_destroy(gf_ctx* c) {
     if (!c) return;
     if (c->h_head) (void)hipHostFree(c->h_head);
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
     delete c;
 }
 

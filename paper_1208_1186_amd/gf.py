@@ -60,6 +60,8 @@ def _signatures(lib):
         "gf_stage_divergence": (i32, [_P, _P]),
         "gf_stage_filter": (i32, [_P, _P, _P]),
         "gf_stage_update": (i32, [_P, _P]),
+        "gf_set_timing": (i32, [_P, i32]),
+        "gf_kernel_times": (i32, [_P, i32, pd, ctypes.POINTER(ctypes.c_int64)]),
         "gf_last_error": (ctypes.c_char_p, [_P]),
         "gf_destroy": (None, [_P]),
     }
@@ -169,6 +171,22 @@ def gf_stage_filter(ctx, d_in, d_out):
 
 def gf_stage_update(ctx, d_scaled):
     _check(ctx, load().gf_stage_update(ctx, _P(d_scaled)))
+
+
+KERNEL_NAMES = ["fft_xy_fwd", "fft_zt_filter", "fft_xy_inv", "update", "divergence", "finalize"]
+NKERNELS = 8
+
+
+def gf_set_timing(ctx, enable):
+    _check(ctx, load().gf_set_timing(ctx, 1 if enable else 0))
+
+
+def gf_kernel_times(ctx):
+    """{kernel name: (total ms, launches)} from the HIP events recorded since gf_set_timing."""
+    ms = (ctypes.c_double * NKERNELS)()
+    cnt = (ctypes.c_int64 * NKERNELS)()
+    _check(ctx, load().gf_kernel_times(ctx, NKERNELS, ms, cnt))
+    return {KERNEL_NAMES[i]: (ms[i], cnt[i]) for i in range(len(KERNEL_NAMES))}
 
 
 def gf_destroy(ctx):
