@@ -35,6 +35,7 @@ def kernel_bytes(name, vol, L, S, nblk):
     links = 4 * L * S * vol
     field = W * S * vol
     return {
+        "update_measure": 2 * links + 2 * field,  # read U, (alpha/2)Delta~; write U', Delta(U')
         "update": 2 * links + field,           # read U and (alpha/2)Delta~, write U
         "divergence": links + field,           # read U, write Delta
         "fft_xy_fwd": 2 * field,

@@ -65,7 +65,8 @@ typedef enum {
 
 enum {
     GF_FLAG_EXACT_EXP = 1u << 0,   /* reserved: g = exp((alpha/2) Delta~) instead of first order */
-    GF_FLAG_NO_FA = 1u << 1        /* plain steepest descent: K(p) = 1 instead of p2max/p^2 */
+    GF_FLAG_NO_FA = 1u << 1,       /* plain steepest descent: K(p) = 1 instead of p2max/p^2 */
+    GF_FLAG_GENERIC_FFT = 1u << 2  /* use the runtime-shaped FFT kernels even where a compile-time one exists */
 };
 
 typedef struct {
@@ -128,12 +129,16 @@ gf_status gf_history(gf_ctx* ctx, int64_t n, double* h_theta, double* h_F);
  *     matrix field); also refreshes theta and F.
  *   gf_stage_filter: d_in (canonical anti-Hermitian traceless field) ->
  *     d_out = (alpha/2) * IFFT[K(p) FFT[d_in]] (canonical matrix field).
+ *   gf_stage_gauge: d_in as for gf_stage_filter -> d_out = g(x) =
+ *     reunitarize(1 + (alpha/2) Delta~(x)) (canonical matrix field), the
+ *     gauge transform the loop applies.
  *   gf_stage_update: U_mu(x) -> g U_mu(x) g(x+mu)^dag with
  *     g = reunitarize(1 + d_scaled(x)), d_scaled a canonical field that already
  *     holds (alpha/2) Delta~.
  */
 gf_status gf_stage_divergence(gf_ctx* ctx, void* d_delta);
 gf_status gf_stage_filter(gf_ctx* ctx, const void* d_in, void* d_out);
+gf_status gf_stage_gauge(gf_ctx* ctx, const void* d_in, void* d_out);
 gf_status gf_stage_update(gf_ctx* ctx, const void* d_scaled);
 
 /*
@@ -145,10 +150,11 @@ gf_status gf_stage_update(gf_ctx* ctx, const void* d_scaled);
 enum {
     GF_K_FFT_XY_FWD = 0,  /* forward 2D FFT over (x, y) */
     GF_K_FFT_ZT = 1,      /* 2D FFT over (z, t), filter, inverse (z, t) */
-    GF_K_FFT_XY_INV = 2,  /* inverse 2D FFT over (x, y) */
-    GF_K_UPDATE = 3,      /* g(x) and U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag */
-    GF_K_DIVERGENCE = 4,  /* Delta(x) and block partial sums of F, theta */
+    GF_K_FFT_XY_INV = 2,  /* inverse 2D FFT over (x, y) (in the loop: followed by g(x)) */
+    GF_K_UPDATE = 3,      /* single-stage update U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag */
+    GF_K_DIVERGENCE = 4,  /* standalone Delta(x) and block partial sums of F, theta */
     GF_K_FINALIZE = 5,    /* fixed-order reduction -> theta, F, stop flag */
+    GF_K_UPDATE_MEASURE = 6,  /* loop kernel: update, divergence of the new links, reduction */
     GF_NKERNELS = 8
 };
 gf_status gf_set_timing(gf_ctx* ctx, int32_t enable);

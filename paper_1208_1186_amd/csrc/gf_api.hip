@@ -2,11 +2,13 @@
 //
 // The context carves the caller's workspace into: a device control block
 // (theta, F, stop flag, iteration count, history), per-block reduction
-// partials, FFT twiddle and sin^2 tables, the four packed Delta fields and
-// the structure-of-arrays links. Every kernel is queued on the caller's
-// stream; the loop reads the control block back every check_every
-// iterations, and kernels queued after the stop flag is set return at once,
-// so the iterate is exactly the one the stopping rule selects.
+// partials, FFT twiddle and sin^2 tables, the divergence buffer D, the FFT
+// buffer Q, the gauge rows G and two link buffers (the loop kernel reads one
+// and writes the other: after k updates the links are in buffer k & 1).
+// Every kernel is queued on the caller's stream; the loop reads the control
+// block back every check_every iterations, and kernels queued after the stop
+// flag is set return at once, so the iterate is exactly the one the stopping
+// rule selects.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,19 +21,23 @@
 #include <vector>
 
 #include "../../include/gf.h"
+#include "gf_fft_ct.hpp"
 #include "gf_kernels.hpp"
 
 using namespace gf;
 
 namespace {
 
-constexpr int kEPT = 8;         // FFT elements held per thread per stage
-constexpr int kMaxExtent = 64;  // largest supported extent
+constexpr int kEPT = 8;          // FFT elements held per thread per stage
+constexpr int kMaxExtent = 64;   // largest supported extent
 constexpr size_t kAlign = 256;
+constexpr size_t kLdsMax = 160 * 1024;
+constexpr int kPlanePad = 256;   // extra elements per plane: staggers plane starts across HBM channels
 
 thread_local std::string g_init_error;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+int round64(int x) { return (x + 63) / 64 * 64; }
 
 bool is_2a3b(int n) {
     if (n < 1) return false;
@@ -40,6 +46,7 @@ bool is_2a3b(int n) {
     return n == 1;
 }
 
+// Radix sequence for a length-n transform: threes first, then eights and fours, a two if left.
 FftPlan make_plan(int n) {
     FftPlan p{};
     p.n = n;
@@ -68,21 +75,23 @@ FftPlan make_plan(int n) {
 struct Layout {
     int n[4];
     int64_t vol;
-    size_t ps;          // plane stride (elements)
-    int nblk;           // site blocks
+    size_t ps;        // plane stride (elements) of every SoA array
+    int nblk;         // blocks of the one-site-per-thread kernels
+    int nblk_fused;   // blocks of the loop kernel (kFusedSites sites each)
     bool fp32;
-    int ne;             // 9 or 6
-    // pass A
+    int ne;           // 9 or 6 complex entries stored per link
+    // forward / inverse (x, y) pass over single-field planes
     int G, rs, thrA;
     size_t ldsA;
-    // pass B
+    // (z, t) pass
     int bx, tsp, thrB;
     size_t ldsB;
+    // inverse (x, y) pass of four fields + gauge rows
+    int thrC, eptC;
+    size_t ldsC;
     // workspace offsets
-    size_t off_ctl, off_part, off_sin2, off_tw, off_z, off_links, total;
+    size_t off_ctl, off_part, off_sin2, off_tw, off_d, off_q, off_g, off_links[2], total;
 };
-
-int round64(int x) { return (x + 63) / 64 * 64; }
 
 gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
     if (!p) {
@@ -104,13 +113,13 @@ gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
         L.n[i] = n;
         vol *= n;
     }
-    if (vol > (int64_t)1 << 31) {
-        err = "lattice too large";
-        return GF_ENOTSUP;
+    if (p->precision < GF_FP64_18 || p->precision > GF_MIXED) {
+        err = "unknown precision";
+        return GF_EINVAL;
     }
-    if (p->precision < GF_FP64_18 || p->precision > GF_FP32_18) {
-        err = p->precision == GF_MIXED ? "GF_MIXED is not available in this build" : "unknown precision";
-        return p->precision == GF_MIXED ? GF_ENOTSUP : GF_EINVAL;
+    if (p->precision == GF_MIXED) {
+        err = "GF_MIXED is not available in this build";
+        return GF_ENOTSUP;
     }
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) {
         err = "alpha must be positive and finite";
@@ -124,10 +133,11 @@ gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
     L.fp32 = p->precision == GF_FP32_12 || p->precision == GF_FP32_18;
     L.ne = (p->precision == GF_FP64_12 || p->precision == GF_FP32_12) ? 6 : 9;
     const size_t csz = L.fp32 ? 8 : 16;
-    L.ps = align_up((size_t)vol, 256);
+    L.ps = align_up((size_t)vol, 256) + kPlanePad;
     L.nblk = (int)((vol + kSiteThreads - 1) / kSiteThreads);
+    L.nblk_fused = (int)((vol + kFusedSites - 1) / kFusedSites);
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2], nt = L.n[3];
-    // Pass A: G planes per block, enough work per block, never straddling a field.
+    // (x, y) pass: G planes per block, enough work per block, never straddling a field.
     const int nzt = nz * nt;
     L.G = 1;
     while (L.G * 2 <= nzt && nzt % (L.G * 2) == 0 && L.G * nx * ny < 512) L.G *= 2;
@@ -135,40 +145,54 @@ gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
     const int EA = L.G * nx * ny;
     L.thrA = std::min(1024, std::max(64, round64((EA + kEPT - 1) / kEPT)));
     L.ldsA = (size_t)(nx + ny) * csz + (size_t)L.G * ny * L.rs * csz;
-    // Pass B: bx consecutive x columns, >= 64 contiguous bytes when possible.
-    const size_t ldsCap = 80 * 1024;
-    L.bx = 1;
+    // (z, t) pass: bx consecutive x columns, up to 128 contiguous bytes per row.
+    L.bx = 0;
     for (int b : {16, 8, 4, 2, 1}) {
         if (nx % b != 0) continue;
         const int E = b * nz * nt;
         const size_t lds = (size_t)(nz + nt) * csz + (size_t)nt * (nz * b + 1) * csz;
-        if (E <= kEPT * 1024 && lds <= ldsCap && (size_t)b * csz <= 128) {
+        if (E <= kEPT * 1024 && lds <= 80 * 1024 && (size_t)b * csz <= 128) {
             L.bx = b;
             break;
         }
     }
-    L.tsp = nz * L.bx + 1;
-    const int EB = L.bx * nz * nt;
-    if (EB > kEPT * 1024) {
-        err = "z-t plane too large";
+    if (L.bx == 0) {
+        err = "z-t plane too large for one block";
         return GF_ENOTSUP;
     }
+    L.tsp = nz * L.bx + 1;
+    const int EB = L.bx * nz * nt;
     L.thrB = std::min(1024, std::max(64, round64((EB + kEPT - 1) / kEPT)));
     L.ldsB = (size_t)(nz + nt) * csz + (size_t)nt * L.tsp * csz;
+    // inverse (x, y) + gauge pass: the four fields of one (z, t) plane per block.
+    const int EC = 4 * nx * ny;
+    L.eptC = EC <= kEPT * 1024 ? kEPT : 16;
+    L.ldsC = (size_t)(nx + ny) * csz + (size_t)4 * ny * L.rs * csz;
+    if (EC > L.eptC * (L.eptC == 16 ? 640 : 1024) || L.ldsC > kLdsMax) {
+        err = "x-y plane too large for one block at this precision";
+        return GF_ENOTSUP;
+    }
+    L.thrC = std::min(1024, std::max(64, round64((EC + L.eptC - 1) / L.eptC)));
     // Workspace.
     size_t o = 0;
     L.off_ctl = o;
     o = align_up(o + sizeof(Ctl), kAlign);
     L.off_part = o;
-    o = align_up(o + (size_t)L.nblk * sizeof(double2), kAlign);
+    o = align_up(o + (size_t)std::max(L.nblk, L.nblk_fused) * sizeof(double2), kAlign);
     L.off_sin2 = o;
     o = align_up(o + 4 * kMaxExtent * sizeof(double), kAlign);
     L.off_tw = o;
     o = align_up(o + 4 * kMaxExtent * 16, kAlign);
-    L.off_z = o;
+    L.off_d = o;
     o = align_up(o + 4 * L.ps * csz, kAlign);
-    L.off_links = o;
-    o = align_up(o + (size_t)4 * L.ne * L.ps * csz, kAlign);
+    L.off_q = o;
+    o = align_up(o + 4 * L.ps * csz, kAlign);
+    L.off_g = o;
+    o = align_up(o + 6 * L.ps * csz, kAlign);
+    for (int i = 0; i < 2; ++i) {
+        L.off_links[i] = o;
+        o = align_up(o + (size_t)4 * L.ne * L.ps * csz, kAlign);
+    }
     L.total = o;
     return GF_OK;
 }
@@ -186,14 +210,17 @@ struct gf_ctx {
     double2* part;
     void* sin2;
     void* tw[4];
-    void* Z;
-    void* links;
+    void* D;      // divergence of the current links (four packed fields)
+    void* Q;      // FFT work buffer (four packed fields)
+    void* Gb;     // gauge rows (six planes)
+    void* Lb[2];  // links after k updates live in Lb[k & 1]
+    long long k_host;  // updates applied, as of the last read of the control block
     FftPlan plan[4];
     Ctl* h_head;  // pinned host copy of the control block's leading scalars
     std::string err;
     // Optional per-kernel HIP-event timing (gf_set_timing / gf_kernel_times).
     bool timing = false;
-    std::vector<hipEvent_t> ev;   // 2 per pending measurement
+    std::vector<hipEvent_t> ev;  // 2 per pending measurement
     std::vector<int> ev_kid;
     int npend = 0;
     double kt_ms[GF_NKERNELS] = {};
@@ -214,12 +241,13 @@ gf_status check_hip(gf_ctx* c, hipError_t e, const char* what) {
     return fail(c, GF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define GF_TRY_HIP(c, call)                                       \
-    do {                                                          \
-        gf_status _s = check_hip((c), (call), #call);             \
-        if (_s != GF_OK) return _s;                               \
+#define GF_TRY_HIP(c, call)                               \
+    do {                                                  \
+        gf_status _s = check_hip((c), (call), #call);     \
+        if (_s != GF_OK) return _s;                       \
     } while (0)
 
+// ---------------------------------------------------------------- timing
 constexpr int kEventPairs = 4096;
 
 void tdrain(gf_ctx* c) {
@@ -254,156 +282,355 @@ void tstop(gf_ctx* c) {
     ++c->npend;
 }
 
+// ---------------------------------------------------------------- launches
+int cur(const gf_ctx* c) { return (int)(c->k_host & 1); }
+double inv3v(const gf_ctx* c) { return 1.0 / (3.0 * (double)c->L.vol); }
+double inv12v(const gf_ctx* c) { return 1.0 / (12.0 * (double)c->L.vol); }
+
 template <typename T, int NE>
-Links<T, NE> links_of(gf_ctx* c) {
-    return Links<T, NE>{reinterpret_cast<cx<T>*>(c->links), c->L.ps};
+Links<T, NE> links_of(gf_ctx* c, int i) {
+    return Links<T, NE>{reinterpret_cast<cx<T>*>(c->Lb[i & 1]), c->L.ps};
+}
+template <typename T>
+cx<T>* cxp(void* p) {
+    return reinterpret_cast<cx<T>*>(p);
+}
+template <typename T>
+const cx<T>* twp(gf_ctx* c, int d) {
+    return reinterpret_cast<const cx<T>*>(c->tw[d]);
+}
+
+// Shapes with compile-time FFT kernels: (Nx, Ny, G) for the (x, y) passes,
+// (Nz, Nt, bx) for the (z, t) pass at each precision, (Nx, Ny) for the gauge pass.
+#define GF_XY_CASES(X) X(8, 8, 8) X(12, 12, 4) X(16, 16, 2) X(24, 24, 1) X(32, 32, 1) X(48, 48, 1)
+#define GF_ZT_CASES_F64(X) \
+    X(8, 8, 8) X(12, 12, 4) X(16, 16, 8) X(24, 8, 8) X(32, 4, 8) X(48, 8, 8) X(32, 32, 4) X(32, 64, 2)
+#define GF_ZT_CASES_F32(X) \
+    X(8, 8, 8) X(12, 12, 4) X(16, 16, 16) X(24, 8, 8) X(32, 4, 16) X(48, 8, 16) X(32, 32, 8) X(32, 64, 4)
+#define GF_GAUGE_CASES(X) X(8, 8) X(12, 12) X(16, 16) X(24, 24) X(32, 32) X(48, 48)
+
+bool generic_fft(const gf_ctx* c) { return (c->p.flags & GF_FLAG_GENERIC_FFT) != 0; }
+
+template <typename T, bool INV>
+bool launch_xy_ct(gf_ctx* c, const void* src, void* dst, int force, bool loop_reduce) {
+    const Layout& L = c->L;
+    const int nzt = L.n[2] * L.n[3];
+    const cx<T>* s = reinterpret_cast<const cx<T>*>(src);
+    const double2* part = loop_reduce ? c->part : nullptr;
+#define GF_X(A, B, GG)                                                                                          \
+    if (L.n[0] == A && L.n[1] == B && L.G == GG) {                                                              \
+        hipLaunchKernelGGL((k_fft_xy_ct<T, A, B, GG, INV>), dim3(4 * nzt / GG), dim3(ct_threads(GG * A * B, 8)), \
+                           0, c->st, s, cxp<T>(dst), L.ps, nzt, twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, part,  \
+                           L.nblk_fused, inv3v(c), inv12v(c));                                                  \
+        return true;                                                                                            \
+    }
+    GF_XY_CASES(GF_X)
+#undef GF_X
+    return false;
 }
 
 template <typename T>
-gf_status launch_fft(gf_ctx* c, int force) {
+bool launch_zt_ct(gf_ctx* c, void* Z, T coef, int no_fa, int force) {
     const Layout& L = c->L;
-    cx<T>* Z = reinterpret_cast<cx<T>*>(c->Z);
-    const cx<T>* tw[4];
-    for (int i = 0; i < 4; ++i) tw[i] = reinterpret_cast<const cx<T>*>(c->tw[i]);
-    const int nzt = L.n[2] * L.n[3];
-    const int gridA = 4 * nzt / L.G;
-    const int gridB = 4 * L.n[1] * (L.n[0] / L.bx);
-    const double coef = 0.5 * c->p.alpha * ((c->p.flags & GF_FLAG_NO_FA) ? 1.0 : 16.0) / (double)L.vol;
-    const int no_fa = (c->p.flags & GF_FLAG_NO_FA) ? 1 : 0;
-    tstart(c, GF_K_FFT_XY_FWD);
-    hipLaunchKernelGGL((k_fft_xy<T, kEPT, false>), dim3(gridA), dim3(L.thrA), L.ldsA, c->st, Z, L.ps, L.n[0], L.n[1],
-                       nzt, L.G, L.rs, c->plan[0], c->plan[1], tw[0], tw[1], c->ctl, force);
-    tstop(c);
-    tstart(c, GF_K_FFT_ZT);
-    hipLaunchKernelGGL((k_fft_zt<T, kEPT>), dim3(gridB), dim3(L.thrB), L.ldsB, c->st, Z, L.ps, L.n[0], L.n[1],
-                       L.n[2], L.n[3], L.bx, L.tsp, c->plan[2], c->plan[3], tw[2], tw[3],
-                       reinterpret_cast<const T*>(c->sin2), (T)coef, no_fa, c->ctl, force);
-    tstop(c);
-    tstart(c, GF_K_FFT_XY_INV);
-    hipLaunchKernelGGL((k_fft_xy<T, kEPT, true>), dim3(gridA), dim3(L.thrA), L.ldsA, c->st, Z, L.ps, L.n[0], L.n[1],
-                       nzt, L.G, L.rs, c->plan[0], c->plan[1], tw[0], tw[1], c->ctl, force);
-    tstop(c);
-    return check_hip(c, hipGetLastError(), "fft launch");
+    const T* s2 = reinterpret_cast<const T*>(c->sin2);
+#define GF_X(A, B, BB)                                                                                     \
+    if (L.n[2] == A && L.n[3] == B && L.bx == BB) {                                                        \
+        hipLaunchKernelGGL((k_fft_zt_ct<T, A, B, BB>), dim3(4 * L.n[1] * (L.n[0] / BB)),                   \
+                           dim3(ct_threads(BB * A * B, 8)), 0, c->st, cxp<T>(Z), L.ps, L.n[0], L.n[1],     \
+                           twp<T>(c, 2), twp<T>(c, 3), s2, coef, no_fa, c->ctl, force);                    \
+        return true;                                                                                       \
+    }
+    if constexpr (sizeof(T) == 8) {
+        GF_ZT_CASES_F64(GF_X)
+    } else {
+        GF_ZT_CASES_F32(GF_X)
+    }
+#undef GF_X
+    return false;
 }
 
+template <typename T>
+bool launch_gauge_ct(gf_ctx* c, int force) {
+    const Layout& L = c->L;
+#define GF_X(A, B)                                                                                             \
+    if (L.n[0] == A && L.n[1] == B) {                                                                          \
+        hipLaunchKernelGGL((k_fft_xy_gauge_ct<T, A, B>), dim3(L.n[2] * L.n[3]),                                \
+                           dim3(ct_threads(4 * A * B, gauge_ept(A, B))), gauge_ct_lds(A, B, sizeof(cx<T>)),    \
+                           c->st, reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps,             \
+                           twp<T>(c, 0), twp<T>(c, 1), c->ctl, force);                                         \
+        return true;                                                                                           \
+    }
+    GF_GAUGE_CASES(GF_X)
+#undef GF_X
+    return false;
+}
+
+template <typename T>
+void raise_lds_ct() {
+#define GF_X(A, B)                                                                                     \
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy_gauge_ct<T, A, B>),            \
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+    GF_GAUGE_CASES(GF_X)
+#undef GF_X
+}
+
+// (x, y) pass src -> dst. With loop_reduce, block 0 also reduces pending loop partials.
+template <typename T, bool INV>
+void launch_xy(gf_ctx* c, const void* src, void* dst, int force, bool loop_reduce) {
+    const Layout& L = c->L;
+    const int nzt = L.n[2] * L.n[3];
+    tstart(c, INV ? GF_K_FFT_XY_INV : GF_K_FFT_XY_FWD);
+    if (!generic_fft(c) && launch_xy_ct<T, INV>(c, src, dst, force, loop_reduce)) {
+        tstop(c);
+        return;
+    }
+    hipLaunchKernelGGL((k_fft_xy<T, kEPT, INV>), dim3(4 * nzt / L.G), dim3(L.thrA), L.ldsA, c->st,
+                       reinterpret_cast<const cx<T>*>(src), cxp<T>(dst), L.ps, L.n[0], L.n[1], nzt, L.G, L.rs,
+                       c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force,
+                       loop_reduce ? c->part : nullptr, L.nblk_fused, inv3v(c), inv12v(c));
+    tstop(c);
+}
+
+template <typename T>
+void launch_zt(gf_ctx* c, void* Z, int force) {
+    const Layout& L = c->L;
+    const bool no_fa = (c->p.flags & GF_FLAG_NO_FA) != 0;
+    const double coef = 0.5 * c->p.alpha * (no_fa ? 1.0 : 16.0) / (double)L.vol;
+    tstart(c, GF_K_FFT_ZT);
+    if (!generic_fft(c) && launch_zt_ct<T>(c, Z, (T)coef, no_fa ? 1 : 0, force)) {
+        tstop(c);
+        return;
+    }
+    hipLaunchKernelGGL((k_fft_zt<T, kEPT>), dim3(4 * L.n[1] * (L.n[0] / L.bx)), dim3(L.thrB), L.ldsB, c->st,
+                       cxp<T>(Z), L.ps, L.n[0], L.n[1], L.n[2], L.n[3], L.bx, L.tsp, c->plan[2], c->plan[3],
+                       twp<T>(c, 2), twp<T>(c, 3), reinterpret_cast<const T*>(c->sin2), (T)coef, no_fa ? 1 : 0,
+                       c->ctl, force);
+    tstop(c);
+}
+
+template <typename T>
+void launch_gauge_pass(gf_ctx* c, int force) {
+    const Layout& L = c->L;
+    tstart(c, GF_K_FFT_XY_INV);
+    if (!generic_fft(c) && launch_gauge_ct<T>(c, force)) {
+        tstop(c);
+        return;
+    }
+    if (L.eptC == kEPT)
+        hipLaunchKernelGGL((k_fft_xy_gauge<T, kEPT>), dim3(L.n[2] * L.n[3]), dim3(L.thrC), L.ldsC, c->st,
+                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
+                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force);
+    else
+        hipLaunchKernelGGL((k_fft_xy_gauge<T, 16>), dim3(L.n[2] * L.n[3]), dim3(L.thrC), L.ldsC, c->st,
+                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
+                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force);
+    tstop(c);
+}
+
+// Standalone measurement of the current links: Delta -> D, theta and F.
 template <typename T, int NE>
-gf_status launch_measure_t(gf_ctx* c, int force) {
+void launch_measure_t(gf_ctx* c) {
     const Layout& L = c->L;
     tstart(c, GF_K_DIVERGENCE);
-    hipLaunchKernelGGL((k_divergence<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c),
-                       reinterpret_cast<cx<T>*>(c->Z), L.ps, c->geom, c->part, c->ctl, force);
+    hipLaunchKernelGGL((k_divergence<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c, cur(c)),
+                       cxp<T>(c->D), L.ps, c->geom, c->part);
     tstop(c);
     tstart(c, GF_K_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, L.nblk, 1.0 / (3.0 * (double)L.vol),
-                       1.0 / (12.0 * (double)L.vol), c->ctl, force);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, L.nblk, inv3v(c), inv12v(c), c->ctl, 0);
     tstop(c);
-    return check_hip(c, hipGetLastError(), "divergence launch");
 }
 
+// In-place update of the current links from (alpha/2) Delta~ packed in Q.
 template <typename T, int NE>
-gf_status launch_update_t(gf_ctx* c, int count) {
+void launch_update_t(gf_ctx* c) {
     const Layout& L = c->L;
     tstart(c, GF_K_UPDATE);
-    hipLaunchKernelGGL((k_update<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c),
-                       reinterpret_cast<const cx<T>*>(c->Z), L.ps, c->geom, c->ctl, count);
+    hipLaunchKernelGGL((k_update<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c, cur(c)),
+                       reinterpret_cast<const cx<T>*>(c->Q), L.ps, c->geom);
     tstop(c);
-    return check_hip(c, hipGetLastError(), "update launch");
 }
 
-#define GF_DISPATCH(c, fn, ...)                                                   \
-    ((c)->L.fp32 ? ((c)->L.ne == 6 ? fn<float, 6>(__VA_ARGS__) : fn<float, 9>(__VA_ARGS__)) \
-                 : ((c)->L.ne == 6 ? fn<double, 6>(__VA_ARGS__) : fn<double, 9>(__VA_ARGS__)))
-
-gf_status launch_measure(gf_ctx* c, int force) { return GF_DISPATCH(c, launch_measure_t, c, force); }
-gf_status launch_update(gf_ctx* c, int count) { return GF_DISPATCH(c, launch_update_t, c, count); }
-gf_status launch_fft_any(gf_ctx* c, int force) {
-    return c->L.fp32 ? launch_fft<float>(c, force) : launch_fft<double>(c, force);
+// Loop kernel from k to k + 1 updates: links Lb[k] -> Lb[k+1], divergence -> D.
+template <typename T, int NE>
+void launch_fused_t(gf_ctx* c, long long k) {
+    const Layout& L = c->L;
+    const int a = (int)(k & 1);
+    tstart(c, GF_K_UPDATE_MEASURE);
+    hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused), dim3(kFusedThreads), 0, c->st,
+                       links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
+                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl);
+    tstop(c);
 }
 
 template <typename T, int NE>
-gf_status launch_pack_t(gf_ctx* c, const double* src) {
-    const int reunit = sizeof(T) == 4 ? 1 : 0;
-    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, src, links_of<T, NE>(c),
-                       c->L.vol, reunit);
-    return check_hip(c, hipGetLastError(), "pack launch");
+void launch_pack_t(gf_ctx* c, const double* src) {
+    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, src,
+                       links_of<T, NE>(c, cur(c)), c->L.vol, sizeof(T) == 4 ? 1 : 0);
 }
 template <typename T, int NE>
-gf_status launch_unpack_t(gf_ctx* c, double* dst) {
-    hipLaunchKernelGGL((k_unpack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c), dst,
-                       c->L.vol);
-    return check_hip(c, hipGetLastError(), "unpack launch");
+void launch_unpack_t(gf_ctx* c, double* dst) {
+    hipLaunchKernelGGL((k_unpack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c, cur(c)),
+                       dst, c->L.vol);
+}
+
+#define GF_DISPATCH(c, fn, ...)                                                                  \
+    do {                                                                                         \
+        if ((c)->L.fp32) {                                                                       \
+            if ((c)->L.ne == 6) fn<float, 6>(__VA_ARGS__); else fn<float, 9>(__VA_ARGS__);       \
+        } else {                                                                                 \
+            if ((c)->L.ne == 6) fn<double, 6>(__VA_ARGS__); else fn<double, 9>(__VA_ARGS__);     \
+        }                                                                                        \
+    } while (0)
+
+gf_status launched(gf_ctx* c, const char* what) { return check_hip(c, hipGetLastError(), what); }
+
+gf_status launch_measure(gf_ctx* c) {
+    GF_DISPATCH(c, launch_measure_t, c);
+    return launched(c, "divergence launch");
+}
+
+// Queue the update from k to k + 1 (no-ops on the device once the stop flag is set).
+gf_status one_iteration(gf_ctx* c, long long k) {
+    if (c->L.fp32) {
+        launch_xy<float, false>(c, c->D, c->Q, 0, true);
+        launch_zt<float>(c, c->Q, 0);
+        launch_gauge_pass<float>(c, 0);
+    } else {
+        launch_xy<double, false>(c, c->D, c->Q, 0, true);
+        launch_zt<double>(c, c->Q, 0);
+        launch_gauge_pass<double>(c, 0);
+    }
+    GF_DISPATCH(c, launch_fused_t, c, k);
+    return launched(c, "loop launch");
+}
+
+gf_status loop_finalize(gf_ctx* c) {
+    tstart(c, GF_K_FINALIZE);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, c->L.nblk_fused, inv3v(c), inv12v(c),
+                       c->ctl, 1);
+    tstop(c);
+    return launched(c, "finalize launch");
 }
 
 gf_status read_head(gf_ctx* c) {
     GF_TRY_HIP(c, hipMemcpyAsync(c->h_head, c->ctl, kHeadBytes, hipMemcpyDeviceToHost, c->st));
     GF_TRY_HIP(c, hipStreamSynchronize(c->st));
     if (c->npend) tdrain(c);
+    c->k_host = c->h_head->iters;
     return GF_OK;
 }
 
 gf_status set_tol(gf_ctx* c, double tol) {
     hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(64), 0, c->st, c->ctl, tol);
-    return check_hip(c, hipGetLastError(), "set_tol launch");
+    return launched(c, "set_tol launch");
 }
 
-gf_status one_iteration(gf_ctx* c) {
-    gf_status s = launch_fft_any(c, 0);
-    if (s == GF_OK) s = launch_update(c, 1);
-    if (s == GF_OK) s = launch_measure(c, 0);
-    return s;
+gf_status unpack_links(gf_ctx* c, double* dst) {
+    GF_DISPATCH(c, launch_unpack_t, c, dst);
+    return launched(c, "unpack launch");
 }
 
-// FFT kernels may take more than 64 KB of dynamic LDS (gfx950 has 160 KB per CU).
+// FFT kernels take more than 64 KB of dynamic LDS on large planes (gfx950 has 160 KB per CU).
 void raise_lds_limits() {
     static bool done = false;
     if (done) return;
-    const int cap = 160 * 1024;
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy<double, kEPT, false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy<double, kEPT, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_zt<double, kEPT>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy<float, kEPT, false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_xy<float, kEPT, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_zt<float, kEPT>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    const int cap = (int)kLdsMax;
+    const void* fns[] = {
+        reinterpret_cast<const void*>(&k_fft_xy<double, kEPT, false>),
+        reinterpret_cast<const void*>(&k_fft_xy<double, kEPT, true>),
+        reinterpret_cast<const void*>(&k_fft_zt<double, kEPT>),
+        reinterpret_cast<const void*>(&k_fft_xy_gauge<double, kEPT>),
+        reinterpret_cast<const void*>(&k_fft_xy_gauge<double, 16>),
+        reinterpret_cast<const void*>(&k_fft_xy<float, kEPT, false>),
+        reinterpret_cast<const void*>(&k_fft_xy<float, kEPT, true>),
+        reinterpret_cast<const void*>(&k_fft_zt<float, kEPT>),
+        reinterpret_cast<const void*>(&k_fft_xy_gauge<float, kEPT>),
+        reinterpret_cast<const void*>(&k_fft_xy_gauge<float, 16>),
+    };
+    for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    raise_lds_ct<double>();
+    raise_lds_ct<float>();
     (void)hipGetLastError();
     done = true;
 }
 
+// sin^2 table [Nx | Ny | Nz | Nt] of 4 sin^2(pi n / N), then twiddles W_N^k per axis.
 template <typename T>
 void fill_tables(gf_ctx* c, std::vector<unsigned char>& host) {
-    // sin^2 table: [Nx | Ny | Nz | Nt] values of 4 sin^2(pi n / N); twiddles W_N^k per axis.
     const Layout& L = c->L;
-    host.assign(L.off_z - L.off_sin2, 0);
+    const long double pi = 3.14159265358979323846264338327950288L;
+    host.assign(L.off_d - L.off_sin2, 0);
     T* s2 = reinterpret_cast<T*>(host.data());
     int k = 0;
     for (int d = 0; d < 4; ++d)
         for (int n = 0; n < L.n[d]; ++n) {
-            const long double sv = sinl(3.14159265358979323846264338327950288L * (long double)n / (long double)L.n[d]);
+            const long double sv = sinl(pi * (long double)n / (long double)L.n[d]);
             s2[k++] = (T)(4.0L * sv * sv);
         }
     for (int d = 0; d < 4; ++d) {
         cx<T>* tw = reinterpret_cast<cx<T>*>(host.data() + (L.off_tw - L.off_sin2) + (size_t)d * kMaxExtent * 16);
         for (int n = 0; n < L.n[d]; ++n) {
-            const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)n / (long double)L.n[d];
+            const long double a = -2.0L * pi * (long double)n / (long double)L.n[d];
             tw[n] = {(T)cosl(a), (T)sinl(a)};
         }
     }
 }
 
 template <typename T>
-void field_pack(gf_ctx* c, const void* src, double scale) {
+void field_pack(gf_ctx* c, const void* src, void* dst) {
     hipLaunchKernelGGL(k_field_pack<T>, dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
-                       reinterpret_cast<const double*>(src), reinterpret_cast<cx<T>*>(c->Z), c->L.ps, c->L.vol, scale);
+                       reinterpret_cast<const double*>(src), cxp<T>(dst), c->L.ps, c->L.vol, 1.0);
 }
 template <typename T>
-void field_unpack(gf_ctx* c, void* dst) {
+void field_unpack(gf_ctx* c, const void* src, void* dst) {
     hipLaunchKernelGGL(k_field_unpack<T>, dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
-                       reinterpret_cast<const cx<T>*>(c->Z), c->L.ps, reinterpret_cast<double*>(dst), c->L.vol);
+                       reinterpret_cast<const cx<T>*>(src), c->L.ps, reinterpret_cast<double*>(dst), c->L.vol);
+}
+template <typename T>
+void gauge_unpack(gf_ctx* c, void* dst) {
+    hipLaunchKernelGGL(k_gauge_unpack<T>, dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
+                       reinterpret_cast<const cx<T>*>(c->Gb), c->L.ps, reinterpret_cast<double*>(dst), c->L.vol);
+}
+
+// Forward FFT of Q, filter, and either the plain inverse (x, y) pass (gauge = false) or the gauge pass.
+template <typename T>
+void stage_spectral(gf_ctx* c, bool gauge) {
+    launch_xy<T, false>(c, c->Q, c->Q, 1, false);
+    launch_zt<T>(c, c->Q, 1);
+    if (gauge)
+        launch_gauge_pass<T>(c, 1);
+    else
+        launch_xy<T, true>(c, c->Q, c->Q, 1, false);
+}
+
+gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    gf_status s = set_tol(c, tol);
+    if (s == GF_OK) s = read_head(c);
+    if (s != GF_OK) return s;
+    const long long start = c->h_head->iters;
+    while (!c->h_head->done && c->h_head->iters - start < max_iter) {
+        const int64_t left = max_iter - (c->h_head->iters - start);
+        const int64_t k = std::min<int64_t>(left, c->p.check_every);
+        for (int64_t i = 0; i < k && s == GF_OK; ++i) s = one_iteration(c, c->k_host + i);
+        if (s == GF_OK) s = loop_finalize(c);
+        if (s == GF_OK) s = read_head(c);
+        if (s != GF_OK) return s;
+    }
+    s = unpack_links(c, c->links_user);
+    if (s == GF_OK) s = check_hip(c, hipStreamSynchronize(c->st), "sync");
+    if (s != GF_OK) return s;
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (r) {
+        r->iters = c->h_head->iters;
+        r->theta = c->h_head->theta;
+        r->F = c->h_head->F;
+        r->phase = 1;
+        r->fallbacks = 0;
+        r->seconds = secs;
+    }
+    if (c->h_head->numeric) return fail(c, GF_ENUMERIC, "theta is not finite");
+    return GF_OK;
 }
 
 }  // namespace
@@ -458,8 +685,11 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
         c->part = reinterpret_cast<double2*>(c->ws + L.off_part);
         c->sin2 = c->ws + L.off_sin2;
         for (int d = 0; d < 4; ++d) c->tw[d] = c->ws + L.off_tw + (size_t)d * kMaxExtent * 16;
-        c->Z = c->ws + L.off_z;
-        c->links = c->ws + L.off_links;
+        c->D = c->ws + L.off_d;
+        c->Q = c->ws + L.off_q;
+        c->Gb = c->ws + L.off_g;
+        for (int i = 0; i < 2; ++i) c->Lb[i] = c->ws + L.off_links[i];
+        c->k_host = 0;
         for (int d = 0; d < 4; ++d) {
             c->geom.n[d] = L.n[d];
             c->plan[d] = make_plan(L.n[d]);
@@ -473,7 +703,6 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
             return GF_EDEVICE;
         }
         raise_lds_limits();
-        // Tables.
         std::vector<unsigned char> host;
         if (L.fp32)
             fill_tables<float>(c, host);
@@ -481,58 +710,30 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
             fill_tables<double>(c, host);
         Ctl head{};
         head.tol = -1.0;
-        auto done_fail = [&](gf_status st) {
+        auto init_fail = [&](gf_status st) {
             g_init_error = c->err;
+            (void)hipStreamSynchronize(c->st);
             (void)hipHostFree(c->h_head);
             delete c;
             return st;
         };
         if ((s = check_hip(c, hipMemcpyAsync(c->sin2, host.data(), host.size(), hipMemcpyHostToDevice, c->st),
                            "table upload")) != GF_OK)
-            return done_fail(s);
+            return init_fail(s);
         if ((s = check_hip(c, hipMemcpyAsync(c->ctl, &head, kHeadBytes, hipMemcpyHostToDevice, c->st),
                            "control upload")) != GF_OK)
-            return done_fail(s);
-        const double* src = c->links_user;
-        s = GF_DISPATCH(c, launch_pack_t, c, src);
-        if (s == GF_OK) s = launch_measure(c, 1);
+            return init_fail(s);
+        GF_DISPATCH(c, launch_pack_t, c, c->links_user);
+        s = launched(c, "pack launch");
+        if (s == GF_OK) s = launch_measure(c);
         if (s == GF_OK) s = read_head(c);
-        if (s != GF_OK) return done_fail(s);
+        if (s != GF_OK) return init_fail(s);
         *out = c;
         return GF_OK;
     } catch (...) {
         g_init_error = "unexpected host exception";
         return GF_EINVAL;
     }
-}
-
-static gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
-    const auto t0 = std::chrono::steady_clock::now();
-    gf_status s = set_tol(c, tol);
-    if (s == GF_OK) s = read_head(c);
-    if (s != GF_OK) return s;
-    const long long start = c->h_head->iters;
-    while (!c->h_head->done && c->h_head->iters - start < max_iter) {
-        const int64_t left = max_iter - (c->h_head->iters - start);
-        const int64_t k = std::min<int64_t>(left, c->p.check_every);
-        for (int64_t i = 0; i < k && s == GF_OK; ++i) s = one_iteration(c);
-        if (s == GF_OK) s = read_head(c);
-        if (s != GF_OK) return s;
-    }
-    s = GF_DISPATCH(c, launch_unpack_t, c, c->links_user);
-    if (s == GF_OK) s = check_hip(c, hipStreamSynchronize(c->st), "sync");
-    if (s != GF_OK) return s;
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    if (r) {
-        r->iters = c->h_head->iters;
-        r->theta = c->h_head->theta;
-        r->F = c->h_head->F;
-        r->phase = 1;
-        r->fallbacks = 0;
-        r->seconds = secs;
-    }
-    if (c->h_head->numeric) return fail(c, GF_ENUMERIC, "theta is not finite");
-    return GF_OK;
 }
 
 gf_status gf_iterate(gf_ctx* c, int64_t n, gf_result* r) {
@@ -560,7 +761,8 @@ gf_status gf_fix_until(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
 }
 
 gf_status gf_quality(gf_ctx* c, double* theta, double* F) {
-    if (!c || !theta || !F) return c ? fail(c, GF_EINVAL, "null output") : GF_EINVAL;
+    if (!c) return GF_EINVAL;
+    if (!theta || !F) return fail(c, GF_EINVAL, "null output");
     gf_status s = read_head(c);
     if (s != GF_OK) return s;
     *theta = c->h_head->theta;
@@ -571,7 +773,7 @@ gf_status gf_quality(gf_ctx* c, double* theta, double* F) {
 gf_status gf_get_links(gf_ctx* c, void* d_out) {
     if (!c) return GF_EINVAL;
     if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
-    gf_status s = GF_DISPATCH(c, launch_unpack_t, c, reinterpret_cast<double*>(d_out));
+    gf_status s = unpack_links(c, reinterpret_cast<double*>(d_out));
     if (s != GF_OK) return s;
     return check_hip(c, hipStreamSynchronize(c->st), "sync");
 }
@@ -598,43 +800,64 @@ gf_status gf_history(gf_ctx* c, int64_t n, double* h_theta, double* h_F) {
 gf_status gf_stage_divergence(gf_ctx* c, void* d_delta) {
     if (!c) return GF_EINVAL;
     if (!d_delta) return fail(c, GF_EINVAL, "d_delta is NULL");
-    gf_status s = launch_measure(c, 1);
+    gf_status s = launch_measure(c);
     if (s != GF_OK) return s;
     if (c->L.fp32)
-        hipLaunchKernelGGL(k_field_unpack<float>, dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
-                           reinterpret_cast<const cx<float>*>(c->Z), c->L.ps, reinterpret_cast<double*>(d_delta),
-                           c->L.vol);
+        field_unpack<float>(c, c->D, d_delta);
     else
-        hipLaunchKernelGGL(k_field_unpack<double>, dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
-                           reinterpret_cast<const cx<double>*>(c->Z), c->L.ps, reinterpret_cast<double*>(d_delta),
-                           c->L.vol);
-    GF_TRY_HIP(c, hipGetLastError());
+        field_unpack<double>(c, c->D, d_delta);
+    s = launched(c, "field unpack launch");
+    if (s != GF_OK) return s;
     return read_head(c);
 }
 
 gf_status gf_stage_filter(gf_ctx* c, const void* d_in, void* d_out) {
     if (!c) return GF_EINVAL;
     if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
-    if (c->L.fp32) field_pack<float>(c, d_in, 1.0); else field_pack<double>(c, d_in, 1.0);
-    GF_TRY_HIP(c, hipGetLastError());
-    gf_status s = launch_fft_any(c, 1);
+    if (c->L.fp32) {
+        field_pack<float>(c, d_in, c->Q);
+        stage_spectral<float>(c, false);
+        field_unpack<float>(c, c->Q, d_out);
+    } else {
+        field_pack<double>(c, d_in, c->Q);
+        stage_spectral<double>(c, false);
+        field_unpack<double>(c, c->Q, d_out);
+    }
+    gf_status s = launched(c, "filter launch");
     if (s != GF_OK) return s;
-    if (c->L.fp32) field_unpack<float>(c, d_out); else field_unpack<double>(c, d_out);
-    GF_TRY_HIP(c, hipGetLastError());
+    return check_hip(c, hipStreamSynchronize(c->st), "sync");
+}
+
+gf_status gf_stage_gauge(gf_ctx* c, const void* d_in, void* d_out) {
+    if (!c) return GF_EINVAL;
+    if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
+    if (c->L.fp32) {
+        field_pack<float>(c, d_in, c->Q);
+        stage_spectral<float>(c, true);
+        gauge_unpack<float>(c, d_out);
+    } else {
+        field_pack<double>(c, d_in, c->Q);
+        stage_spectral<double>(c, true);
+        gauge_unpack<double>(c, d_out);
+    }
+    gf_status s = launched(c, "gauge launch");
+    if (s != GF_OK) return s;
     return check_hip(c, hipStreamSynchronize(c->st), "sync");
 }
 
 gf_status gf_stage_update(gf_ctx* c, const void* d_scaled) {
     if (!c) return GF_EINVAL;
     if (!d_scaled) return fail(c, GF_EINVAL, "null pointer");
-    if (c->L.fp32) field_pack<float>(c, d_scaled, 1.0); else field_pack<double>(c, d_scaled, 1.0);
-    GF_TRY_HIP(c, hipGetLastError());
-    // Run the update regardless of the stop flag, without counting it.
-    gf_status s = set_tol(c, -1.0);
-    if (s == GF_OK) s = launch_update(c, 0);
-    if (s == GF_OK) s = GF_DISPATCH(c, launch_unpack_t, c, c->links_user);
+    if (c->L.fp32)
+        field_pack<float>(c, d_scaled, c->Q);
+    else
+        field_pack<double>(c, d_scaled, c->Q);
+    GF_DISPATCH(c, launch_update_t, c);
+    gf_status s = launched(c, "update launch");
+    if (s == GF_OK) s = unpack_links(c, c->links_user);
+    if (s == GF_OK) s = launch_measure(c);  // theta, F and divergence of the updated links
     if (s != GF_OK) return s;
-    return check_hip(c, hipStreamSynchronize(c->st), "sync");
+    return read_head(c);
 }
 
 gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
@@ -665,6 +888,7 @@ const char* gf_last_error(const gf_ctx* c) { return c ? c->err.c_str() : g_init_
 
 void gf_destroy(gf_ctx* c) {
     if (!c) return;
+    (void)hipStreamSynchronize(c->st);
     if (c->h_head) (void)hipHostFree(c->h_head);
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     delete c;

@@ -261,6 +261,8 @@ struct Ctl {
     long long iters;  // updates applied
     int done;         // theta < tol reached: later kernels of the loop return at once
     int numeric;      // theta was not finite
+    int pending;      // block partials of the loop kernel not yet reduced
+    int reserved;
     double hist_theta[kHist];
     double hist_F[kHist];
 };

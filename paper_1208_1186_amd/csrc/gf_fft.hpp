@@ -140,3 +140,113 @@ __device__ __forceinline__ void fft_rows(cx<T>* buf, const cx<T>* tw, const FftP
 }
 
 }  // namespace gf
+
+// ------------------------------------------------ compile-time specialisation
+// The same Stockham stages with the transform length, radix sequence, row
+// geometry and thread count known at compile time, so that every index
+// division and modulo becomes a shift or multiply and every loop unrolls.
+namespace gf {
+
+constexpr int ct_nst(int n) {
+    int s = 0, m = n;
+    while (m % 3 == 0) {
+        ++s;
+        m /= 3;
+    }
+    int a = 0;
+    while (m % 2 == 0) {
+        ++a;
+        m /= 2;
+    }
+    while (a >= 3 && a != 4) {
+        ++s;
+        a -= 3;
+    }
+    while (a >= 2) {
+        ++s;
+        a -= 2;
+    }
+    if (a == 1) ++s;
+    return s;
+}
+
+constexpr int ct_rad(int n, int idx) {
+    int r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int s = 0, m = n;
+    while (m % 3 == 0) {
+        r[s++] = 3;
+        m /= 3;
+    }
+    int a = 0;
+    while (m % 2 == 0) {
+        ++a;
+        m /= 2;
+    }
+    while (a >= 3 && a != 4) {
+        r[s++] = 8;
+        a -= 3;
+    }
+    while (a >= 2) {
+        r[s++] = 4;
+        a -= 2;
+    }
+    if (a == 1) r[s++] = 2;
+    return r[idx];
+}
+
+// Geometry of a batch of rows: row b starts at (b % N0)*S0 + (b / N0)*S1,
+// elements ES apart.
+template <int NROWS, int ES, int N0, int S0, int S1>
+struct Rows {
+    static constexpr int nrows = NROWS, es = ES, n0 = N0, s0 = S0, s1 = S1;
+};
+
+template <int N, int R, int P, class RW, int NT, typename T, bool INV>
+__device__ __forceinline__ void fft_stage_ct(cx<T>* buf, const cx<T>* tw) {
+    constexpr int M = N / R;
+    constexpr int ITEMS = RW::nrows * M;
+    constexpr int PER = (ITEMS + NT - 1) / NT;
+    constexpr int TWSTEP = N / (P * R);
+    cx<T> v[PER][R];
+    int ob[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (ITEMS % NT == 0 || w < ITEMS) {
+            const int b = w % RW::nrows, i = w / RW::nrows;
+            const int base = (b % RW::n0) * RW::s0 + (b / RW::n0) * RW::s1;
+            const int k = i % P;
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[it][j] = buf[base + (i + j * M) * RW::es];
+            ob[it] = base + ((i - k) * R + k) * RW::es;
+#pragma unroll
+            for (int j = 1; j < R; ++j) {
+                cx<T> t = tw[j * k * TWSTEP];
+                if (INV) t.im = -t.im;
+                v[it][j] = cmul(v[it][j], t);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const int w = threadIdx.x + it * NT;
+        if (ITEMS % NT == 0 || w < ITEMS) {
+            dft_small<R, T, INV>(v[it]);
+#pragma unroll
+            for (int j = 0; j < R; ++j) buf[ob[it] + j * P * RW::es] = v[it][j];
+        }
+    }
+    __syncthreads();
+}
+
+template <int N, int S, int P, class RW, int NT, typename T, bool INV>
+__device__ __forceinline__ void fft_rows_ct(cx<T>* buf, const cx<T>* tw) {
+    if constexpr (S < ct_nst(N)) {
+        constexpr int R = ct_rad(N, S);
+        fft_stage_ct<N, R, P, RW, NT, T, INV>(buf, tw);
+        fft_rows_ct<N, S + 1, P * R, RW, NT, T, INV>(buf, tw);
+    }
+}
+
+}  // namespace gf

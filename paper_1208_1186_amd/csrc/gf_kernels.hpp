@@ -1,12 +1,16 @@
 // HIP kernels of the Fourier-accelerated steepest-descent iteration.
 //
-// One iteration (paper, Section 1 and Section 2.2):
-//   k_fft_xy<fwd>  2D FFT over (x, y) planes of the four packed Delta fields
-//   k_fft_zt       2D FFT over (z, t), multiply by (alpha/2) K(p)/V, inverse (z, t)
-//   k_fft_xy<inv>  inverse 2D FFT over (x, y)  -> (alpha/2) Delta~
-//   k_update       g = reunitarize(1 + (alpha/2) Delta~); U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag
-//   k_divergence   Delta of the new links, per-block FP64 sums of Re Tr U and Tr Delta Delta^dag
-//   k_finalize     fixed-order FP64 sum of the block partials -> theta, F, stop flag
+// One loop iteration, from k to k + 1 applied updates (paper, Section 1 for
+// the method, Section 2.2 for the per-element FFT split 2D + 2D):
+//   k_fft_xy<fwd>   Delta (buffer D) -> 2D FFT over (x, y) -> buffer Q; block 0
+//                   also reduces the theta/F partials left by the previous step
+//   k_fft_zt        in Q: 2D FFT over (z, t), times (alpha/2) K(p) / V, inverse
+//   k_fft_xy_gauge  Q -> inverse 2D FFT over (x, y) -> g = reunitarize(1 +
+//                   (alpha/2) Delta~), rows 1-2 stored in buffer G
+//   k_update_measure  U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag (links ping-pong),
+//                   Delta of the new links -> D, FP64 block partials of F, theta
+// The partials are reduced by the next iteration's k_fft_xy (or by k_finalize
+// before the host reads the control block), in a fixed order.
 //
 // Delta is traceless anti-Hermitian, so it is carried as four complex fields:
 // Z0 = Delta01, Z1 = Delta02, Z2 = Delta12, Z3 = d0 + i d1 with Delta00 = i d0,
@@ -75,10 +79,10 @@ __global__ void __launch_bounds__(kSiteThreads) k_field_pack(const double* __res
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
     if (s >= vol) return;
     const double* m = f + s * 18;
-    Z[s] = {(T)(m[2] * scale), (T)(m[3] * scale)};                 // (0,1)
-    Z[zps + s] = {(T)(m[4] * scale), (T)(m[5] * scale)};           // (0,2)
-    Z[2 * zps + s] = {(T)(m[10] * scale), (T)(m[11] * scale)};     // (1,2)
-    Z[3 * zps + s] = {(T)(m[1] * scale), (T)(m[9] * scale)};       // Im(0,0), Im(1,1)
+    Z[s] = {(T)(m[2] * scale), (T)(m[3] * scale)};              // (0,1)
+    Z[zps + s] = {(T)(m[4] * scale), (T)(m[5] * scale)};        // (0,2)
+    Z[2 * zps + s] = {(T)(m[10] * scale), (T)(m[11] * scale)};  // (1,2)
+    Z[3 * zps + s] = {(T)(m[1] * scale), (T)(m[9] * scale)};    // Im(0,0), Im(1,1)
 }
 
 // Four packed fields -> canonical anti-Hermitian traceless matrix field.
@@ -90,15 +94,125 @@ __global__ void __launch_bounds__(kSiteThreads) k_field_unpack(const cx<T>* __re
     const cx<T> z0 = Z[s], z1 = Z[zps + s], z2 = Z[2 * zps + s], z3 = Z[3 * zps + s];
     double* m = f + s * 18;
     const double d0 = z3.re, d1 = z3.im;
-    m[0] = 0.0;          m[1] = d0;
-    m[2] = z0.re;        m[3] = z0.im;
-    m[4] = z1.re;        m[5] = z1.im;
-    m[6] = -(double)z0.re; m[7] = z0.im;
-    m[8] = 0.0;          m[9] = d1;
-    m[10] = z2.re;       m[11] = z2.im;
-    m[12] = -(double)z1.re; m[13] = z1.im;
-    m[14] = -(double)z2.re; m[15] = z2.im;
-    m[16] = 0.0;         m[17] = -(d0 + d1);
+    m[0] = 0.0;
+    m[1] = d0;
+    m[2] = z0.re;
+    m[3] = z0.im;
+    m[4] = z1.re;
+    m[5] = z1.im;
+    m[6] = -(double)z0.re;
+    m[7] = z0.im;
+    m[8] = 0.0;
+    m[9] = d1;
+    m[10] = z2.re;
+    m[11] = z2.im;
+    m[12] = -(double)z1.re;
+    m[13] = z1.im;
+    m[14] = -(double)z2.re;
+    m[15] = z2.im;
+    m[16] = 0.0;
+    m[17] = -(d0 + d1);
+}
+
+// ------------------------------------------------------------ gauge field g
+// g(x) is stored as its first two rows (six complex planes, gps apart); the
+// third row follows from unitarity.
+template <typename T>
+__device__ __forceinline__ su3<T> g_rows_at(const cx<T>* __restrict__ G, size_t gps, int64_t s) {
+    su3<T> g;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) g.e[k / 3][k % 3] = G[(size_t)k * gps + s];
+    third_row(g.e[0], g.e[1], g.e[2]);
+    return g;
+}
+
+// Stored g rows -> canonical matrix field.
+template <typename T>
+__global__ void __launch_bounds__(kSiteThreads) k_gauge_unpack(const cx<T>* __restrict__ G, size_t gps,
+                                                               double* __restrict__ f, int64_t vol) {
+    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
+    if (s >= vol) return;
+    su3<double> g;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const cx<T> e = G[(size_t)k * gps + s];
+        g.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
+    }
+    third_row(g.e[0], g.e[1], g.e[2]);
+    double* m = f + s * 18;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        m[2 * k] = g.e[k / 3][k % 3].re;
+        m[2 * k + 1] = g.e[k / 3][k % 3].im;
+    }
+}
+
+// ------------------------------------------------------------ reductions
+// Fixed-order FP64 sum of n block partials (F part, theta part) by the
+// calling block, independent of its size: 256 virtual lanes each add every
+// 256th partial in increasing order, then a fixed pairwise tree. Thread 0
+// publishes theta, F, the history entry and the stop flag; with advance set
+// it first counts one more applied update.
+__device__ __forceinline__ void reduce_partials(const double2* __restrict__ part, int n, double inv3v,
+                                                double inv12v, Ctl* ctl, int advance) {
+    __shared__ double ra[256], rb[256];
+    for (int vt = threadIdx.x; vt < 256; vt += blockDim.x) {
+        double a = 0.0, b = 0.0;
+        for (int i0 = vt; i0 < n; i0 += 8 * 256) {
+            double2 p[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int i = i0 + k * 256;
+                p[k] = i < n ? part[i] : make_double2(0.0, 0.0);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                a += p[k].x;
+                b += p[k].y;
+            }
+        }
+        ra[vt] = a;
+        rb[vt] = b;
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        for (int vt = threadIdx.x; vt < h; vt += blockDim.x) {
+            ra[vt] += ra[vt + h];
+            rb[vt] += rb[vt + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double F = ra[0] * inv12v, th = rb[0] * inv3v;
+        const long long k = ctl->iters + (advance ? 1 : 0);
+        ctl->iters = k;
+        ctl->pending = 0;
+        ctl->F = F;
+        ctl->theta = th;
+        ctl->hist_theta[k % kHist] = th;
+        ctl->hist_F[k % kHist] = F;
+        if (!isfinite(th)) {
+            ctl->numeric = 1;
+            ctl->done = 1;
+        } else if (th < ctl->tol) {
+            ctl->done = 1;
+        }
+    }
+}
+
+// mode 0: reduce a standalone measurement of the current links;
+// mode 1: reduce the loop kernel's partials if they are still pending.
+__global__ void __launch_bounds__(256) k_finalize(const double2* __restrict__ part, int n, double inv3v,
+                                                  double inv12v, Ctl* ctl, int mode) {
+    if (mode == 1 && !ctl->pending) return;
+    reduce_partials(part, n, inv3v, inv12v, ctl, mode);
+}
+
+__global__ void k_set_tol(Ctl* ctl, double tol) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->tol = tol;
+        ctl->done = (ctl->numeric || ctl->theta < tol) ? 1 : 0;
+    }
 }
 
 // ------------------------------------------------------------- divergence
@@ -106,9 +220,7 @@ __global__ void __launch_bounds__(kSiteThreads) k_field_unpack(const cx<T>* __re
 // of Re Tr U_mu(x) (for F) and of Tr Delta Delta^dag (for theta).
 template <typename T, int NE>
 __global__ void __launch_bounds__(kSiteThreads) k_divergence(Links<T, NE> L, cx<T>* __restrict__ Z, size_t zps,
-                                                             Geom g, double2* __restrict__ part,
-                                                             const Ctl* __restrict__ ctl, int force) {
-    if (!force && ctl->done) return;
+                                                             Geom g, double2* __restrict__ part) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t s = (int64_t)b * kSiteThreads + threadIdx.x;
     double fsum = 0.0, tsum = 0.0;
@@ -147,63 +259,28 @@ __global__ void __launch_bounds__(kSiteThreads) k_divergence(Links<T, NE> L, cx<
     if (threadIdx.x == 0) part[b] = make_double2(fsum, tsum);
 }
 
-// Fixed-order reduction of the block partials; sets theta, F and the stop flag.
-__global__ void __launch_bounds__(256) k_finalize(const double2* __restrict__ part, int n, double inv3v,
-                                                  double inv12v, Ctl* ctl, int force) {
-    if (!force && ctl->done) return;
-    double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        a += part[i].x;
-        b += part[i].y;
-    }
-    block_sum2<256>(a, b);
-    if (threadIdx.x == 0) {
-        const double F = a * inv12v, th = b * inv3v;
-        ctl->F = F;
-        ctl->theta = th;
-        const long long k = ctl->iters;
-        ctl->hist_theta[k % kHist] = th;
-        ctl->hist_F[k % kHist] = F;
-        if (!isfinite(th)) {
-            ctl->numeric = 1;
-            ctl->done = 1;
-        } else if (th < ctl->tol) {
-            ctl->done = 1;
-        }
-    }
-}
-
-__global__ void k_set_tol(Ctl* ctl, double tol) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        ctl->tol = tol;
-        ctl->done = (ctl->numeric || ctl->theta < tol) ? 1 : 0;
-    }
-}
-
-// ------------------------------------------------------------------ update
+// ------------------------------------------------------- single update
 template <typename T>
-__device__ __forceinline__ su3<T> g_at(const cx<T>* __restrict__ Z, size_t zps, int64_t s) {
+__device__ __forceinline__ su3<T> g_at_packed(const cx<T>* __restrict__ Z, size_t zps, int64_t s) {
     return g_from_packed(Z[s], Z[zps + s], Z[2 * zps + s], Z[3 * zps + s]);
 }
 
-// U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag, g = reunitarize(1 + Z(x)), Z holding
-// (alpha/2) Delta~. Float links are re-orthonormalised on write; double
-// links are stored as computed.
+// U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag in place, g = reunitarize(1 + Z(x)) with
+// Z holding (alpha/2) Delta~ packed. Used by the single-stage entry point;
+// float links are re-orthonormalised on write, double links stored as computed.
 template <typename T, int NE>
 __global__ void __launch_bounds__(kSiteThreads) k_update(Links<T, NE> L, const cx<T>* __restrict__ Z, size_t zps,
-                                                         Geom g, Ctl* ctl, int count) {
-    if (ctl->done) return;
-    if (count && blockIdx.x == 0 && threadIdx.x == 0) ctl->iters = ctl->iters + 1;
+                                                         Geom g) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t s = (int64_t)b * kSiteThreads + threadIdx.x;
     if (s >= g.vol) return;
     int c[4];
     site_coords(g, s, c);
-    const su3<T> g0 = g_at(Z, zps, s);
+    const su3<T> g0 = g_at_packed(Z, zps, s);
     constexpr int NR = NE == 9 ? 3 : 2;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        const su3<T> g1 = g_at(Z, zps, site_fwd(g, s, c, mu));
+        const su3<T> g1 = g_at_packed(Z, zps, site_fwd(g, s, c, mu));
         const su3<T> u = L.load(mu, s);
         const su3<T> gu = mul_rows<T, NR>(g0, u);
         su3<T> un = mul_adj<T, NR>(gu, g1);
@@ -212,15 +289,159 @@ __global__ void __launch_bounds__(kSiteThreads) k_update(Links<T, NE> L, const c
     }
 }
 
+// ------------------------------------------------ loop kernel: update + divergence
+// Anti-Hermitian part of a 3x3 matrix, kept as the nine reals that Delta needs:
+// X01 - conj(X10), X02 - conj(X20), X12 - conj(X21) and Im X00, Im X11, Im X22.
+template <typename T>
+struct AhAcc {
+    cx<T> o01, o02, o12;
+    T d0, d1, d2;
+    __device__ __forceinline__ void zero() {
+        o01 = o02 = o12 = {T(0), T(0)};
+        d0 = d1 = d2 = T(0);
+    }
+    __device__ __forceinline__ void add(const su3<T>& x, T sign) {
+        o01 = o01 + cscale(x.e[0][1] - conj(x.e[1][0]), sign);
+        o02 = o02 + cscale(x.e[0][2] - conj(x.e[2][0]), sign);
+        o12 = o12 + cscale(x.e[1][2] - conj(x.e[2][1]), sign);
+        d0 += sign * x.e[0][0].im;
+        d1 += sign * x.e[1][1].im;
+        d2 += sign * x.e[2][2].im;
+    }
+};
+
+// Sum over the four lanes l, l^16, l^32, l^48 of a wave (all four receive the
+// same bits): two cross-row swaps on gfx950 (v_permlane16_swap /
+// v_permlane32_swap), each followed by an add of the swapped pair.
+__device__ __forceinline__ float xor_sum4(float v) {
+    auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+__device__ __forceinline__ double xor_sum4(double v) {
+    unsigned lo = __double2loint(v), hi = __double2hiint(v);
+    auto al = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    auto ah = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    v = __hiloint2double(ah[0], al[0]) + __hiloint2double(ah[1], al[1]);
+    lo = __double2loint(v);
+    hi = __double2hiint(v);
+    auto bl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    auto bh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double(bh[0], bl[0]) + __hiloint2double(bh[1], bl[1]);
+}
+
+// Reads links Lin and the gauge rows G and writes U' = g U g(x+mu)^dag to
+// Lout, the divergence of U' to D and one FP64 partial (F, theta) per block.
+// Four lanes per site, one direction each: a wave covers 16 consecutive sites
+// x 4 directions, so every load and store is a 16-site run in one plane. Lane
+// mu updates U_mu(x) and forms U'_mu(x - mu) = g(x - mu) U_mu(x - mu) g(x)^dag
+// from the old neighbour link (no thread reads another thread's output, so
+// the step needs every link from HBM once); the four lanes add their
+// anti-Hermitian parts across lanes. All loads are issued before any
+// arithmetic, so a wave waits for one memory round trip. Lin and Lout must differ.
+constexpr int kFusedThreads = 256;
+constexpr int kFusedSites = kFusedThreads / 4;
+
+template <typename T, int NE>
+__global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> Lin, Links<T, NE> Lout,
+                                                                  const cx<T>* __restrict__ G, cx<T>* __restrict__ D,
+                                                                  size_t ps, Geom g, double2* __restrict__ part,
+                                                                  Ctl* ctl) {
+    if (ctl->done) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int mu = lane >> 4;
+    const int64_t s = (int64_t)b * kFusedSites + (threadIdx.x >> 6) * 16 + (lane & 15);
+    const bool valid = s < g.vol;
+    double fsum = 0.0, tsum = 0.0;
+    AhAcc<T> acc;
+    acc.zero();
+    if (valid) {
+        int c[4];
+        site_coords(g, s, c);
+        const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
+        const int nm = mu == 0 ? g.n[0] : mu == 1 ? g.n[1] : mu == 2 ? g.n[2] : g.n[3];
+        const int64_t sm = mu == 0 ? g.stride[0] : mu == 1 ? g.stride[1] : mu == 2 ? g.stride[2] : g.stride[3];
+        const int64_t sf = cm == nm - 1 ? s - (int64_t)(nm - 1) * sm : s + sm;
+        const int64_t sb = cm == 0 ? s + (int64_t)(nm - 1) * sm : s - sm;
+        // every load first
+        su3<T> g0, gfw, gb, u, ub;
+        const cx<T>* lp = Lin.p + (size_t)(mu * NE) * ps;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            g0.e[k / 3][k % 3] = G[(size_t)k * ps + s];
+            gfw.e[k / 3][k % 3] = G[(size_t)k * ps + sf];
+            gb.e[k / 3][k % 3] = G[(size_t)k * ps + sb];
+        }
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            u.e[k / 3][k % 3] = lp[(size_t)k * ps + s];
+            ub.e[k / 3][k % 3] = lp[(size_t)k * ps + sb];
+        }
+        third_row(g0.e[0], g0.e[1], g0.e[2]);
+        third_row(gfw.e[0], gfw.e[1], gfw.e[2]);
+        third_row(gb.e[0], gb.e[1], gb.e[2]);
+        if constexpr (NE == 6) {
+            third_row(u.e[0], u.e[1], u.e[2]);
+            third_row(ub.e[0], ub.e[1], ub.e[2]);
+        }
+        // rows 1-2 of g0 U g(x+mu)^dag; row 3 from unitarity (float: re-orthonormalised first)
+        su3<T> un = mul_adj<T, 2>(mul_rows<T, 2>(g0, u), gfw);
+        if constexpr (sizeof(T) == 4) {
+            reunitarize(un);
+        } else {
+            third_row(un.e[0], un.e[1], un.e[2]);
+        }
+        Lout.store(mu, s, un);
+        fsum = (double)un.e[0][0].re + (double)un.e[1][1].re + (double)un.e[2][2].re;
+        acc.add(un, T(-1));
+        acc.add(mul_adj<T, 3>(mul(gb, ub), g0), T(1));  // U'_mu(x - mu)
+    }
+    acc.o01.re = xor_sum4(acc.o01.re);
+    acc.o01.im = xor_sum4(acc.o01.im);
+    acc.o02.re = xor_sum4(acc.o02.re);
+    acc.o02.im = xor_sum4(acc.o02.im);
+    acc.o12.re = xor_sum4(acc.o12.re);
+    acc.o12.im = xor_sum4(acc.o12.im);
+    acc.d0 = xor_sum4(acc.d0);
+    acc.d1 = xor_sum4(acc.d1);
+    acc.d2 = xor_sum4(acc.d2);
+    if (valid) {
+        const T tr = (acc.d0 + acc.d1 + acc.d2) / T(3);
+        const T d0 = T(2) * (acc.d0 - tr), d1 = T(2) * (acc.d1 - tr);
+        const cx<T> z0 = acc.o01, z1 = acc.o02, z2 = acc.o12;
+        const cx<T> out = mu == 0 ? z0 : mu == 1 ? z1 : mu == 2 ? z2 : cx<T>{d0, d1};
+        D[(size_t)mu * ps + s] = out;
+        if (mu == 0) {
+            const double e0 = norm2(z0), e1 = norm2(z1), e2 = norm2(z2);
+            const double dd0 = d0, dd1 = d1;
+            tsum = 2.0 * (e0 + e1 + e2) + dd0 * dd0 + dd1 * dd1 + (dd0 + dd1) * (dd0 + dd1);
+        }
+    }
+    block_sum2<kFusedThreads>(fsum, tsum);
+    if (threadIdx.x == 0) {
+        part[b] = make_double2(fsum, tsum);
+        if (b == 0) ctl->pending = 1;
+    }
+}
+
 // --------------------------------------------------------------------- FFT
-// 2D FFT over the (x, y) plane. Each block takes G consecutive planes of one
-// field (flattened plane index = field * Nz*Nt + z + Nz*t), stages them in LDS
-// with rows padded to rs elements, transforms along x then y, writes back.
+// 2D FFT over the (x, y) plane, src -> dst (may alias). Each block takes G
+// consecutive planes of one field (flattened plane index = field * Nz*Nt +
+// z + Nz*t), stages them in LDS with rows padded to rs elements, transforms
+// along x then y, and writes them out. With part set, block 0 first reduces
+// the loop kernel's pending partials (npart of them) into the control block.
 template <typename T, int EPT, bool INV>
-__global__ void __launch_bounds__(1024) k_fft_xy(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, int nzt, int G,
-                                                 int rs, FftPlan px, FftPlan py, const cx<T>* __restrict__ twgx,
-                                                 const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
-                                                 int force) {
+__global__ void __launch_bounds__(1024) k_fft_xy(const cx<T>* src, cx<T>* dst, size_t zps, int nx, int ny,
+                                                 int nzt, int G, int rs, FftPlan px, FftPlan py,
+                                                 const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
+                                                 Ctl* ctl, int force, const double2* __restrict__ part, int npart,
+                                                 double inv3v, double inv12v) {
+    if (part != nullptr && blockIdx.x == 0 && ctl->pending) {
+        reduce_partials(part, npart, inv3v, inv12v, ctl, 1);
+        __syncthreads();
+    }
     if (!force && ctl->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* twx = reinterpret_cast<cx<T>*>(smem);
@@ -229,26 +450,28 @@ __global__ void __launch_bounds__(1024) k_fft_xy(cx<T>* __restrict__ Z, size_t z
     const int nthr = blockDim.x;
     for (int i = threadIdx.x; i < nx; i += nthr) twx[i] = twgx[i];
     for (int i = threadIdx.x; i < ny; i += nthr) twy[i] = twgy[i];
-    const int q0 = blockIdx.x * G;
+    const int q0 = xcd_remap(blockIdx.x, gridDim.x) * G;
     const int f = q0 / nzt, zt0 = q0 - f * nzt;
-    cx<T>* gp = Z + (size_t)f * zps + (size_t)zt0 * nx * ny;
+    const size_t off = (size_t)f * zps + (size_t)zt0 * nx * ny;
+    const cx<T>* gs = src + off;
+    cx<T>* gd = dst + off;
     const int E = G * nx * ny;
     for (int e = threadIdx.x; e < E; e += nthr) {
         const int row = e / nx, x = e - row * nx;
-        buf[row * rs + x] = gp[e];
+        buf[row * rs + x] = gs[e];
     }
     __syncthreads();
     fft_rows<EPT, T, INV>(buf, twx, px, 1, G * ny, G * ny, rs, 0);
     fft_rows<EPT, T, INV>(buf, twy, py, rs, G * nx, nx, 1, ny * rs);
     for (int e = threadIdx.x; e < E; e += nthr) {
         const int row = e / nx, x = e - row * nx;
-        gp[e] = buf[row * rs + x];
+        gd[e] = buf[row * rs + x];
     }
 }
 
 // 2D FFT over (z, t) for bx consecutive x columns at one y of one field,
 // multiply every mode by coef / p^2(p) (coef = (alpha/2) p2max / V; zero mode
-// -> 0; coef alone when no_fa), then the inverse (z, t) transform.
+// -> 0; coef alone when no_fa), then the inverse (z, t) transform, in place.
 // LDS element (xo, z, t) sits at t*tsp + z*bx + xo.
 template <typename T, int EPT>
 __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, int nz, int nt,
@@ -265,8 +488,9 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
     for (int i = threadIdx.x; i < nz; i += nthr) twz[i] = twgz[i];
     for (int i = threadIdx.x; i < nt; i += nthr) twt[i] = twgt[i];
     const int nxb = nx / bx;
-    const int xb = blockIdx.x % nxb;
-    const int rest = blockIdx.x / nxb;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int xb = blk % nxb;
+    const int rest = blk / nxb;
     const int y = rest % ny, f = rest / ny;
     const int x0 = xb * bx;
     cx<T>* gp = Z + (size_t)f * zps + x0 + (size_t)nx * y;
@@ -299,6 +523,43 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
         const int xo = e % bx, zt = e / bx;
         const int z = zt % nz, t = zt / nz;
         gp[xo + zt * pstep] = buf[t * tsp + z * bx + xo];
+    }
+}
+
+// Inverse 2D FFT over (x, y) of all four packed fields of one (z, t) plane,
+// then g(x) = reunitarize(1 + (alpha/2) Delta~(x)) for every site of the
+// plane; rows 1-2 of g go to G (six planes, gps apart).
+template <typename T, int EPT>
+__global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const cx<T>* __restrict__ Q, size_t zps,
+                                                       cx<T>* __restrict__ G, size_t gps, int nx, int ny, int rs,
+                                                       FftPlan px, FftPlan py, const cx<T>* __restrict__ twgx,
+                                                       const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
+                                                       int force) {
+    if (!force && ctl->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T>* twx = reinterpret_cast<cx<T>*>(smem);
+    cx<T>* twy = twx + nx;
+    cx<T>* buf = twy + ny;
+    const int nthr = blockDim.x;
+    for (int i = threadIdx.x; i < nx; i += nthr) twx[i] = twgx[i];
+    for (int i = threadIdx.x; i < ny; i += nthr) twy[i] = twgy[i];
+    const int P = nx * ny;
+    const int pl = ny * rs;  // LDS elements per field plane
+    const size_t base = (size_t)xcd_remap(blockIdx.x, gridDim.x) * P;
+    for (int e = threadIdx.x; e < 4 * P; e += nthr) {
+        const int f = e / P, r = e - f * P;
+        const int row = r / nx, x = r - row * nx;
+        buf[f * pl + row * rs + x] = Q[(size_t)f * zps + base + r];
+    }
+    __syncthreads();
+    fft_rows<EPT, T, true>(buf, twx, px, 1, 4 * ny, 4 * ny, rs, 0);
+    fft_rows<EPT, T, true>(buf, twy, py, rs, 4 * nx, nx, 1, pl);
+    for (int r = threadIdx.x; r < P; r += nthr) {
+        const int row = r / nx, x = r - row * nx;
+        const int li = row * rs + x;
+        const su3<T> g = g_from_packed(buf[li], buf[pl + li], buf[2 * pl + li], buf[3 * pl + li]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) G[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
     }
 }
 

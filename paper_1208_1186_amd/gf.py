@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "GF_OK", 1: "GF_EINVAL", 2: "GF_ENOTSUP", 3: "GF_EDEVICE", 4:
 PRECISIONS = {"fp64_18": 0, "fp64_12": 1, "fp32_12": 2, "fp32_18": 3, "mixed": 4}
 FLAG_EXACT_EXP = 1 << 0
 FLAG_NO_FA = 1 << 1
+FLAG_GENERIC_FFT = 1 << 2
 
 
 class gf_params(ctypes.Structure):
@@ -59,6 +60,7 @@ def _signatures(lib):
         "gf_history": (i32, [_P, i64, pd, pd]),
         "gf_stage_divergence": (i32, [_P, _P]),
         "gf_stage_filter": (i32, [_P, _P, _P]),
+        "gf_stage_gauge": (i32, [_P, _P, _P]),
         "gf_stage_update": (i32, [_P, _P]),
         "gf_set_timing": (i32, [_P, i32]),
         "gf_kernel_times": (i32, [_P, i32, pd, ctypes.POINTER(ctypes.c_int64)]),
@@ -169,11 +171,15 @@ def gf_stage_filter(ctx, d_in, d_out):
     _check(ctx, load().gf_stage_filter(ctx, _P(d_in), _P(d_out)))
 
 
+def gf_stage_gauge(ctx, d_in, d_out):
+    _check(ctx, load().gf_stage_gauge(ctx, _P(d_in), _P(d_out)))
+
+
 def gf_stage_update(ctx, d_scaled):
     _check(ctx, load().gf_stage_update(ctx, _P(d_scaled)))
 
 
-KERNEL_NAMES = ["fft_xy_fwd", "fft_zt_filter", "fft_xy_inv", "update", "divergence", "finalize"]
+KERNEL_NAMES = ["fft_xy_fwd", "fft_zt_filter", "fft_xy_inv", "update", "divergence", "finalize", "update_measure"]
 NKERNELS = 8
 
 

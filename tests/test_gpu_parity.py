@@ -19,7 +19,7 @@ pytestmark = pytest.mark.gpu
 
 ALPHA = 0.08
 SHAPES = [(2, 2, 2, 2), (4, 4, 4, 4), (6, 4, 8, 2), (12, 6, 4, 8), (8, 8, 8, 8), (16, 8, 6, 4), (48, 4, 6, 2),
-          (4, 2, 2, 64)]
+          (4, 2, 2, 64), (48, 48, 2, 2)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -64,6 +64,22 @@ def test_filter(dims):
     gf.gf_stage_filter(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
     got = out.cpu().numpy()
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+@pytest.mark.parametrize("dims", SHAPES)
+@pytest.mark.parametrize("precision", ["fp64_18", "fp32_12"])
+def test_gauge_stage(dims, precision):
+    """The loop's inverse (x, y) pass emits g = reunitarize(1 + (alpha/2) Delta~) directly."""
+    print(f"gauge dims={dims} {precision}", flush=True)
+    u = synth.make_config(dims, 4)
+    d = landau.divergence(u)
+    want = landau.gauge_from_delta(landau.fa_filter(d), ALPHA)
+    fx, _ = fixer_for(u, precision)
+    out = torch.empty_like(to_dev(d))
+    gf.gf_stage_gauge(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    got = out.cpu().numpy()
+    tol = 1e-13 if precision.startswith("fp64") else 2e-6
+    assert np.max(np.abs(got - want)) < tol
 
 
 @pytest.mark.parametrize("dims", SHAPES)
@@ -153,3 +169,84 @@ def test_full_size_32x4_one_step():
     ug = links.cpu().numpy()
     assert np.max(np.abs(ug - u1)) < 1e-13
     assert abs(res.theta - landau.theta(u1)) <= 1e-12 * res.theta
+
+
+@pytest.mark.parametrize("dims", SHAPES + [(6, 4, 2, 2)])
+@pytest.mark.parametrize("precision", ["fp64_18", "fp64_12"])
+def test_loop_iterates_match_oracle(dims, precision):
+    """Five loop iterations (fused update + divergence + reduction) against the oracle, every shape."""
+    print(f"loop dims={dims} {precision}", flush=True)
+    u = synth.make_config(dims, 7)
+    fx, links = fixer_for(u, precision, check_every=2)
+    res = fx.iterate(5)
+    ref = u
+    want_hist = [(landau.theta(u), landau.functional(u))]
+    for _ in range(5):
+        ref, *_ = landau.fa_step(ref, ALPHA)
+        want_hist.append((landau.theta(ref), landau.functional(ref)))
+    assert res.iters == 5
+    ug = links.cpu().numpy()
+    assert np.max(np.abs(ug - ref)) < 1e-12
+    th, f = fx.history(6)
+    want = np.array(want_hist)
+    assert np.max(np.abs(th - want[:, 0]) / want[:, 0]) < 1e-10
+    assert np.max(np.abs(f - want[:, 1])) < 1e-13
+    # the loop's divergence buffer equals a fresh divergence of the stored links
+    out = torch.empty(u.shape[:4] + (3, 3), dtype=torch.complex128, device="cuda:0")
+    gf.gf_stage_divergence(fx.ctx, out.data_ptr())
+    assert np.max(np.abs(out.cpu().numpy() - landau.divergence(ref))) < 1e-12
+
+
+def test_bitwise_reproducible():
+    u = synth.make_config((16, 8, 12, 8), 8)
+    outs = []
+    for _ in range(2):
+        fx, links = fixer_for(u, check_every=5)
+        fx.iterate(12)
+        th, f = fx.history(13)
+        outs.append((links.cpu().numpy(), th, f))
+        fx.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][2], outs[1][2])
+
+
+CT_SHAPES = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 16), (24, 24, 24, 8), (32, 32, 32, 4)]
+
+
+@pytest.mark.parametrize("dims", CT_SHAPES)
+@pytest.mark.parametrize("generic", [False, True])
+@pytest.mark.parametrize("precision", ["fp64_18", "fp32_12"])
+def test_workload_shapes_filter_and_gauge(dims, generic, precision):
+    """Compile-time (default) and runtime-shaped FFT kernels on the workload lattice shapes."""
+    print(f"workload shape {dims} generic={generic} {precision}", flush=True)
+    u = synth.make_config(dims, 9)
+    d = landau.divergence(u)
+    dt = landau.fa_filter(d)
+    flags = gf.FLAG_GENERIC_FFT if generic else 0
+    fx, _ = fixer_for(u, precision, flags=flags)
+    out = torch.empty_like(to_dev(d))
+    gf.gf_stage_filter(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    want = 0.5 * ALPHA * dt
+    tol = 1e-12 if precision.startswith("fp64") else 3e-6
+    assert np.max(np.abs(out.cpu().numpy() - want)) <= tol * np.max(np.abs(want))
+    gf.gf_stage_gauge(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    g_want = landau.gauge_from_delta(dt, ALPHA)
+    assert np.max(np.abs(out.cpu().numpy() - g_want)) < (1e-13 if precision.startswith("fp64") else 2e-6)
+
+
+@pytest.mark.parametrize("dims", CT_SHAPES[:3])
+def test_workload_shapes_loop(dims):
+    print(f"workload loop {dims}", flush=True)
+    u = synth.make_config(dims, 10)
+    ref = u
+    for _ in range(3):
+        ref, *_ = landau.fa_step(ref, ALPHA)
+    outs = []
+    for flags in (0, gf.FLAG_GENERIC_FFT):
+        fx, links = fixer_for(u, "fp64_18", check_every=3, flags=flags)
+        res = fx.iterate(3)
+        ug = links.cpu().numpy()
+        assert np.max(np.abs(ug - ref)) < 1e-12
+        assert abs(res.theta - landau.theta(ref)) < 1e-10 * res.theta
+        outs.append(ug)
+    assert np.max(np.abs(outs[0] - outs[1])) < 1e-14

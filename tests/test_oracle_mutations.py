@@ -1,0 +1,121 @@
+"""The oracle's pins catch plausible mistakes: each mutation below is planted in
+the oracle (on the CPU, by monkeypatching one function) and at least one pin
+must then fail."""
+import numpy as np
+import pytest
+
+from oracle import landau, su3
+import test_oracle_landau as pins
+
+_EYE = np.eye(3, dtype=np.complex128)
+_ORIG_KERNEL = landau.fa_kernel
+_ORIG_FILTER = landau.fa_filter
+
+
+def _div_no_trace(u):
+    m = sum(landau.shift(u[..., mu, :, :], mu, -1) - u[..., mu, :, :] for mu in range(4))
+    return m - su3.dag(m)
+
+
+def _div_wrong_sign(u):
+    m = sum(u[..., mu, :, :] - landau.shift(u[..., mu, :, :], mu, -1) for mu in range(4))
+    a = m - su3.dag(m)
+    return a - (su3.trace(a) / 3.0)[..., None, None] * _EYE
+
+
+def _div_forward_neighbour(u):
+    m = sum(landau.shift(u[..., mu, :, :], mu, +1) - u[..., mu, :, :] for mu in range(4))
+    a = m - su3.dag(m)
+    return a - (su3.trace(a) / 3.0)[..., None, None] * _EYE
+
+
+def _psq_double_angle(dims):
+    nx, ny, nz, nt = dims
+    c = [4.0 * np.sin(2 * np.pi * np.arange(n) / n) ** 2 for n in (nx, ny, nz, nt)]
+    return c[3][:, None, None, None] + c[2][None, :, None, None] + c[1][None, None, :, None] + c[0][None, None, None, :]
+
+
+def _kernel_sqrt(dims):
+    p2 = landau.momentum_sq(dims)
+    k = np.zeros_like(p2)
+    k[p2 > 0] = 4.0 / np.sqrt(p2[p2 > 0])
+    return k
+
+
+def _kernel_pmax_4(dims):
+    return _ORIG_KERNEL(dims) / 4.0
+
+
+def _g_full_alpha(dt, alpha, exact_exp=False):
+    return su3.reunitarize(_EYE + alpha * dt)
+
+
+def _update_back_neighbour(u, g):
+    out = np.empty_like(u)
+    gd = su3.dag(g)
+    for mu in range(4):
+        out[..., mu, :, :] = g @ u[..., mu, :, :] @ landau.shift(gd, mu, -1)
+    return out
+
+
+def _update_transposed(u, g):
+    out = np.empty_like(u)
+    for mu in range(4):
+        out[..., mu, :, :] = g @ u[..., mu, :, :] @ landau.shift(g, mu, +1).swapaxes(-1, -2)
+    return out
+
+
+def _functional_9v(u):
+    vol = np.prod(u.shape[:4])
+    return float(np.sum(su3.trace(u).real) / (9.0 * vol))
+
+
+def _filter_unnormalised(d, kernel=None):
+    return _ORIG_FILTER(d, kernel) * np.prod(d.shape[:4])
+
+
+MUTATIONS = {
+    "divergence without trace removal": ("divergence", _div_no_trace),
+    "divergence with the wrong sign": ("divergence", _div_wrong_sign),
+    "divergence with the forward neighbour": ("divergence", _div_forward_neighbour),
+    "momentum with the double angle": ("momentum_sq", _psq_double_angle),
+    "filter 1/|p| instead of 1/p^2": ("fa_kernel", _kernel_sqrt),
+    "filter with a wrong p2max": ("fa_kernel", _kernel_pmax_4),
+    "step alpha instead of alpha/2": ("gauge_from_delta", _g_full_alpha),
+    "update with g(x-mu)^dag": ("apply_gauge", _update_back_neighbour),
+    "update with a transposed g": ("apply_gauge", _update_transposed),
+    "functional normalised by 9V": ("functional", _functional_9v),
+    "inverse FFT without 1/V": ("fa_filter", _filter_unnormalised),
+}
+
+PINS = [
+    lambda: pins.test_unit_configuration(),
+    lambda: pins.test_single_link_closed_form(1.1),
+    lambda: pins.test_laplacian_eigenvalues_pin_momentum(),
+    lambda: pins.test_filter_inverts_laplacian(),
+    lambda: pins.test_filter_matches_brute_force_dft(),
+    lambda: pins.test_free_field_contraction_fourier_accelerated(),
+    lambda: pins.test_plane_wave_contraction_plain_sd(),
+    lambda: pins.test_divergence_structure(),
+    lambda: pins.test_gauge_invariants_under_random_transform(),
+    lambda: pins.test_first_order_step_increases_F(),
+]
+
+
+def test_unmutated_oracle_passes_every_pin():
+    for pin in PINS:
+        pin()
+
+
+@pytest.mark.parametrize("label", sorted(MUTATIONS))
+def test_pins_catch_mutation(label, monkeypatch):
+    name, fn = MUTATIONS[label]
+    monkeypatch.setattr(landau, name, fn)
+    failed = 0
+    for pin in PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError):
+            failed += 1
+    assert failed >= 1, f"no pin caught: {label}"
