@@ -81,6 +81,40 @@ def time_to_theta(gf, torch, u_dev, precision, tol=1e-15):
     return dt, r
 
 
+def mixed_workload(gf, torch, synth, dev, dims=(48, 48, 48, 8)):
+    """48^3 x 8, plaquette ~0.60: float bulk to theta < 1e-8 then double to 1e-15, vs plain double."""
+    from oracle import landau, observables
+    log(f"mixed-precision workload {dims}")
+    u = synth.make_config(dims, 0, synth.EPS_P060)
+    u_dev = torch.from_numpy(u).to(dev)
+    p0 = observables.plaquette(u)
+    out = {"lattice": list(dims), "switch_theta": 1e-8}
+    for prec in ["fp64_18", "mixed"]:
+        best = None
+        for _ in range(3):
+            links = u_dev.clone()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fx = gf.GaugeFixer(links, prec, check_every=10, switch_theta=1e-8)
+            r = fx.fix_until(1e-15, 100000)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            fx.close()
+            if best is None or dt < best[0]:
+                best = (dt, r, links)
+        dt, r, links = best
+        ug = links.cpu().numpy()
+        out[prec] = {"wall_s_to_theta_1e-15": round(dt, 4), "iters": int(r.iters), "status": int(r.status),
+                     "theta": r.theta, "F": r.F,
+                     "oracle_theta_of_result": landau.theta(ug),
+                     "plaquette_abs_err": abs(observables.plaquette(ug) - p0)}
+        log(f"{prec}: {r.iters} iterations, {dt:.4f}s, theta {r.theta:.2e}")
+    out["mixed_speedup_vs_fp64"] = round(out["fp64_18"]["wall_s_to_theta_1e-15"]
+                                         / out["mixed"]["wall_s_to_theta_1e-15"], 3)
+    out["F_abs_diff_mixed_vs_fp64"] = abs(out["mixed"]["F"] - out["fp64_18"]["F"])
+    return out
+
+
 def cpu_baseline(u, budget_s=12.0):
     """The FP64 NumPy oracle's FA iterations on the same input, on the host cores."""
     from oracle import landau
@@ -109,6 +143,7 @@ def main():
     ap.add_argument("--precision", default="fp64_18")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and time-to-theta")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3x8 mixed-precision workload")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -185,6 +220,9 @@ def main():
             extras[f"{p2}_iters_to_theta_1e-15"] = int(rr.iters)
             extras[f"{p2}_final_theta"] = rr.theta
             log(f"{p2}: theta<1e-15 in {rr.iters} iterations, {tt:.3f}s (status {rr.status})")
+
+    if not args.no_extras and not args.no_mixed:
+        extras["mixed_48x48x48x8"] = mixed_workload(gf, torch, synth, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -66,7 +66,10 @@ typedef enum {
 enum {
     GF_FLAG_EXACT_EXP = 1u << 0,   /* reserved: g = exp((alpha/2) Delta~) instead of first order */
     GF_FLAG_NO_FA = 1u << 1,       /* plain steepest descent: K(p) = 1 instead of p2max/p^2 */
-    GF_FLAG_GENERIC_FFT = 1u << 2  /* use the runtime-shaped FFT kernels even where a compile-time one exists */
+    GF_FLAG_GENERIC_FFT = 1u << 2, /* use the runtime-shaped FFT kernels even where a compile-time one exists */
+    GF_FLAG_ACCUMULATE_GAUGE = 1u << 3, /* keep G(x) with U = G U_input G(x+mu)^dag (gf_get_gauge) */
+    GF_FLAG_LEARNED = 1u << 4,          /* reserve the learned preconditioner (gf_mlp_set_weights) */
+    GF_FLAG_RECORD_SPECTRA = 1u << 5    /* reserve spectrum recording (gf_record_spectra) */
 };
 
 typedef struct {
@@ -117,8 +120,17 @@ gf_status gf_quality(gf_ctx* ctx, double* theta, double* F);
 gf_status gf_get_links(gf_ctx* ctx, void* d_out);
 
 /*
+ * Write the accumulated gauge transform G (canonical matrix field, V*9
+ * complex double) with U_current(x) = G(x) U_input(x) G(x+mu)^dag. Needs
+ * GF_FLAG_ACCUMULATE_GAUGE (always on for GF_MIXED); else GF_ESTATE.
+ * Float contexts re-orthonormalise G after every update.
+ */
+gf_status gf_get_gauge(gf_ctx* ctx, void* d_out);
+
+/*
  * Copy the last n recorded (theta_k, F_k) pairs, k = iters-n+1 .. iters, into
- * host arrays (n <= 16384 and n <= iters + 1).
+ * host arrays (n <= 16384 and n <= iters + 1). GF_MIXED: the history of the
+ * active phase, counted from the start of that phase.
  */
 gf_status gf_history(gf_ctx* ctx, int64_t n, double* h_theta, double* h_F);
 
@@ -159,6 +171,66 @@ enum {
 };
 gf_status gf_set_timing(gf_ctx* ctx, int32_t enable);
 gf_status gf_kernel_times(gf_ctx* ctx, int32_t n, double* h_ms_total, int64_t* h_counts);
+
+/*
+ * Learned spectral preconditioner (an extension of the paper's fixed filter).
+ * The multiplier of mode p becomes m0(p) exp(o_s(p) + o_a(0)), where m0 is
+ * the Fourier-acceleration multiplier (alpha/2) p2max/p^2 and (o_s, o_a) are
+ * the outputs of a 6 -> 64 -> 64 -> 2 tanh network (float) on the features
+ * of the momentum tuple n_mu in [0, N_mu/2] at iteration k:
+ *   x = (p^2_mu/4 - 1/2 for mu = 0..3, log10(theta_k)/8 + 1, k/64),
+ * o_a being read at the zero tuple. Parameters, gf_mlp_param_count() floats:
+ * W1 (64x6, row-major), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2).
+ * A learned step that increases theta or lowers F (beyond 1e-14) is undone
+ * and replaced by a plain Fourier-accelerated step; after 3 consecutive
+ * rejections the network is switched off (gf_result.fallbacks counts them).
+ */
+int32_t gf_mlp_param_count(void);
+
+/* Copy d_params (device) into the context and switch the network on (enable = 1) or off. */
+gf_status gf_mlp_set_weights(gf_ctx* ctx, const float* d_params, int32_t enable);
+
+/*
+ * Apply n plain Fourier-accelerated updates and record, for every step k
+ * and every momentum tuple i (n_mu in [0, N_mu/2], first axis fastest),
+ * d_records[(k*T + i)*2 + 0] = P_k = sum over the tuple's +-n reflections and
+ * the four packed divergence fields of |Z_k(p)|^2 after the forward FFT, and
+ * [.. + 1] = C_k = the same sum of Re[Z_{k+1}(p) conj(Z_k(p))] (T tuples,
+ * double). h_theta[k] = theta_k. Needs GF_FLAG_RECORD_SPECTRA.
+ */
+gf_status gf_record_spectra(gf_ctx* ctx, int64_t n, double* d_records, double* h_theta);
+
+/*
+ * Training (no lattice context). Rows are momentum tuples of samples; sample
+ * s owns rows [offsets[s], offsets[s+1]) of x (6 floats per row, the features
+ * above) and tgt (m0, P, kappa per row), its first row being the zero tuple.
+ * Loss = mean over samples of sum_p P (1 - m kappa)^2 / sum_p P with
+ * m = m0 exp(o_s + o_a(first row)). All pointers are device pointers except
+ * h_loss (host, may be NULL); d_ws holds gf_mlp_workspace_bytes(n_rows,
+ * n_samples) bytes. Adam: beta1 0.9, beta2 0.999, eps 1e-8, step from 1.
+ */
+size_t gf_mlp_workspace_bytes(int64_t n_rows, int32_t n_samples);
+/*
+ * Training rows from records of gf_record_spectra: for sample s (record of
+ * step d_k[s] with quality d_theta[s]) and tuple i, row s*T + i of d_x gets
+ * the features and of d_tgt (m0, P, kappa), m0 = (alpha/2) p2max/p^2 and
+ * kappa = (1 - C/P)/m0 clipped to [1e-3, 1e3] (1 where P or m0 is 0).
+ * dims: host array {Nx, Ny, Nz, Nt}; T = prod(N_mu/2 + 1).
+ */
+gf_status gf_mlp_make_samples(const double* d_records, const double* d_theta, const int32_t* d_k,
+                              int32_t n_samples, const int32_t* dims, double alpha, float* d_x,
+                              float* d_tgt, void* stream);
+gf_status gf_mlp_forward(const float* d_params, const float* d_x, int64_t n_rows, float* d_out,
+                         void* d_ws, size_t ws_bytes, void* stream);
+gf_status gf_mlp_loss_grad(const float* d_params, const float* d_x, const float* d_tgt,
+                           const int32_t* d_offsets, int32_t n_samples, int64_t n_rows, float* d_grad,
+                           void* d_ws, size_t ws_bytes, void* stream, double* h_loss);
+gf_status gf_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t step,
+                      float lr, void* stream);
+gf_status gf_mlp_train_step(float* d_params, float* d_m, float* d_v, int64_t step, float lr,
+                            const float* d_x, const float* d_tgt, const int32_t* d_offsets,
+                            int32_t n_samples, int64_t n_rows, float* d_grad, void* d_ws,
+                            size_t ws_bytes, void* stream, double* h_loss);
 
 /* Message of the last error on this context (or of the last failed gf_init if ctx is NULL). */
 const char* gf_last_error(const gf_ctx* ctx);

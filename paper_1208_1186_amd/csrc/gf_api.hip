@@ -89,15 +89,24 @@ struct Layout {
     // inverse (x, y) pass of four fields + gauge rows
     int thrC, eptC;
     size_t ldsC;
+    bool acc;         // keep the accumulated gauge transform
+    bool learned;     // reserve the network parameters and the multiplier table
+    bool record;      // reserve two spectra and the per-tuple record
+    int ntuples;      // distinct momentum tuples (N_mu/2 + 1 per axis)
     // workspace offsets
-    size_t off_ctl, off_part, off_sin2, off_tw, off_d, off_q, off_g, off_links[2], total;
+    size_t off_ctl, off_part, off_sin2, off_tw, off_d, off_q, off_g, off_acc, off_links[2], off_mlp, off_mtab,
+        off_spec[2], off_rec, total;
+    // GF_MIXED: a float child (bulk) and a double child (polish) share the workspace
+    bool mixed;
+    size_t child_off[2];
 };
 
-gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
+gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     if (!p) {
         err = "params is NULL";
         return GF_EINVAL;
     }
+    L.mixed = false;
     int64_t vol = 1;
     for (int i = 0; i < 4; ++i) {
         const int n = p->dims[i];
@@ -117,10 +126,6 @@ gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
         err = "unknown precision";
         return GF_EINVAL;
     }
-    if (p->precision == GF_MIXED) {
-        err = "GF_MIXED is not available in this build";
-        return GF_ENOTSUP;
-    }
     if (!(p->alpha > 0.0) || !std::isfinite(p->alpha)) {
         err = "alpha must be positive and finite";
         return GF_EINVAL;
@@ -130,6 +135,14 @@ gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
         return GF_EINVAL;
     }
     L.vol = vol;
+    L.acc = (p->flags & GF_FLAG_ACCUMULATE_GAUGE) != 0;
+    L.learned = (p->flags & GF_FLAG_LEARNED) != 0;
+    L.record = (p->flags & GF_FLAG_RECORD_SPECTRA) != 0;
+    if (L.learned && L.acc) {
+        err = "GF_FLAG_LEARNED cannot be combined with an accumulated gauge transform (GF_FLAG_ACCUMULATE_GAUGE, GF_MIXED)";
+        return GF_EINVAL;
+    }
+    L.ntuples = (L.n[0] / 2 + 1) * (L.n[1] / 2 + 1) * (L.n[2] / 2 + 1) * (L.n[3] / 2 + 1);
     L.fp32 = p->precision == GF_FP32_12 || p->precision == GF_FP32_18;
     L.ne = (p->precision == GF_FP64_12 || p->precision == GF_FP32_12) ? 6 : 9;
     const size_t csz = L.fp32 ? 8 : 16;
@@ -189,12 +202,53 @@ gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
     o = align_up(o + 4 * L.ps * csz, kAlign);
     L.off_g = o;
     o = align_up(o + 6 * L.ps * csz, kAlign);
+    L.off_acc = o;
+    if (L.acc) o = align_up(o + 6 * L.ps * csz, kAlign);
     for (int i = 0; i < 2; ++i) {
         L.off_links[i] = o;
         o = align_up(o + (size_t)4 * L.ne * L.ps * csz, kAlign);
     }
+    L.off_mlp = o;
+    if (L.learned) o = align_up(o + kMlpParams * sizeof(float), kAlign);
+    L.off_mtab = o;
+    if (L.learned) o = align_up(o + (size_t)L.ntuples * csz / 2, kAlign);
+    for (int i = 0; i < 2; ++i) {
+        L.off_spec[i] = o;
+        if (L.record) o = align_up(o + 4 * L.ps * csz, kAlign);
+    }
+    L.off_rec = o;
+    if (L.record) o = align_up(o + (size_t)L.ntuples * 2 * sizeof(double), kAlign);
     L.total = o;
     return GF_OK;
+}
+
+// Parameters of the two children of a GF_MIXED context.
+gf_params mixed_child(const gf_params& p, int which) {
+    gf_params q = p;
+    q.precision = which == 0 ? GF_FP32_12 : GF_FP64_18;
+    q.flags |= GF_FLAG_ACCUMULATE_GAUGE;
+    return q;
+}
+
+gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
+    if (p && p->precision == GF_MIXED) {
+        if (!(p->switch_theta > 0.0) || !std::isfinite(p->switch_theta)) {
+            err = "switch_theta must be positive and finite";
+            return GF_EINVAL;
+        }
+        Layout a, b;
+        gf_params q0 = mixed_child(*p, 0), q1 = mixed_child(*p, 1);
+        gf_status s = plan_plain(&q0, a, err);
+        if (s == GF_OK) s = plan_plain(&q1, b, err);
+        if (s != GF_OK) return s;
+        L = b;
+        L.mixed = true;
+        L.child_off[0] = 0;
+        L.child_off[1] = align_up(a.total, kAlign);
+        L.total = L.child_off[1] + b.total;
+        return GF_OK;
+    }
+    return plan_plain(p, L, err);
 }
 
 }  // namespace
@@ -214,6 +268,22 @@ struct gf_ctx {
     void* Q;      // FFT work buffer (four packed fields)
     void* Gb;     // gauge rows (six planes)
     void* Lb[2];  // links after k updates live in Lb[k & 1]
+    void* Acc;    // accumulated gauge transform rows (or nullptr)
+    // learned preconditioner state
+    TupleGeom tg;
+    float* mlp;          // network parameters (workspace copy)
+    void* mtab;          // multiplier per tuple for the current iteration
+    bool net_on = false;       // gf_mlp_set_weights called and not disabled
+    bool net_this = false;     // the iteration being queued uses the table
+    int rejects = 0;           // consecutive rejected learned steps
+    int fallbacks = 0;         // rejected learned steps in total
+    // spectrum recording
+    void* spec[2];
+    double* rec;
+    void* spec_capture = nullptr;  // where the (z, t) pass writes the spectrum, if anywhere
+    // GF_MIXED parent: the float and double children, and the active phase
+    gf_ctx* child[2] = {nullptr, nullptr};
+    int phase = 1;
     long long k_host;  // updates applied, as of the last read of the control block
     FftPlan plan[4];
     Ctl* h_head;  // pinned host copy of the control block's leading scalars
@@ -330,14 +400,14 @@ bool launch_xy_ct(gf_ctx* c, const void* src, void* dst, int force, bool loop_re
 }
 
 template <typename T>
-bool launch_zt_ct(gf_ctx* c, void* Z, T coef, int no_fa, int force) {
+bool launch_zt_ct(gf_ctx* c, void* Z, T coef, int no_fa, int force, const T* mtab, cx<T>* spec) {
     const Layout& L = c->L;
     const T* s2 = reinterpret_cast<const T*>(c->sin2);
 #define GF_X(A, B, BB)                                                                                     \
     if (L.n[2] == A && L.n[3] == B && L.bx == BB) {                                                        \
         hipLaunchKernelGGL((k_fft_zt_ct<T, A, B, BB>), dim3(4 * L.n[1] * (L.n[0] / BB)),                   \
                            dim3(ct_threads(BB * A * B, 8)), 0, c->st, cxp<T>(Z), L.ps, L.n[0], L.n[1],     \
-                           twp<T>(c, 2), twp<T>(c, 3), s2, coef, no_fa, c->ctl, force);                    \
+                           twp<T>(c, 2), twp<T>(c, 3), s2, coef, no_fa, c->ctl, force, mtab, c->tg, spec); \
         return true;                                                                                       \
     }
     if constexpr (sizeof(T) == 8) {
@@ -397,14 +467,16 @@ void launch_zt(gf_ctx* c, void* Z, int force) {
     const bool no_fa = (c->p.flags & GF_FLAG_NO_FA) != 0;
     const double coef = 0.5 * c->p.alpha * (no_fa ? 1.0 : 16.0) / (double)L.vol;
     tstart(c, GF_K_FFT_ZT);
-    if (!generic_fft(c) && launch_zt_ct<T>(c, Z, (T)coef, no_fa ? 1 : 0, force)) {
+    const T* mtab = c->net_this ? reinterpret_cast<const T*>(c->mtab) : nullptr;
+    cx<T>* spec = reinterpret_cast<cx<T>*>(c->spec_capture);
+    if (!generic_fft(c) && launch_zt_ct<T>(c, Z, (T)coef, no_fa ? 1 : 0, force, mtab, spec)) {
         tstop(c);
         return;
     }
     hipLaunchKernelGGL((k_fft_zt<T, kEPT>), dim3(4 * L.n[1] * (L.n[0] / L.bx)), dim3(L.thrB), L.ldsB, c->st,
                        cxp<T>(Z), L.ps, L.n[0], L.n[1], L.n[2], L.n[3], L.bx, L.tsp, c->plan[2], c->plan[3],
                        twp<T>(c, 2), twp<T>(c, 3), reinterpret_cast<const T*>(c->sin2), (T)coef, no_fa ? 1 : 0,
-                       c->ctl, force);
+                       c->ctl, force, mtab, c->tg, spec);
     tstop(c);
 }
 
@@ -458,7 +530,7 @@ void launch_fused_t(gf_ctx* c, long long k) {
     tstart(c, GF_K_UPDATE_MEASURE);
     hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused), dim3(kFusedThreads), 0, c->st,
                        links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
-                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl);
+                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl, reinterpret_cast<cx<T>*>(c->Acc));
     tstop(c);
 }
 
@@ -491,12 +563,21 @@ gf_status launch_measure(gf_ctx* c) {
 
 // Queue the update from k to k + 1 (no-ops on the device once the stop flag is set).
 gf_status one_iteration(gf_ctx* c, long long k) {
+    const double coef = 0.5 * c->p.alpha * 16.0 / (double)c->L.vol;
     if (c->L.fp32) {
         launch_xy<float, false>(c, c->D, c->Q, 0, true);
+        if (c->net_this)
+            hipLaunchKernelGGL(k_mlp_table<float>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st, c->mlp,
+                               reinterpret_cast<const float*>(c->sin2), c->tg, coef, c->ctl,
+                               reinterpret_cast<float*>(c->mtab));
         launch_zt<float>(c, c->Q, 0);
         launch_gauge_pass<float>(c, 0);
     } else {
         launch_xy<double, false>(c, c->D, c->Q, 0, true);
+        if (c->net_this)
+            hipLaunchKernelGGL(k_mlp_table<double>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st, c->mlp,
+                               reinterpret_cast<const double*>(c->sin2), c->tg, coef, c->ctl,
+                               reinterpret_cast<double*>(c->mtab));
         launch_zt<double>(c, c->Q, 0);
         launch_gauge_pass<double>(c, 0);
     }
@@ -603,13 +684,54 @@ void stage_spectral(gf_ctx* c, bool gauge) {
         launch_xy<T, true>(c, c->Q, c->Q, 1, false);
 }
 
-gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
+constexpr int kMaxRejects = 3;  // consecutive rejected learned steps before the network is switched off
+
+// One learned step from k with the acceptance test: if theta grows or F
+// drops, the step is undone (the links of step k are still in Lb[k & 1]) and
+// a plain Fourier-accelerated step is taken instead.
+gf_status learned_step(gf_ctx* c) {
+    const long long k0 = c->k_host;
+    const double th0 = c->h_head->theta, f0 = c->h_head->F;
+    c->net_this = true;
+    gf_status s = one_iteration(c, k0);
+    c->net_this = false;
+    if (s == GF_OK) s = loop_finalize(c);
+    if (s == GF_OK) s = read_head(c);
+    if (s != GF_OK) return s;
+    if (c->h_head->done && c->h_head->numeric == 0 && c->h_head->theta < th0) {
+        c->rejects = 0;
+        return GF_OK;
+    }
+    const bool worse = c->h_head->numeric || !(c->h_head->theta <= th0) || c->h_head->F < f0 - 1e-14;
+    if (!worse) {
+        c->rejects = 0;
+        return GF_OK;
+    }
+    ++c->fallbacks;
+    if (++c->rejects >= kMaxRejects) c->net_on = false;
+    hipLaunchKernelGGL(k_rollback, dim3(1), dim3(64), 0, c->st, c->ctl, k0);
+    c->k_host = k0;
+    s = launched(c, "rollback launch");
+    if (s == GF_OK) s = launch_measure(c);
+    if (s == GF_OK) s = read_head(c);
+    if (s == GF_OK && !c->h_head->done) s = one_iteration(c, k0);
+    if (s == GF_OK) s = loop_finalize(c);
+    if (s == GF_OK) s = read_head(c);
+    return s;
+}
+
+gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r, bool unpack = true) {
     const auto t0 = std::chrono::steady_clock::now();
     gf_status s = set_tol(c, tol);
     if (s == GF_OK) s = read_head(c);
     if (s != GF_OK) return s;
     const long long start = c->h_head->iters;
     while (!c->h_head->done && c->h_head->iters - start < max_iter) {
+        if (c->net_on) {
+            s = learned_step(c);
+            if (s != GF_OK) return s;
+            continue;
+        }
         const int64_t left = max_iter - (c->h_head->iters - start);
         const int64_t k = std::min<int64_t>(left, c->p.check_every);
         for (int64_t i = 0; i < k && s == GF_OK; ++i) s = one_iteration(c, c->k_host + i);
@@ -617,19 +739,179 @@ gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
         if (s == GF_OK) s = read_head(c);
         if (s != GF_OK) return s;
     }
-    s = unpack_links(c, c->links_user);
-    if (s == GF_OK) s = check_hip(c, hipStreamSynchronize(c->st), "sync");
-    if (s != GF_OK) return s;
+    if (unpack) {
+        s = unpack_links(c, c->links_user);
+        if (s == GF_OK) s = check_hip(c, hipStreamSynchronize(c->st), "sync");
+        if (s != GF_OK) return s;
+    }
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (r) {
         r->iters = c->h_head->iters;
         r->theta = c->h_head->theta;
         r->F = c->h_head->F;
-        r->phase = 1;
-        r->fallbacks = 0;
+        r->phase = c->L.fp32 ? 0 : 1;
+        r->fallbacks = c->fallbacks;
         r->seconds = secs;
     }
     if (c->h_head->numeric) return fail(c, GF_ENUMERIC, "theta is not finite");
+    return GF_OK;
+}
+
+// Carve a plain (single-precision-class) context out of ws and set it up:
+// tables, control block, links packed from the canonical d_links, the
+// accumulated transform set to 1, and (if measure) theta and F of the input.
+gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsigned char* ws,
+                     hipStream_t st, bool measure) {
+    c->p = p;
+    c->L = L;
+    c->st = st;
+    c->links_user = d_links;
+    c->ws = ws;
+    c->ctl = reinterpret_cast<Ctl*>(ws + L.off_ctl);
+    c->part = reinterpret_cast<double2*>(ws + L.off_part);
+    c->sin2 = ws + L.off_sin2;
+    for (int d = 0; d < 4; ++d) c->tw[d] = ws + L.off_tw + (size_t)d * kMaxExtent * 16;
+    c->D = ws + L.off_d;
+    c->Q = ws + L.off_q;
+    c->Gb = ws + L.off_g;
+    c->Acc = L.acc ? ws + L.off_acc : nullptr;
+    c->mlp = L.learned ? reinterpret_cast<float*>(ws + L.off_mlp) : nullptr;
+    c->mtab = L.learned ? ws + L.off_mtab : nullptr;
+    for (int i = 0; i < 2; ++i) c->spec[i] = L.record ? ws + L.off_spec[i] : nullptr;
+    c->rec = L.record ? reinterpret_cast<double*>(ws + L.off_rec) : nullptr;
+    for (int d = 0; d < 4; ++d) {
+        c->tg.n[d] = L.n[d];
+        c->tg.h[d] = L.n[d] / 2 + 1;
+    }
+    c->tg.count = L.ntuples;
+    for (int i = 0; i < 2; ++i) c->Lb[i] = ws + L.off_links[i];
+    c->k_host = 0;
+    c->phase = L.fp32 ? 0 : 1;
+    for (int d = 0; d < 4; ++d) {
+        c->geom.n[d] = L.n[d];
+        c->plan[d] = make_plan(L.n[d]);
+    }
+    c->geom.vol = L.vol;
+    c->geom.stride[0] = 1;
+    for (int d = 1; d < 4; ++d) c->geom.stride[d] = c->geom.stride[d - 1] * L.n[d - 1];
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_head), kHeadBytes) != hipSuccess) {
+        c->h_head = nullptr;
+        return fail(c, GF_EDEVICE, "hipHostMalloc of the control readback buffer failed");
+    }
+    std::memset(c->h_head, 0, kHeadBytes);
+    raise_lds_limits();
+    std::vector<unsigned char> host;
+    if (L.fp32)
+        fill_tables<float>(c, host);
+    else
+        fill_tables<double>(c, host);
+    Ctl head{};
+    head.tol = -1.0;
+    gf_status s;
+    if ((s = check_hip(c, hipMemcpyAsync(c->sin2, host.data(), host.size(), hipMemcpyHostToDevice, c->st),
+                       "table upload")) != GF_OK)
+        return s;
+    if ((s = check_hip(c, hipMemcpyAsync(c->ctl, &head, kHeadBytes, hipMemcpyHostToDevice, c->st),
+                       "control upload")) != GF_OK)
+        return s;
+    GF_DISPATCH(c, launch_pack_t, c, c->links_user);
+    s = launched(c, "pack launch");
+    if (s == GF_OK && c->Acc) {
+        if (L.fp32)
+            hipLaunchKernelGGL(k_gauge_identity<float>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st, cxp<float>(c->Acc),
+                               L.ps, L.vol);
+        else
+            hipLaunchKernelGGL(k_gauge_identity<double>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st,
+                               cxp<double>(c->Acc), L.ps, L.vol);
+        s = launched(c, "identity launch");
+    }
+    if (s == GF_OK && measure) s = launch_measure(c);
+    if (s == GF_OK) s = read_head(c);
+    if (s == GF_OK) {
+        // hipMemcpyAsync from pageable memory may return before the copy is done: keep `host` alive until here.
+        s = check_hip(c, hipStreamSynchronize(c->st), "sync");
+    }
+    return s;
+}
+
+void free_ctx(gf_ctx* c) {
+    if (!c) return;
+    for (int i = 0; i < 2; ++i) free_ctx(c->child[i]);
+    if (c->h_head) {
+        (void)hipStreamSynchronize(c->st);
+        (void)hipHostFree(c->h_head);
+    }
+    for (auto& e : c->ev) (void)hipEventDestroy(e);
+    delete c;
+}
+
+gf_ctx* active(gf_ctx* c) { return c->L.mixed ? c->child[c->phase] : c; }
+
+// GF_MIXED: float iterations (accumulating G) until theta < max(switch_theta,
+// tol) or the float descent stalls, then U64 = G U0 G(x+mu)^dag in double and
+// double iterations. tol < 0 means "apply max_iter updates" (gf_iterate).
+constexpr double kStallTheta = 1e-5;   // below this, a batch that does not cut theta by 5% has stalled
+constexpr double kStallRatio = 0.95;
+
+gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    gf_ctx* a = c->child[0];
+    gf_ctx* b = c->child[1];
+    int64_t left = max_iter;
+    gf_status s = GF_OK;
+    if (c->phase == 0) {
+        const double sw = std::max(c->p.switch_theta, tol);
+        double last = a->h_head->theta;
+        bool stalled = false;
+        while (left > 0 && !stalled) {
+            const long long before = a->h_head->iters;
+            s = run_loop(a, sw, std::min<int64_t>(left, a->p.check_every), nullptr, false);
+            if (s != GF_OK) return fail(c, s, a->err);
+            left -= a->h_head->iters - before;
+            if (a->h_head->done) break;
+            const double th = a->h_head->theta;
+            stalled = th < kStallTheta && th > kStallRatio * last;
+            last = th;
+        }
+        if (a->h_head->numeric) return fail(c, GF_ENUMERIC, "theta is not finite");
+        const bool reached = a->h_head->theta < sw;
+        if ((tol > 0.0 && a->h_head->theta < tol) || (!reached && !stalled)) {
+            // converged in float, or out of iterations before the hand-over
+            s = unpack_links(a, c->links_user);
+            if (s == GF_OK) s = check_hip(a, hipStreamSynchronize(a->st), "sync");
+            if (s != GF_OK) return fail(c, s, a->err);
+            if (r) {
+                r->iters = a->h_head->iters;
+                r->theta = a->h_head->theta;
+                r->F = a->h_head->F;
+                r->phase = 0;
+                r->fallbacks = 0;
+                r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            }
+            if (tol > 0.0 && !(a->h_head->theta < tol)) return fail(c, GF_ENOTCONV, "max_iter reached before theta < tol");
+            return GF_OK;
+        }
+        // hand-over: the double child's buffer 0 holds the input links
+        hipLaunchKernelGGL(k_apply_accumulated<9>, dim3(b->L.nblk), dim3(kSiteThreads), 0, b->st,
+                           links_of<double, 9>(b, 0), reinterpret_cast<const cx<float>*>(a->Acc), a->L.ps,
+                           reinterpret_cast<cx<double>*>(b->Acc), b->L.ps, b->geom);
+        s = launched(b, "hand-over launch");
+        if (s == GF_OK) s = launch_measure(b);
+        if (s == GF_OK) s = read_head(b);
+        if (s != GF_OK) return fail(c, s, b->err);
+        c->phase = 1;
+    }
+    s = run_loop(b, tol, left, nullptr, true);
+    if (s != GF_OK) return fail(c, s, b->err);
+    if (r) {
+        r->iters = a->h_head->iters + b->h_head->iters;
+        r->theta = b->h_head->theta;
+        r->F = b->h_head->F;
+        r->phase = 1;
+        r->fallbacks = 0;
+        r->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (tol > 0.0 && !b->h_head->done) return fail(c, GF_ENOTCONV, "max_iter reached before theta < tol");
     return GF_OK;
 }
 
@@ -676,58 +958,36 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
             g_init_error = "out of host memory";
             return GF_EINVAL;
         }
-        c->p = *params;
-        c->L = L;
-        c->st = reinterpret_cast<hipStream_t>(stream);
-        c->links_user = reinterpret_cast<double*>(d_links);
-        c->ws = reinterpret_cast<unsigned char*>(d_workspace);
-        c->ctl = reinterpret_cast<Ctl*>(c->ws + L.off_ctl);
-        c->part = reinterpret_cast<double2*>(c->ws + L.off_part);
-        c->sin2 = c->ws + L.off_sin2;
-        for (int d = 0; d < 4; ++d) c->tw[d] = c->ws + L.off_tw + (size_t)d * kMaxExtent * 16;
-        c->D = c->ws + L.off_d;
-        c->Q = c->ws + L.off_q;
-        c->Gb = c->ws + L.off_g;
-        for (int i = 0; i < 2; ++i) c->Lb[i] = c->ws + L.off_links[i];
-        c->k_host = 0;
-        for (int d = 0; d < 4; ++d) {
-            c->geom.n[d] = L.n[d];
-            c->plan[d] = make_plan(L.n[d]);
+        double* links = reinterpret_cast<double*>(d_links);
+        unsigned char* ws = reinterpret_cast<unsigned char*>(d_workspace);
+        hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+        if (!L.mixed) {
+            s = init_plain(c, *params, L, links, ws, st, true);
+        } else {
+            c->p = *params;
+            c->L = L;
+            c->st = st;
+            c->links_user = links;
+            c->phase = 0;
+            for (int i = 0; i < 2 && s == GF_OK; ++i) {
+                c->child[i] = new (std::nothrow) gf_ctx();
+                if (!c->child[i]) {
+                    s = fail(c, GF_EINVAL, "out of host memory");
+                    break;
+                }
+                const gf_params q = mixed_child(*params, i);
+                Layout Lc;
+                plan_plain(&q, Lc, err);
+                // the double child keeps the input links untouched in its buffer 0 until the hand-over
+                s = init_plain(c->child[i], q, Lc, links, ws + L.child_off[i], st, i == 0);
+                if (s != GF_OK) c->err = c->child[i]->err;
+            }
         }
-        c->geom.vol = L.vol;
-        c->geom.stride[0] = 1;
-        for (int d = 1; d < 4; ++d) c->geom.stride[d] = c->geom.stride[d - 1] * L.n[d - 1];
-        if (hipHostMalloc(reinterpret_cast<void**>(&c->h_head), kHeadBytes) != hipSuccess) {
-            g_init_error = "hipHostMalloc of the control readback buffer failed";
-            delete c;
-            return GF_EDEVICE;
-        }
-        raise_lds_limits();
-        std::vector<unsigned char> host;
-        if (L.fp32)
-            fill_tables<float>(c, host);
-        else
-            fill_tables<double>(c, host);
-        Ctl head{};
-        head.tol = -1.0;
-        auto init_fail = [&](gf_status st) {
+        if (s != GF_OK) {
             g_init_error = c->err;
-            (void)hipStreamSynchronize(c->st);
-            (void)hipHostFree(c->h_head);
-            delete c;
-            return st;
-        };
-        if ((s = check_hip(c, hipMemcpyAsync(c->sin2, host.data(), host.size(), hipMemcpyHostToDevice, c->st),
-                           "table upload")) != GF_OK)
-            return init_fail(s);
-        if ((s = check_hip(c, hipMemcpyAsync(c->ctl, &head, kHeadBytes, hipMemcpyHostToDevice, c->st),
-                           "control upload")) != GF_OK)
-            return init_fail(s);
-        GF_DISPATCH(c, launch_pack_t, c, c->links_user);
-        s = launched(c, "pack launch");
-        if (s == GF_OK) s = launch_measure(c);
-        if (s == GF_OK) s = read_head(c);
-        if (s != GF_OK) return init_fail(s);
+            free_ctx(c);
+            return s;
+        }
         *out = c;
         return GF_OK;
     } catch (...) {
@@ -740,6 +1000,7 @@ gf_status gf_iterate(gf_ctx* c, int64_t n, gf_result* r) {
     if (!c) return GF_EINVAL;
     if (n < 0) return fail(c, GF_EINVAL, "n must be >= 0");
     try {
+        if (c->L.mixed) return mixed_run(c, -1.0, n, r);
         return run_loop(c, -1.0, n, r);
     } catch (...) {
         return fail(c, GF_EINVAL, "unexpected host exception");
@@ -751,6 +1012,7 @@ gf_status gf_fix_until(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     if (!(tol > 0.0)) return fail(c, GF_EINVAL, "theta_tol must be > 0");
     if (max_iter < 0) return fail(c, GF_EINVAL, "max_iter must be >= 0");
     try {
+        if (c->L.mixed) return mixed_run(c, tol, max_iter, r);
         gf_status s = run_loop(c, tol, max_iter, r);
         if (s != GF_OK) return s;
         if (!c->h_head->done) return fail(c, GF_ENOTCONV, "max_iter reached before theta < tol");
@@ -763,16 +1025,18 @@ gf_status gf_fix_until(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
 gf_status gf_quality(gf_ctx* c, double* theta, double* F) {
     if (!c) return GF_EINVAL;
     if (!theta || !F) return fail(c, GF_EINVAL, "null output");
-    gf_status s = read_head(c);
-    if (s != GF_OK) return s;
-    *theta = c->h_head->theta;
-    *F = c->h_head->F;
+    gf_ctx* a = active(c);
+    gf_status s = read_head(a);
+    if (s != GF_OK) return fail(c, s, a->err);
+    *theta = a->h_head->theta;
+    *F = a->h_head->F;
     return GF_OK;
 }
 
 gf_status gf_get_links(gf_ctx* c, void* d_out) {
     if (!c) return GF_EINVAL;
     if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
+    if (c->L.mixed) c = active(c);
     gf_status s = unpack_links(c, reinterpret_cast<double*>(d_out));
     if (s != GF_OK) return s;
     return check_hip(c, hipStreamSynchronize(c->st), "sync");
@@ -781,6 +1045,7 @@ gf_status gf_get_links(gf_ctx* c, void* d_out) {
 gf_status gf_history(gf_ctx* c, int64_t n, double* h_theta, double* h_F) {
     if (!c) return GF_EINVAL;
     if (!h_theta || !h_F) return fail(c, GF_EINVAL, "null output");
+    if (c->L.mixed) c = active(c);
     gf_status s = read_head(c);
     if (s != GF_OK) return s;
     const long long it = c->h_head->iters;
@@ -799,6 +1064,7 @@ gf_status gf_history(gf_ctx* c, int64_t n, double* h_theta, double* h_F) {
 
 gf_status gf_stage_divergence(gf_ctx* c, void* d_delta) {
     if (!c) return GF_EINVAL;
+    if (c->L.mixed) c = active(c);
     if (!d_delta) return fail(c, GF_EINVAL, "d_delta is NULL");
     gf_status s = launch_measure(c);
     if (s != GF_OK) return s;
@@ -813,6 +1079,7 @@ gf_status gf_stage_divergence(gf_ctx* c, void* d_delta) {
 
 gf_status gf_stage_filter(gf_ctx* c, const void* d_in, void* d_out) {
     if (!c) return GF_EINVAL;
+    if (c->L.mixed) c = active(c);
     if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
     if (c->L.fp32) {
         field_pack<float>(c, d_in, c->Q);
@@ -830,6 +1097,7 @@ gf_status gf_stage_filter(gf_ctx* c, const void* d_in, void* d_out) {
 
 gf_status gf_stage_gauge(gf_ctx* c, const void* d_in, void* d_out) {
     if (!c) return GF_EINVAL;
+    if (c->L.mixed) c = active(c);
     if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
     if (c->L.fp32) {
         field_pack<float>(c, d_in, c->Q);
@@ -847,6 +1115,7 @@ gf_status gf_stage_gauge(gf_ctx* c, const void* d_in, void* d_out) {
 
 gf_status gf_stage_update(gf_ctx* c, const void* d_scaled) {
     if (!c) return GF_EINVAL;
+    if (c->L.mixed) c = active(c);
     if (!d_scaled) return fail(c, GF_EINVAL, "null pointer");
     if (c->L.fp32)
         field_pack<float>(c, d_scaled, c->Q);
@@ -862,6 +1131,13 @@ gf_status gf_stage_update(gf_ctx* c, const void* d_scaled) {
 
 gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
     if (!c) return GF_EINVAL;
+    if (c->L.mixed) {
+        for (int i = 0; i < 2; ++i) {
+            gf_status s = gf_set_timing(c->child[i], enable);
+            if (s != GF_OK) return s;
+        }
+        return GF_OK;
+    }
     GF_TRY_HIP(c, hipStreamSynchronize(c->st));
     tdrain(c);
     c->timing = enable != 0;
@@ -875,6 +1151,23 @@ gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
 gf_status gf_kernel_times(gf_ctx* c, int32_t n, double* h_ms_total, int64_t* h_counts) {
     if (!c) return GF_EINVAL;
     if (!h_ms_total || !h_counts || n < 0 || n > GF_NKERNELS) return fail(c, GF_EINVAL, "bad arguments");
+    if (c->L.mixed) {
+        double ms[GF_NKERNELS];
+        int64_t cnt[GF_NKERNELS];
+        for (int i = 0; i < n; ++i) {
+            h_ms_total[i] = 0.0;
+            h_counts[i] = 0;
+        }
+        for (int k = 0; k < 2; ++k) {
+            gf_status s = gf_kernel_times(c->child[k], n, ms, cnt);
+            if (s != GF_OK) return s;
+            for (int i = 0; i < n; ++i) {
+                h_ms_total[i] += ms[i];
+                h_counts[i] += cnt[i];
+            }
+        }
+        return GF_OK;
+    }
     GF_TRY_HIP(c, hipStreamSynchronize(c->st));
     tdrain(c);
     for (int i = 0; i < n; ++i) {
@@ -886,12 +1179,213 @@ gf_status gf_kernel_times(gf_ctx* c, int32_t n, double* h_ms_total, int64_t* h_c
 
 const char* gf_last_error(const gf_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
-void gf_destroy(gf_ctx* c) {
-    if (!c) return;
-    (void)hipStreamSynchronize(c->st);
-    if (c->h_head) (void)hipHostFree(c->h_head);
-    for (auto& e : c->ev) (void)hipEventDestroy(e);
-    delete c;
+gf_status gf_get_gauge(gf_ctx* c, void* d_out) {
+    if (!c) return GF_EINVAL;
+    if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
+    gf_ctx* a = active(c);
+    if (!a->Acc) return fail(c, GF_ESTATE, "the accumulated gauge transform is not kept (GF_FLAG_ACCUMULATE_GAUGE)");
+    if (a->L.fp32)
+        hipLaunchKernelGGL(k_gauge_unpack<float>, dim3(a->L.nblk), dim3(kSiteThreads), 0, a->st,
+                           reinterpret_cast<const cx<float>*>(a->Acc), a->L.ps, reinterpret_cast<double*>(d_out),
+                           a->L.vol);
+    else
+        hipLaunchKernelGGL(k_gauge_unpack<double>, dim3(a->L.nblk), dim3(kSiteThreads), 0, a->st,
+                           reinterpret_cast<const cx<double>*>(a->Acc), a->L.ps, reinterpret_cast<double*>(d_out),
+                           a->L.vol);
+    gf_status s = launched(a, "gauge unpack launch");
+    if (s == GF_OK) s = check_hip(a, hipStreamSynchronize(a->st), "sync");
+    return s == GF_OK ? s : fail(c, s, a->err);
 }
+
+gf_status gf_mlp_set_weights(gf_ctx* c, const float* d_params, int32_t enable) {
+    if (!c) return GF_EINVAL;
+    if (c->L.mixed || !c->mlp) return fail(c, GF_ESTATE, "context was created without GF_FLAG_LEARNED");
+    if (enable && !d_params) return fail(c, GF_EINVAL, "d_params is NULL");
+    if (d_params) GF_TRY_HIP(c, hipMemcpyAsync(c->mlp, d_params, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, c->st));
+    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    c->net_on = enable != 0;
+    c->rejects = 0;
+    return GF_OK;
+}
+
+gf_status gf_record_spectra(gf_ctx* c, int64_t n, double* d_records, double* h_theta) {
+    if (!c) return GF_EINVAL;
+    if (c->L.mixed || !c->rec) return fail(c, GF_ESTATE, "context was created without GF_FLAG_RECORD_SPECTRA");
+    if (n < 1 || !d_records || !h_theta) return fail(c, GF_EINVAL, "bad arguments");
+    if (n + 1 > kHist) return fail(c, GF_EINVAL, "n too large");
+    const bool was_on = c->net_on;
+    c->net_on = false;
+    gf_status s = set_tol(c, -1.0);
+    if (s == GF_OK) s = read_head(c);
+    const long long k0 = c->k_host;
+    const size_t recn = (size_t)c->L.ntuples * 2;
+    for (int64_t i = 0; i <= n && s == GF_OK; ++i) {
+        c->spec_capture = c->spec[i & 1];
+        if (i < n) {
+            s = one_iteration(c, c->k_host + i);
+        } else {  // spectrum of the last iterate only: forward (x, y) and (z, t) passes into Q
+            if (c->L.fp32) {
+                launch_xy<float, false>(c, c->D, c->Q, 1, true);
+                launch_zt<float>(c, c->Q, 1);
+            } else {
+                launch_xy<double, false>(c, c->D, c->Q, 1, true);
+                launch_zt<double>(c, c->Q, 1);
+            }
+            s = launched(c, "spectrum launch");
+        }
+        c->spec_capture = nullptr;
+        if (s == GF_OK && i >= 1) {
+            const int a = (i - 1) & 1, b = i & 1;
+            if (c->L.fp32)
+                hipLaunchKernelGGL(k_record_tuples<float>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st,
+                                   reinterpret_cast<const cx<float>*>(c->spec[a]),
+                                   reinterpret_cast<const cx<float>*>(c->spec[b]), c->L.ps, c->tg,
+                                   d_records + (size_t)(i - 1) * recn);
+            else
+                hipLaunchKernelGGL(k_record_tuples<double>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st,
+                                   reinterpret_cast<const cx<double>*>(c->spec[a]),
+                                   reinterpret_cast<const cx<double>*>(c->spec[b]), c->L.ps, c->tg,
+                                   d_records + (size_t)(i - 1) * recn);
+            s = launched(c, "record launch");
+        }
+    }
+    if (s == GF_OK) s = loop_finalize(c);
+    if (s == GF_OK) s = read_head(c);
+    if (s == GF_OK) s = unpack_links(c, c->links_user);
+    c->net_on = was_on;
+    if (s != GF_OK) return s;
+    std::vector<double> th(kHist), f(kHist);
+    GF_TRY_HIP(c, hipMemcpyAsync(th.data(), c->ctl->hist_theta, kHist * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    for (int64_t i = 0; i < n; ++i) h_theta[i] = th[(k0 + i) % kHist];
+    return GF_OK;
+}
+
+// ----------------------------------------------------------- training
+size_t gf_mlp_workspace_bytes(int64_t n_rows, int32_t n_samples) {
+    if (n_rows < 1 || n_samples < 1) return 0;
+    const size_t nb = (size_t)((n_rows + kBwdRows - 1) / kBwdRows);
+    size_t o = 0;
+    o = align_up(o + (size_t)n_rows * kMlpH * sizeof(float), kAlign);   // H1
+    o = align_up(o + (size_t)n_rows * kMlpH * sizeof(float), kAlign);   // H2
+    o = align_up(o + (size_t)n_rows * 2 * sizeof(float), kAlign);       // O
+    o = align_up(o + (size_t)n_rows * 2 * sizeof(float), kAlign);       // dO
+    o = align_up(o + nb * kMlpParams * sizeof(float), kAlign);          // block partial gradients
+    o = align_up(o + (size_t)n_samples * sizeof(double), kAlign);       // sample losses
+    return o;
+}
+
+namespace {
+struct MlpWs {
+    float *h1, *h2, *o, *dO, *gpart;
+    double* sloss;
+    int nb;
+};
+MlpWs carve_mlp(void* ws, int64_t n_rows, int32_t n_samples) {
+    MlpWs w;
+    unsigned char* b = reinterpret_cast<unsigned char*>(ws);
+    w.nb = (int)((n_rows + kBwdRows - 1) / kBwdRows);
+    size_t o = 0;
+    w.h1 = reinterpret_cast<float*>(b + o);
+    o = align_up(o + (size_t)n_rows * kMlpH * sizeof(float), kAlign);
+    w.h2 = reinterpret_cast<float*>(b + o);
+    o = align_up(o + (size_t)n_rows * kMlpH * sizeof(float), kAlign);
+    w.o = reinterpret_cast<float*>(b + o);
+    o = align_up(o + (size_t)n_rows * 2 * sizeof(float), kAlign);
+    w.dO = reinterpret_cast<float*>(b + o);
+    o = align_up(o + (size_t)n_rows * 2 * sizeof(float), kAlign);
+    w.gpart = reinterpret_cast<float*>(b + o);
+    o = align_up(o + (size_t)w.nb * kMlpParams * sizeof(float), kAlign);
+    w.sloss = reinterpret_cast<double*>(b + o);
+    (void)n_samples;
+    return w;
+}
+gf_status mlp_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return GF_OK;
+    g_init_error = std::string(what) + ": " + hipGetErrorString(e);
+    return GF_EDEVICE;
+}
+}  // namespace
+
+gf_status gf_mlp_forward(const float* d_params, const float* d_x, int64_t n_rows, float* d_out, void* d_ws,
+                         size_t ws_bytes, void* stream) {
+    if (!d_params || !d_x || !d_out || !d_ws || n_rows < 1) return GF_EINVAL;
+    if (ws_bytes < gf_mlp_workspace_bytes(n_rows, 1)) return GF_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    MlpWs w = carve_mlp(d_ws, n_rows, 1);
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, st, d_params, d_x, n_rows,
+                       w.h1, w.h2, d_out);
+    gf_status s = mlp_status(hipGetLastError(), "mlp forward");
+    if (s == GF_OK) s = mlp_status(hipStreamSynchronize(st), "sync");
+    return s;
+}
+
+gf_status gf_mlp_loss_grad(const float* d_params, const float* d_x, const float* d_tgt, const int32_t* d_offsets,
+                           int32_t n_samples, int64_t n_rows, float* d_grad, void* d_ws, size_t ws_bytes,
+                           void* stream, double* h_loss) {
+    if (!d_params || !d_x || !d_tgt || !d_offsets || !d_grad || !d_ws || n_rows < 1 || n_samples < 1)
+        return GF_EINVAL;
+    if (ws_bytes < gf_mlp_workspace_bytes(n_rows, n_samples)) return GF_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    MlpWs w = carve_mlp(d_ws, n_rows, n_samples);
+    hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, st, d_params, d_x, n_rows,
+                       w.h1, w.h2, w.o);
+    hipLaunchKernelGGL(k_mlp_loss, dim3(n_samples), dim3(256), 0, st, w.o, d_tgt, d_offsets, n_samples, w.dO, w.sloss);
+    hipLaunchKernelGGL(k_mlp_backward, dim3(w.nb), dim3(256), 0, st, d_params, d_x, w.h1, w.h2, w.dO, n_rows, w.gpart);
+    hipLaunchKernelGGL(k_grad_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, w.gpart, w.nb, d_grad);
+    gf_status s = mlp_status(hipGetLastError(), "mlp loss/gradient");
+    if (s == GF_OK && h_loss) {
+        std::vector<double> sl(n_samples);
+        s = mlp_status(hipMemcpyAsync(sl.data(), w.sloss, n_samples * sizeof(double), hipMemcpyDeviceToHost, st),
+                       "loss readback");
+        if (s == GF_OK) s = mlp_status(hipStreamSynchronize(st), "sync");
+        double t = 0.0;
+        for (double v : sl) t += v;
+        *h_loss = t / n_samples;
+    }
+    return s;
+}
+
+gf_status gf_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t step, float lr,
+                      void* stream) {
+    if (!d_params || !d_m || !d_v || !d_grad || step < 1 || !(lr > 0.f)) return GF_EINVAL;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)step)), c2 = (float)(1.0 - std::pow(0.999, (double)step));
+    hipLaunchKernelGGL(k_adam, dim3((kMlpParams + 255) / 256), dim3(256), 0, reinterpret_cast<hipStream_t>(stream),
+                       d_params, d_m, d_v, d_grad, lr, b1, b2, 1e-8f, c1, c2);
+    return mlp_status(hipGetLastError(), "adam");
+}
+
+gf_status gf_mlp_train_step(float* d_params, float* d_m, float* d_v, int64_t step, float lr, const float* d_x,
+                            const float* d_tgt, const int32_t* d_offsets, int32_t n_samples, int64_t n_rows,
+                            float* d_grad, void* d_ws, size_t ws_bytes, void* stream, double* h_loss) {
+    gf_status s = gf_mlp_loss_grad(d_params, d_x, d_tgt, d_offsets, n_samples, n_rows, d_grad, d_ws, ws_bytes, stream,
+                                   h_loss);
+    if (s != GF_OK) return s;
+    return gf_mlp_adam(d_params, d_m, d_v, d_grad, step, lr, stream);
+}
+
+int32_t gf_mlp_param_count(void) { return kMlpParams; }
+
+gf_status gf_mlp_make_samples(const double* d_records, const double* d_theta, const int32_t* d_k, int32_t n_samples,
+                              const int32_t* dims, double alpha, float* d_x, float* d_tgt, void* stream) {
+    if (!d_records || !d_theta || !d_k || !dims || !d_x || !d_tgt || n_samples < 1 || !(alpha > 0.0))
+        return GF_EINVAL;
+    TupleGeom tg;
+    tg.count = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (dims[d] < 2 || dims[d] % 2) return GF_EINVAL;
+        tg.n[d] = dims[d];
+        tg.h[d] = dims[d] / 2 + 1;
+        tg.count *= tg.h[d];
+    }
+    const int64_t nrows = (int64_t)n_samples * tg.count;
+    hipLaunchKernelGGL(k_make_samples, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), d_records, d_theta, d_k, nrows, tg, 0.5 * alpha * 16.0,
+                       d_x, d_tgt);
+    return mlp_status(hipGetLastError(), "make samples");
+}
+
+void gf_destroy(gf_ctx* c) { free_ctx(c); }
 
 }  // extern "C"

@@ -55,7 +55,8 @@ template <typename T, int NZ, int NTT, int BX>
 __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     k_fft_zt_ct(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, const cx<T>* __restrict__ twgz,
                 const cx<T>* __restrict__ twgt, const T* __restrict__ sin2, T coef, int no_fa,
-                const Ctl* __restrict__ ctl, int force) {
+                const Ctl* __restrict__ ctl, int force, const T* __restrict__ mtab, TupleGeom tg,
+                cx<T>* __restrict__ spec) {
     constexpr int TSP = NZ * BX + 1, E = BX * NZ * NTT, NT = ct_threads(E, 8);
     if (!force && ctl->done) return;
     __shared__ cx<T> twz[NZ], twt[NTT], buf[NTT * TSP];
@@ -91,9 +92,15 @@ __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
         if (E % NT == 0 || e < E) {
             const int xo = e % BX, zt = e / BX;
             const int z = zt % NZ, t = zt / NZ;
-            const T p2 = sx[x0 + xo] + sxy + sz[z] + st[t];
-            const T mult = p2 > T(0) ? (no_fa ? coef : coef / p2) : T(0);
             const int li = t * TSP + z * BX + xo;
+            if (spec) spec[xo + zt * pstep + (gp - Z)] = buf[li];
+            T mult;
+            if (mtab) {
+                mult = mtab[tuple_index(tg, x0 + xo, y, z, t)];
+            } else {
+                const T p2 = sx[x0 + xo] + sxy + sz[z] + st[t];
+                mult = p2 > T(0) ? (no_fa ? coef : coef / p2) : T(0);
+            }
             buf[li] = cscale(buf[li], mult);
         }
     }

@@ -20,6 +20,7 @@
 
 #include "gf_device.hpp"
 #include "gf_fft.hpp"
+#include "gf_learn.hpp"
 
 namespace gf {
 
@@ -208,6 +209,16 @@ __global__ void __launch_bounds__(256) k_finalize(const double2* __restrict__ pa
     reduce_partials(part, n, inv3v, inv12v, ctl, mode);
 }
 
+// Forget a rejected update: the count goes back to k (the links of step k are
+// still in their buffer; the caller re-measures them).
+__global__ void k_rollback(Ctl* ctl, long long k) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->iters = k;
+        ctl->done = 0;
+        ctl->pending = 0;
+    }
+}
+
 __global__ void k_set_tol(Ctl* ctl, double tol) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         ctl->tol = tol;
@@ -343,11 +354,13 @@ __device__ __forceinline__ double xor_sum4(double v) {
 constexpr int kFusedThreads = 256;
 constexpr int kFusedSites = kFusedThreads / 4;
 
+// With acc_g set (six planes, ps apart) the lane of direction 0 also
+// accumulates the total gauge transform in place: A(x) <- reunitarize(g(x) A(x)).
 template <typename T, int NE>
 __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> Lin, Links<T, NE> Lout,
                                                                   const cx<T>* __restrict__ G, cx<T>* __restrict__ D,
                                                                   size_t ps, Geom g, double2* __restrict__ part,
-                                                                  Ctl* ctl) {
+                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g) {
     if (ctl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
@@ -397,6 +410,13 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
         fsum = (double)un.e[0][0].re + (double)un.e[1][1].re + (double)un.e[2][2].re;
         acc.add(un, T(-1));
         acc.add(mul_adj<T, 3>(mul(gb, ub), g0), T(1));  // U'_mu(x - mu)
+        if (acc_g != nullptr && mu == 0) {
+            su3<T> a = g_rows_at(acc_g, ps, s);
+            a = mul_rows<T, 2>(g0, a);
+            reunitarize(a);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc_g[(size_t)k * ps + s] = a.e[k / 3][k % 3];
+        }
     }
     acc.o01.re = xor_sum4(acc.o01.re);
     acc.o01.im = xor_sum4(acc.o01.im);
@@ -423,6 +443,51 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
     if (threadIdx.x == 0) {
         part[b] = make_double2(fsum, tsum);
         if (b == 0) ctl->pending = 1;
+    }
+}
+
+// ------------------------------------------------ mixed-precision hand-over
+// Rows 1-2 of the identity in the six planes of an accumulated gauge transform.
+template <typename T>
+__global__ void __launch_bounds__(kSiteThreads) k_gauge_identity(cx<T>* __restrict__ A, size_t ps, int64_t vol) {
+    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
+    if (s >= vol) return;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) A[(size_t)k * ps + s] = {(k == 0 || k == 4) ? T(1) : T(0), T(0)};
+}
+
+// U_mu(x) <- G(x) U_mu(x) G(x+mu)^dag in place on double links, G taken from
+// the float accumulated transform, promoted to double and re-orthonormalised
+// (the same computation at x and at every x - mu, so neighbours agree). The
+// double G is also stored (rows 1-2) in Aout, where accumulation continues.
+template <int NE>
+__global__ void __launch_bounds__(kSiteThreads) k_apply_accumulated(Links<double, NE> L,
+                                                                    const cx<float>* __restrict__ A, size_t aps,
+                                                                    cx<double>* __restrict__ Aout, size_t ops,
+                                                                    Geom g) {
+    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
+    if (s >= g.vol) return;
+    auto load_g = [&](int64_t site) {
+        su3<double> m;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const cx<float> e = A[(size_t)k * aps + site];
+            m.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
+        }
+        reunitarize(m);
+        return m;
+    };
+    int c[4];
+    site_coords(g, s, c);
+    const su3<double> g0 = load_g(s);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Aout[(size_t)k * ops + s] = g0.e[k / 3][k % 3];
+    constexpr int NR = NE == 9 ? 3 : 2;
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        const su3<double> g1 = load_g(site_fwd(g, s, c, mu));
+        const su3<double> u = L.load(mu, s);
+        L.store(mu, s, mul_adj<double, NR>(mul_rows<double, NR>(g0, u), g1));
     }
 }
 
@@ -478,7 +543,8 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
                                                  int bx, int tsp, FftPlan pz, FftPlan pt,
                                                  const cx<T>* __restrict__ twgz, const cx<T>* __restrict__ twgt,
                                                  const T* __restrict__ sin2, T coef, int no_fa,
-                                                 const Ctl* __restrict__ ctl, int force) {
+                                                 const Ctl* __restrict__ ctl, int force, const T* __restrict__ mtab,
+                                                 TupleGeom tg, cx<T>* __restrict__ spec) {
     if (!force && ctl->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* twz = reinterpret_cast<cx<T>*>(smem);
@@ -511,9 +577,15 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
     for (int e = threadIdx.x; e < E; e += nthr) {
         const int xo = e % bx, zt = e / bx;
         const int z = zt % nz, t = zt / nz;
-        const T p2 = sx[x0 + xo] + sy[y] + sz[z] + st[t];
-        const T mult = p2 > T(0) ? (no_fa ? coef : coef / p2) : T(0);
         const int li = t * tsp + z * bx + xo;
+        if (spec) spec[xo + zt * pstep + (gp - Z)] = buf[li];
+        T mult;
+        if (mtab) {
+            mult = mtab[tuple_index(tg, x0 + xo, y, z, t)];
+        } else {
+            const T p2 = sx[x0 + xo] + sy[y] + sz[z] + st[t];
+            mult = p2 > T(0) ? (no_fa ? coef : coef / p2) : T(0);
+        }
         buf[li] = cscale(buf[li], mult);
     }
     __syncthreads();

@@ -1,0 +1,369 @@
+// Learned spectral preconditioner: recording, inference table and training.
+//
+// The fixed Fourier-acceleration multiplier m0(p) = (alpha/2) p2max / p^2(p)
+// (divided by V for the unnormalised transforms) is replaced by
+//     m(p) = m0(p) * exp(o_s(p) + o_a(0)),
+// where (o_s, o_a) are the outputs of a 6 -> 64 -> 64 -> 2 tanh network on the
+// features of each distinct momentum tuple n_mu in [0, N_mu/2] (p^2 is even
+// in every n_mu): x = (p^2_mu/4 - 1/2 for mu = 0..3, log10(theta_k)/8 + 1,
+// k/64). o_a at the zero tuple sets a global step; all-zero outputs give the
+// fixed multiplier exactly. Parameters (float): W1 (64x6), b1, W2 (64x64), b2,
+// W3 (2x64), b3.
+//
+// Training signal, recorded on plain-FA trajectories: per tuple,
+// P_k = sum over the +-n reflections and the four packed fields of |Z(p)|^2
+// after the forward FFT, and C_k = the same sum of Re[Z_{k+1}(p) conj(Z_k(p))].
+// Loss of one sample: sum_p P (1 - m kappa)^2 / sum_p P with
+// kappa = (1 - C/P)/m0, the observed response of each mode.
+#pragma once
+
+#include "gf_device.hpp"
+
+namespace gf {
+
+constexpr int kMlpIn = 6, kMlpH = 64, kMlpOut = 2;
+constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
+constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH,
+              kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpOut * kMlpH;
+
+// Folded tuple index (first axis fastest) of the mode n of a lattice.
+__device__ __forceinline__ int fold1(int n, int N) { return n <= N / 2 ? n : N - n; }
+
+struct TupleGeom {
+    int n[4];   // lattice extents
+    int h[4];   // N_mu/2 + 1
+    int count;  // number of tuples
+};
+
+__device__ __forceinline__ int tuple_index(const TupleGeom& tg, int nx, int ny, int nz, int nt) {
+    return fold1(nx, tg.n[0]) + tg.h[0] * (fold1(ny, tg.n[1]) + tg.h[1] * (fold1(nz, tg.n[2]) + tg.h[2] * fold1(nt, tg.n[3])));
+}
+
+// -------------------------------------------------------------- recording
+// Per tuple: P from spectrum Sk and C from Sk, Sk1 (both full 4D spectra of
+// the four packed fields, planes ps apart), summed over the tuple's +-n
+// reflections; out[2*i] = P, out[2*i+1] = C (double).
+template <typename T>
+__global__ void __launch_bounds__(256) k_record_tuples(const cx<T>* __restrict__ Sk, const cx<T>* __restrict__ Sk1,
+                                                       size_t ps, TupleGeom tg, double* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= tg.count) return;
+    int t[4], r = i;
+    for (int m = 0; m < 4; ++m) {
+        t[m] = r % tg.h[m];
+        r /= tg.h[m];
+    }
+    double P = 0.0, C = 0.0;
+    for (int a = 0; a < 16; ++a) {
+        int q[4];
+        bool dup = false;
+        for (int m = 0; m < 4; ++m) {
+            const int flip = (a >> m) & 1;
+            q[m] = flip ? (tg.n[m] - t[m]) % tg.n[m] : t[m];
+            if (flip && q[m] == t[m]) dup = true;  // the reflection is the mode itself
+        }
+        if (dup) continue;
+        const size_t s = (size_t)q[0] + (size_t)tg.n[0] * (q[1] + (size_t)tg.n[1] * (q[2] + (size_t)tg.n[2] * q[3]));
+        for (int f = 0; f < 4; ++f) {
+            const cx<T> z0 = Sk[(size_t)f * ps + s], z1 = Sk1[(size_t)f * ps + s];
+            P += (double)z0.re * z0.re + (double)z0.im * z0.im;
+            C += (double)z1.re * z0.re + (double)z1.im * z0.im;
+        }
+    }
+    out[2 * i] = P;
+    out[2 * i + 1] = C;
+}
+
+// ------------------------------------------------------------ inference
+__device__ __forceinline__ void mlp_features(const float* sin2_4, float log10_theta, float k, float x[kMlpIn]) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[m] = sin2_4[m] * 0.25f - 0.5f;
+    x[4] = log10_theta * 0.125f + 1.0f;
+    x[5] = k * (1.0f / 64.0f);
+}
+
+// One row through the network with weights in LDS; returns both outputs.
+__device__ __forceinline__ void mlp_row(const float* __restrict__ w, const float x[kMlpIn], float& o0, float& o1) {
+    float h1[kMlpH];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) {
+        float a = w[kOffB1 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) a = fmaf(w[kOffW1 + j * kMlpIn + i], x[i], a);
+        h1[j] = tanhf(a);
+    }
+    float a0 = w[kOffB3], a1 = w[kOffB3 + 1];
+    for (int j = 0; j < kMlpH; ++j) {
+        float a = w[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpH; ++i) a = fmaf(w[kOffW2 + j * kMlpH + i], h1[i], a);
+        const float h2 = tanhf(a);
+        a0 = fmaf(w[kOffW3 + j], h2, a0);
+        a1 = fmaf(w[kOffW3 + kMlpH + j], h2, a1);
+    }
+    o0 = a0;
+    o1 = a1;
+}
+
+// Multiplier table for the current iteration: mtab[i] = coef / p^2 *
+// exp(o_s(i) + o_a(0)) (coef = (alpha/2) p2max / V), 0 at the zero tuple.
+// theta and the iteration count come from the control block.
+template <typename T>
+__global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ params, const T* __restrict__ sin2,
+                                                   TupleGeom tg, double coef, const Ctl* __restrict__ ctl,
+                                                   T* __restrict__ mtab) {
+    if (ctl->done) return;
+    __shared__ float w[kMlpParams];
+    for (int i = threadIdx.x; i < kMlpParams; i += 256) w[i] = params[i];
+    __syncthreads();
+    const float lt = (float)log10(fmax(ctl->theta, 1e-300));
+    const float kk = (float)ctl->iters;
+    // global log step: second output at the zero tuple (every block computes the same value)
+    __shared__ float oa_s;
+    if (threadIdx.x == 0 && blockIdx.x != 0) {
+        float zx[kMlpIn], zs[4] = {0.f, 0.f, 0.f, 0.f}, o0, o1;
+        mlp_features(zs, lt, kk, zx);
+        mlp_row(w, zx, o0, o1);
+        oa_s = o1;
+    }
+    __syncthreads();
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    int t[4], r = i < tg.count ? i : 0;
+    for (int m = 0; m < 4; ++m) {
+        t[m] = r % tg.h[m];
+        r /= tg.h[m];
+    }
+    const T* sx = sin2;
+    const T* sy = sx + tg.n[0];
+    const T* sz = sy + tg.n[1];
+    const T* st = sz + tg.n[2];
+    float s4[4] = {(float)sx[t[0]], (float)sy[t[1]], (float)sz[t[2]], (float)st[t[3]]};
+    const double p2 = (double)sx[t[0]] + (double)sy[t[1]] + (double)sz[t[2]] + (double)st[t[3]];
+    float x[kMlpIn], o0 = 0.f, o1 = 0.f;
+    if (i < tg.count) {
+        mlp_features(s4, lt, kk, x);
+        mlp_row(w, x, o0, o1);
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) oa_s = o1;  // row 0 is the zero tuple
+    __syncthreads();
+    if (i < tg.count) mtab[i] = p2 > 0.0 ? (T)(coef / p2 * exp((double)o0 + (double)oa_s)) : T(0);
+}
+
+// --------------------------------------------------------------- training
+// Samples from records: row r = s*T + i (sample s, tuple i) gets the features
+// of tuple i at (theta[s], kidx[s]) and the target (m0, P, kappa) with
+// m0 = (alpha/2) p2max / p^2 (0 at the zero tuple) and kappa = (1 - C/P)/m0
+// clipped to [1e-3, 1e3] (1 where P or m0 vanishes).
+__global__ void __launch_bounds__(256) k_make_samples(const double* __restrict__ rec, const double* __restrict__ theta,
+                                                      const int* __restrict__ kidx, int64_t nrows, TupleGeom tg,
+                                                      double half_alpha_p2max, float* __restrict__ X,
+                                                      float* __restrict__ tgt) {
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= nrows) return;
+    const int s = (int)(row / tg.count), i = (int)(row % tg.count);
+    int t[4], r = i;
+    for (int m = 0; m < 4; ++m) {
+        t[m] = r % tg.h[m];
+        r /= tg.h[m];
+    }
+    float s4[4];
+    double p2 = 0.0;
+    for (int m = 0; m < 4; ++m) {
+        const double sv = sinpi((double)t[m] / (double)tg.n[m]);
+        const double c = 4.0 * sv * sv;
+        s4[m] = (float)c;
+        p2 += c;
+    }
+    float x[kMlpIn];
+    mlp_features(s4, (float)log10(fmax(theta[s], 1e-300)), (float)kidx[s], x);
+#pragma unroll
+    for (int q = 0; q < kMlpIn; ++q) X[row * kMlpIn + q] = x[q];
+    const double P = rec[2 * row], C = rec[2 * row + 1];
+    const double m0 = p2 > 0.0 ? half_alpha_p2max / p2 : 0.0;
+    double kap = 1.0;
+    if (P > 0.0 && m0 > 0.0) {
+        kap = (1.0 - C / P) / m0;
+        if (!isfinite(kap)) kap = 1.0;
+        kap = fmin(fmax(kap, 1e-3), 1e3);
+    }
+    tgt[row * 3] = (float)m0;
+    tgt[row * 3 + 1] = (float)P;
+    tgt[row * 3 + 2] = (float)kap;
+}
+
+// Rows are momentum tuples of samples; sample s owns rows [off[s], off[s+1]),
+// its first row being the zero tuple. tgt row = (m0, P, kappa).
+
+// Forward pass keeping the activations: H1, H2 (n x 64), O (n x 2).
+__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ params, const float* __restrict__ X,
+                                                     int64_t n, float* __restrict__ H1, float* __restrict__ H2,
+                                                     float* __restrict__ O) {
+    __shared__ float w[kMlpParams];
+    for (int i = threadIdx.x; i < kMlpParams; i += 256) w[i] = params[i];
+    __syncthreads();
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= n) return;
+    float x[kMlpIn];
+#pragma unroll
+    for (int i = 0; i < kMlpIn; ++i) x[i] = X[row * kMlpIn + i];
+    float h1[kMlpH];
+#pragma unroll
+    for (int j = 0; j < kMlpH; ++j) {
+        float a = w[kOffB1 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) a = fmaf(w[kOffW1 + j * kMlpIn + i], x[i], a);
+        h1[j] = tanhf(a);
+        H1[row * kMlpH + j] = h1[j];
+    }
+    float a0 = w[kOffB3], a1 = w[kOffB3 + 1];
+    for (int j = 0; j < kMlpH; ++j) {
+        float a = w[kOffB2 + j];
+#pragma unroll
+        for (int i = 0; i < kMlpH; ++i) a = fmaf(w[kOffW2 + j * kMlpH + i], h1[i], a);
+        const float h2 = tanhf(a);
+        H2[row * kMlpH + j] = h2;
+        a0 = fmaf(w[kOffW3 + j], h2, a0);
+        a1 = fmaf(w[kOffW3 + kMlpH + j], h2, a1);
+    }
+    O[row * 2] = a0;
+    O[row * 2 + 1] = a1;
+}
+
+// One block per sample: loss (double) and dL/dO for the sample's rows, the
+// mean over ns samples. dO is written for every row (o_a only at row 0).
+__global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ O, const float* __restrict__ tgt,
+                                                  const int* __restrict__ off, int ns, float* __restrict__ dO,
+                                                  double* __restrict__ sample_loss) {
+    const int s = blockIdx.x;
+    const int r0 = off[s], r1 = off[s + 1];
+    const double oa = O[(int64_t)r0 * 2 + 1];
+    __shared__ double red[4][256 / 64];
+    double psum = 0.0, lsum = 0.0;
+    for (int r = r0 + threadIdx.x; r < r1; r += 256) {
+        const double m0 = tgt[(int64_t)r * 3], P = tgt[(int64_t)r * 3 + 1], kap = tgt[(int64_t)r * 3 + 2];
+        const double m = m0 * exp((double)O[(int64_t)r * 2] + oa);
+        const double res = 1.0 - m * kap;
+        psum += P;
+        lsum += P * res * res;
+    }
+    // block sums of P and of P r^2
+    psum = wave_sum(psum);
+    lsum = wave_sum(lsum);
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) {
+        red[0][wv] = psum;
+        red[1][wv] = lsum;
+    }
+    __syncthreads();
+    double Ptot = 0.0, Ltot = 0.0;
+    for (int i = 0; i < 256 / 64; ++i) {
+        Ptot += red[0][i];
+        Ltot += red[1][i];
+    }
+    // dL/dm = -2 P r kappa / (Ptot ns); do_s = dL/dm * m; do_a(row 0) = sum over rows
+    double gsum = 0.0;
+    for (int r = r0 + threadIdx.x; r < r1; r += 256) {
+        const double m0 = tgt[(int64_t)r * 3], P = tgt[(int64_t)r * 3 + 1], kap = tgt[(int64_t)r * 3 + 2];
+        const double m = m0 * exp((double)O[(int64_t)r * 2] + oa);
+        const double g = -2.0 * P * (1.0 - m * kap) * kap / (Ptot * ns) * m;
+        dO[(int64_t)r * 2] = (float)g;
+        dO[(int64_t)r * 2 + 1] = 0.0f;
+        gsum += g;
+    }
+    gsum = wave_sum(gsum);
+    __syncthreads();
+    if (l == 0) red[2][wv] = gsum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < 256 / 64; ++i) t += red[2][i];
+        dO[(int64_t)r0 * 2 + 1] = (float)t;
+        sample_loss[s] = Ltot / Ptot;
+    }
+}
+
+// Backward pass: each block takes kBwdRows consecutive rows and writes its
+// partial gradient (kMlpParams floats, summed in double then rounded) to
+// gpart[block]; k_grad_reduce adds the block partials in a fixed order.
+constexpr int kBwdRows = 256;
+
+__global__ void __launch_bounds__(256) k_mlp_backward(const float* __restrict__ params, const float* __restrict__ X,
+                                                      const float* __restrict__ H1, const float* __restrict__ H2,
+                                                      const float* __restrict__ dO, int64_t n,
+                                                      float* __restrict__ gpart) {
+    __shared__ float w2[kMlpH * kMlpH];
+    __shared__ float w3[kMlpOut * kMlpH];
+    __shared__ float dz2s[kBwdRows][kMlpH + 1];
+    __shared__ float dz1s[kBwdRows][kMlpH + 1];
+    for (int i = threadIdx.x; i < kMlpH * kMlpH; i += 256) w2[i] = params[kOffW2 + i];
+    for (int i = threadIdx.x; i < kMlpOut * kMlpH; i += 256) w3[i] = params[kOffW3 + i];
+    __syncthreads();
+    const int64_t row0 = (int64_t)blockIdx.x * kBwdRows;
+    // per row: dz2 = (dO W3) (1 - h2^2), dz1 = (dz2 W2) (1 - h1^2)
+    {
+        const int64_t row = row0 + threadIdx.x;
+        const bool ok = row < n;
+        const float d0 = ok ? dO[row * 2] : 0.f, d1 = ok ? dO[row * 2 + 1] : 0.f;
+        for (int j = 0; j < kMlpH; ++j) {
+            const float h2 = ok ? H2[row * kMlpH + j] : 0.f;
+            dz2s[threadIdx.x][j] = (d0 * w3[j] + d1 * w3[kMlpH + j]) * (1.f - h2 * h2);
+        }
+        for (int i = 0; i < kMlpH; ++i) {
+            float a = 0.f;
+            for (int j = 0; j < kMlpH; ++j) a = fmaf(dz2s[threadIdx.x][j], w2[j * kMlpH + i], a);
+            const float h1 = ok ? H1[row * kMlpH + i] : 0.f;
+            dz1s[threadIdx.x][i] = a * (1.f - h1 * h1);
+        }
+    }
+    __syncthreads();
+    const int nr = (int)min<int64_t>(kBwdRows, n - row0);
+    float* gp = gpart + (size_t)blockIdx.x * kMlpParams;
+    // every thread owns some parameter entries and sums over the block's rows in order
+    for (int p = threadIdx.x; p < kMlpParams; p += 256) {
+        double acc = 0.0;
+        if (p < kOffB1) {  // W1[j][i] += dz1[j] x[i]
+            const int j = p / kMlpIn, i = p % kMlpIn;
+            for (int r = 0; r < nr; ++r) acc += (double)dz1s[r][j] * X[(row0 + r) * kMlpIn + i];
+        } else if (p < kOffW2) {
+            const int j = p - kOffB1;
+            for (int r = 0; r < nr; ++r) acc += dz1s[r][j];
+        } else if (p < kOffB2) {  // W2[j][i] += dz2[j] h1[i]
+            const int q = p - kOffW2, j = q / kMlpH, i = q % kMlpH;
+            for (int r = 0; r < nr; ++r) acc += (double)dz2s[r][j] * H1[(row0 + r) * kMlpH + i];
+        } else if (p < kOffW3) {
+            const int j = p - kOffB2;
+            for (int r = 0; r < nr; ++r) acc += dz2s[r][j];
+        } else if (p < kOffB3) {  // W3[o][j] += dO[o] h2[j]
+            const int q = p - kOffW3, o = q / kMlpH, j = q % kMlpH;
+            for (int r = 0; r < nr; ++r) acc += (double)dO[(row0 + r) * 2 + o] * H2[(row0 + r) * kMlpH + j];
+        } else {
+            const int o = p - kOffB3;
+            for (int r = 0; r < nr; ++r) acc += dO[(row0 + r) * 2 + o];
+        }
+        gp[p] = (float)acc;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_grad_reduce(const float* __restrict__ gpart, int nb, float* __restrict__ grad) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kMlpParams) return;
+    double a = 0.0;
+    for (int b = 0; b < nb; ++b) a += gpart[(size_t)b * kMlpParams + p];
+    grad[p] = (float)a;
+}
+
+// Adam (Kingma and Ba 2015), step counted from 1.
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ params, float* __restrict__ m, float* __restrict__ v,
+                                              const float* __restrict__ grad, float lr, float b1, float b2, float eps,
+                                              float c1, float c2) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kMlpParams) return;
+    const float g = grad[p];
+    const float mm = b1 * m[p] + (1.f - b1) * g;
+    const float vv = b2 * v[p] + (1.f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    params[p] -= lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+}
+
+}  // namespace gf

@@ -24,6 +24,9 @@ PRECISIONS = {"fp64_18": 0, "fp64_12": 1, "fp32_12": 2, "fp32_18": 3, "mixed": 4
 FLAG_EXACT_EXP = 1 << 0
 FLAG_NO_FA = 1 << 1
 FLAG_GENERIC_FFT = 1 << 2
+FLAG_ACCUMULATE_GAUGE = 1 << 3
+FLAG_LEARNED = 1 << 4
+FLAG_RECORD_SPECTRA = 1 << 5
 
 
 class gf_params(ctypes.Structure):
@@ -57,6 +60,7 @@ def _signatures(lib):
         "gf_fix_until": (i32, [_P, dbl, i64, pr]),
         "gf_quality": (i32, [_P, pd, pd]),
         "gf_get_links": (i32, [_P, _P]),
+        "gf_get_gauge": (i32, [_P, _P]),
         "gf_history": (i32, [_P, i64, pd, pd]),
         "gf_stage_divergence": (i32, [_P, _P]),
         "gf_stage_filter": (i32, [_P, _P, _P]),
@@ -64,6 +68,15 @@ def _signatures(lib):
         "gf_stage_update": (i32, [_P, _P]),
         "gf_set_timing": (i32, [_P, i32]),
         "gf_kernel_times": (i32, [_P, i32, pd, ctypes.POINTER(ctypes.c_int64)]),
+        "gf_mlp_param_count": (i32, []),
+        "gf_mlp_set_weights": (i32, [_P, _P, i32]),
+        "gf_record_spectra": (i32, [_P, i64, _P, pd]),
+        "gf_mlp_workspace_bytes": (sz, [i64, i32]),
+        "gf_mlp_make_samples": (i32, [_P, _P, _P, i32, ctypes.POINTER(i32), dbl, _P, _P, _P]),
+        "gf_mlp_forward": (i32, [_P, _P, i64, _P, _P, sz, _P]),
+        "gf_mlp_loss_grad": (i32, [_P, _P, _P, _P, i32, i64, _P, _P, sz, _P, pd]),
+        "gf_mlp_adam": (i32, [_P, _P, _P, _P, i64, ctypes.c_float, _P]),
+        "gf_mlp_train_step": (i32, [_P, _P, _P, i64, ctypes.c_float, _P, _P, _P, i32, i64, _P, _P, sz, _P, pd]),
         "gf_last_error": (ctypes.c_char_p, [_P]),
         "gf_destroy": (None, [_P]),
     }
@@ -154,6 +167,10 @@ def gf_get_links(ctx, d_out):
     _check(ctx, load().gf_get_links(ctx, _P(d_out)))
 
 
+def gf_get_gauge(ctx, d_out):
+    _check(ctx, load().gf_get_gauge(ctx, _P(d_out)))
+
+
 def gf_history(ctx, n):
     import numpy as np
     th = np.zeros(n)
@@ -193,6 +210,64 @@ def gf_kernel_times(ctx):
     cnt = (ctypes.c_int64 * NKERNELS)()
     _check(ctx, load().gf_kernel_times(ctx, NKERNELS, ms, cnt))
     return {KERNEL_NAMES[i]: (ms[i], cnt[i]) for i in range(len(KERNEL_NAMES))}
+
+
+def gf_mlp_param_count():
+    return load().gf_mlp_param_count()
+
+
+def gf_mlp_set_weights(ctx, d_params, enable=True):
+    _check(ctx, load().gf_mlp_set_weights(ctx, _P(d_params), 1 if enable else 0))
+
+
+def gf_record_spectra(ctx, n, d_records):
+    """Run n plain FA updates recording per-tuple (P_k, C_k) into d_records; returns theta_k (numpy)."""
+    import numpy as np
+    th = np.zeros(n)
+    _check(ctx, load().gf_record_spectra(ctx, int(n), _P(d_records), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return th
+
+
+def _mlp_check(st, what):
+    if st != GF_OK:
+        raise GfError(st, f"{what}: {gf_last_error(None)}")
+
+
+def gf_mlp_workspace_bytes(n_rows, n_samples):
+    return load().gf_mlp_workspace_bytes(int(n_rows), int(n_samples))
+
+
+def gf_mlp_make_samples(d_records, d_theta, d_k, n_samples, dims, alpha, d_x, d_tgt, stream=0):
+    arr = (ctypes.c_int32 * 4)(*[int(d) for d in dims])
+    _mlp_check(load().gf_mlp_make_samples(_P(d_records), _P(d_theta), _P(d_k), int(n_samples), arr, float(alpha),
+                                          _P(d_x), _P(d_tgt), _P(stream)), "gf_mlp_make_samples")
+
+
+def gf_mlp_forward(d_params, d_x, n_rows, d_out, d_ws, ws_bytes, stream=0):
+    _mlp_check(load().gf_mlp_forward(_P(d_params), _P(d_x), int(n_rows), _P(d_out), _P(d_ws), ws_bytes, _P(stream)),
+               "gf_mlp_forward")
+
+
+def gf_mlp_loss_grad(d_params, d_x, d_tgt, d_off, n_samples, n_rows, d_grad, d_ws, ws_bytes, stream=0):
+    loss = ctypes.c_double()
+    _mlp_check(load().gf_mlp_loss_grad(_P(d_params), _P(d_x), _P(d_tgt), _P(d_off), int(n_samples), int(n_rows),
+                                       _P(d_grad), _P(d_ws), ws_bytes, _P(stream), ctypes.byref(loss)),
+               "gf_mlp_loss_grad")
+    return loss.value
+
+
+def gf_mlp_adam(d_params, d_m, d_v, d_grad, step, lr, stream=0):
+    _mlp_check(load().gf_mlp_adam(_P(d_params), _P(d_m), _P(d_v), _P(d_grad), int(step), float(lr), _P(stream)),
+               "gf_mlp_adam")
+
+
+def gf_mlp_train_step(d_params, d_m, d_v, step, lr, d_x, d_tgt, d_off, n_samples, n_rows, d_grad, d_ws, ws_bytes,
+                      stream=0):
+    loss = ctypes.c_double()
+    _mlp_check(load().gf_mlp_train_step(_P(d_params), _P(d_m), _P(d_v), int(step), float(lr), _P(d_x), _P(d_tgt),
+                                        _P(d_off), int(n_samples), int(n_rows), _P(d_grad), _P(d_ws), ws_bytes,
+                                        _P(stream), ctypes.byref(loss)), "gf_mlp_train_step")
+    return loss.value
 
 
 def gf_destroy(ctx):
@@ -264,6 +339,28 @@ class GaugeFixer:
         if out is None:
             out = torch.empty_like(self.links)
         gf_get_links(self.ctx, out.data_ptr())
+        return out
+
+    def set_weights(self, params, enable=True):
+        """Switch the learned preconditioner on with a float32 CUDA tensor of gf_mlp_param_count() parameters."""
+        self._mlp = params.contiguous()
+        gf_mlp_set_weights(self.ctx, self._mlp.data_ptr(), enable)
+
+    def record(self, n):
+        """n plain FA updates; returns (records tensor (n, tuples, 2) float64, theta_k numpy)."""
+        import torch
+        nt, nz, ny, nx = self.links.shape[:4]
+        ntup = (nx // 2 + 1) * (ny // 2 + 1) * (nz // 2 + 1) * (nt // 2 + 1)
+        rec = torch.empty((n, ntup, 2), dtype=torch.float64, device=self.links.device)
+        th = gf_record_spectra(self.ctx, n, rec.data_ptr())
+        return rec, th
+
+    def get_gauge(self, out=None):
+        """The accumulated transform G(x) as a complex128 tensor (Nt, Nz, Ny, Nx, 3, 3)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.links.shape[:4] + (3, 3), dtype=torch.complex128, device=self.links.device)
+        gf_get_gauge(self.ctx, out.data_ptr())
         return out
 
     def close(self):

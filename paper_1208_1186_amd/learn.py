@@ -1,0 +1,115 @@
+"""Driver for the learned spectral preconditioner: record, train, evaluate.
+
+Every numerical step runs in libgf (recording of per-mode spectra during
+plain Fourier-accelerated steepest descent, assembly of training rows, the
+network's forward/backward/Adam kernels, and the learned iterations with
+their plain-FA fallback). This module only moves device buffers around and
+schedules the calls.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import gf, synth
+
+
+def init_params(seed=0):
+    """Glorot-uniform hidden layers and a zero output layer (the network starts as plain FA), float32 numpy."""
+    rng = np.random.default_rng(seed)
+    h, nin = 64, 6
+    w1 = rng.uniform(-1, 1, (h, nin)) * np.sqrt(6.0 / (nin + h))
+    w2 = rng.uniform(-1, 1, (h, h)) * np.sqrt(6.0 / (2 * h))
+    parts = [w1, np.zeros(h), w2, np.zeros(h), np.zeros((2, h)), np.zeros(2)]
+    out = np.concatenate([p.ravel() for p in parts]).astype(np.float32)
+    assert out.size == gf.gf_mlp_param_count()
+    return out
+
+
+def n_tuples(dims):
+    return int(np.prod([d // 2 + 1 for d in dims]))
+
+
+def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=0.08, device="cuda:0",
+            every=1, log=None):
+    """Record plain-FA trajectories of the given seeds; returns (X, TGT, n_samples) as CUDA tensors."""
+    import torch
+    T = n_tuples(dims)
+    xs, ts = [], []
+    for seed in seeds:
+        u = synth.make_config(dims, seed, eps)
+        links = torch.from_numpy(u).to(device)
+        fx = gf.GaugeFixer(links, precision, alpha=alpha, flags=gf.FLAG_RECORD_SPECTRA)
+        rec, theta = fx.record(n_iter)
+        keep = np.arange(0, n_iter, every)
+        keep = keep[theta[keep] > 1e-13]  # below this the float spectra are rounding noise
+        if len(keep) == 0:
+            fx.close()
+            continue
+        rec = rec[torch.as_tensor(keep, device=device)].contiguous()
+        th = torch.as_tensor(theta[keep], dtype=torch.float64, device=device)
+        kk = torch.as_tensor(keep.astype(np.int32), device=device)
+        n = len(keep)
+        X = torch.empty((n * T, 6), dtype=torch.float32, device=device)
+        TG = torch.empty((n * T, 3), dtype=torch.float32, device=device)
+        gf.gf_mlp_make_samples(rec.data_ptr(), th.data_ptr(), kk.data_ptr(), n, dims, alpha, X.data_ptr(),
+                               TG.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        xs.append(X)
+        ts.append(TG)
+        fx.close()
+        if log:
+            log(f"recorded seed {seed}: {n} samples")
+    X = torch.cat(xs)
+    TG = torch.cat(ts)
+    return X, TG, X.shape[0] // T
+
+
+def train(X, TG, T, n_samples, epochs=20, batch=16, lr=2e-3, seed=0, params=None, log=None):
+    """Adam on minibatches of whole samples; returns (params tensor, [mean loss per epoch])."""
+    import torch
+    dev = X.device
+    p = torch.from_numpy(init_params(seed) if params is None else params).to(dev)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    g = torch.zeros_like(p)
+    rows = batch * T
+    nbytes = gf.gf_mlp_workspace_bytes(rows, batch)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    st = torch.cuda.current_stream().cuda_stream
+    rng = np.random.default_rng(seed)
+    hist = []
+    step = 0
+    for ep in range(epochs):
+        order = rng.permutation(n_samples // batch)
+        losses = []
+        for b in order:
+            s0 = b * batch
+            off = torch.arange(0, batch + 1, dtype=torch.int32, device=dev) * T
+            x = X[s0 * T:(s0 + batch) * T]
+            t = TG[s0 * T:(s0 + batch) * T]
+            step += 1
+            losses.append(gf.gf_mlp_train_step(p.data_ptr(), m.data_ptr(), v.data_ptr(), step, lr, x.data_ptr(),
+                                               t.data_ptr(), off.data_ptr(), batch, rows, g.data_ptr(),
+                                               ws.data_ptr(), nbytes, st))
+        hist.append(float(np.mean(losses)))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.5f}")
+    return p, hist
+
+
+def solve(u, precision="fp64_18", params=None, tol=1e-15, max_iter=20000, device="cuda:0", check_every=10):
+    """Fix the gauge of u with or without the network; returns (result, wall seconds, final links)."""
+    import torch
+    links = torch.from_numpy(u).to(device)
+    flags = gf.FLAG_LEARNED if params is not None else 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fx = gf.GaugeFixer(links, precision, check_every=check_every, flags=flags)
+    if params is not None:
+        fx.set_weights(params)
+    res = fx.fix_until(tol, max_iter)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fx.close()
+    return res, dt, links

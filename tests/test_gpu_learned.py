@@ -1,0 +1,175 @@
+"""Learned spectral preconditioner on the GPU against the FP64 oracle.
+
+Float32 network kernels are held to float bounds: outputs to 1e-5, the
+gradient to 1e-4 of its largest component, one Adam step to 1e-6. Recorded
+spectra (double) to 1e-10 relative. A network with a zero output layer must
+reproduce plain Fourier acceleration exactly, and corrupted weights must be
+caught by the fallback.
+"""
+import numpy as np
+import pytest
+
+from oracle import landau, mlp
+from paper_1208_1186_amd import gf, learn, synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+ALPHA = 0.08
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gf.load()
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.to("cuda:0")
+
+
+def _rand_samples(dims, nsamp, seed):
+    rng = np.random.default_rng(seed)
+    tuples = mlp.folded_tuples(dims)
+    psq = mlp.tuple_psq(dims, tuples)
+    p2 = psq.sum(1)
+    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
+    out = []
+    for _ in range(nsamp):
+        x = mlp.features(psq, 10.0 ** rng.uniform(-12, 0), float(rng.integers(0, 60)))
+        power = rng.uniform(0.1, 2.0, len(tuples))
+        power[0] = 0.0
+        kappa = 2.0 * p2 * rng.uniform(0.6, 1.0, len(tuples))
+        kappa[0] = 1.0
+        out.append((x, m0, power, kappa))
+    return out
+
+
+def _stack(samples):
+    x = np.concatenate([s[0] for s in samples]).astype(np.float32)
+    tgt = np.concatenate([np.stack([s[1], s[2], s[3]], 1) for s in samples]).astype(np.float32)
+    off = np.cumsum([0] + [len(s[0]) for s in samples]).astype(np.int32)
+    return x, tgt, off
+
+
+def _params(seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    return (mlp.init_params(seed) + scale * rng.standard_normal(mlp.n_params())).astype(np.float32)
+
+
+def test_forward_matches_oracle():
+    dims = (6, 4, 4, 8)
+    (x, m0, p, k), = _rand_samples(dims, 1, 1)
+    th = _params(2)
+    n = len(x)
+    out = torch.empty((n, 2), dtype=torch.float32, device="cuda:0")
+    nb = gf.gf_mlp_workspace_bytes(n, 1)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    th_d, x_d = dev(th), dev(x.astype(np.float32))  # held: a freed temporary's block is reused at once
+    gf.gf_mlp_forward(th_d.data_ptr(), x_d.data_ptr(), n, out.data_ptr(), ws.data_ptr(), nb)
+    _, _, want = mlp.forward(th.astype(np.float64), x.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(out.cpu().numpy() - want)) < 1e-5
+
+
+def test_loss_and_gradient_match_oracle():
+    dims = (4, 6, 4, 4)
+    samples = _rand_samples(dims, 5, 3)
+    th = _params(4)
+    x, tgt, off = _stack(samples)
+    n = len(x)
+    nb = gf.gf_mlp_workspace_bytes(n, len(samples))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda:0")
+    g = torch.empty(gf.gf_mlp_param_count(), dtype=torch.float32, device="cuda:0")
+    th_d, x_d, t_d, o_d = dev(th), dev(x), dev(tgt), dev(off)
+    loss = gf.gf_mlp_loss_grad(th_d.data_ptr(), x_d.data_ptr(), t_d.data_ptr(), o_d.data_ptr(), len(samples), n,
+                               g.data_ptr(), ws.data_ptr(), nb)
+    # the oracle sees exactly the float inputs the GPU saw
+    samples64 = [(x[a:b].astype(np.float64), tgt[a:b, 0].astype(np.float64), tgt[a:b, 1].astype(np.float64),
+                  tgt[a:b, 2].astype(np.float64)) for a, b in zip(off[:-1], off[1:])]
+    th64 = th.astype(np.float64)
+    assert loss == pytest.approx(mlp.loss(th64, samples64), rel=1e-5)
+    want = mlp.loss_grad(th64, samples64)
+    got = g.cpu().numpy().astype(np.float64)
+    assert np.max(np.abs(got - want)) <= 1e-4 * np.max(np.abs(want))
+
+
+def test_adam_step_matches_oracle():
+    rng = np.random.default_rng(5)
+    n = gf.gf_mlp_param_count()
+    th = rng.standard_normal(n).astype(np.float32)
+    gr = rng.standard_normal(n).astype(np.float32)
+    m = (0.1 * rng.standard_normal(n)).astype(np.float32)
+    v = np.abs(0.1 * rng.standard_normal(n)).astype(np.float32)
+    p_d, m_d, v_d, g_d = dev(th), dev(m), dev(v), dev(gr)
+    gf.gf_mlp_adam(p_d.data_ptr(), m_d.data_ptr(), v_d.data_ptr(), g_d.data_ptr(), 7, 1e-3)
+    torch.cuda.synchronize()
+    want, wm, wv = mlp.adam_step(th.astype(np.float64), gr.astype(np.float64), m.astype(np.float64),
+                                 v.astype(np.float64), 7, 1e-3)
+    assert np.max(np.abs(p_d.cpu().numpy() - want)) < 1e-6
+    assert np.max(np.abs(m_d.cpu().numpy() - wm)) < 1e-6
+
+
+@pytest.mark.parametrize("dims", [(8, 4, 6, 4), (8, 8, 8, 8)])
+def test_recorded_spectra_match_oracle(dims):
+    u = synth.make_config(dims, 11)
+    links = dev(u)
+    fx = gf.GaugeFixer(links, "fp64_18", flags=gf.FLAG_RECORD_SPECTRA)
+    rec, theta = fx.record(3)
+    rec = rec.cpu().numpy()
+    tuples = mlp.folded_tuples(dims)
+    cur = u
+    specs = []
+    for k in range(4):
+        specs.append(mlp.packed_spectrum(landau.divergence(cur)))
+        if k < 3:
+            assert theta[k] == pytest.approx(landau.theta(cur), rel=1e-12)
+            cur, *_ = landau.fa_step(cur, ALPHA)
+    for k in range(3):
+        p, c = mlp.record(specs[k], specs[k + 1], dims, tuples)
+        assert np.max(np.abs(rec[k, :, 0] - p)) <= 1e-10 * np.max(np.abs(p))
+        assert np.max(np.abs(rec[k, :, 1] - c)) <= 1e-10 * np.max(np.abs(p))
+    # the links were advanced by exactly the recorded updates
+    assert np.max(np.abs(links.cpu().numpy() - cur)) < 1e-12
+    # training rows assembled on the GPU match the oracle's features and targets
+    n = 3
+    X = torch.empty((n * len(tuples), 6), dtype=torch.float32, device="cuda:0")
+    TG = torch.empty((n * len(tuples), 3), dtype=torch.float32, device="cuda:0")
+    kk = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    rec_d, th_d = dev(rec), dev(theta[:n])
+    gf.gf_mlp_make_samples(rec_d.data_ptr(), th_d.data_ptr(), kk.data_ptr(), n, dims, ALPHA, X.data_ptr(),
+                           TG.data_ptr())
+    X, TG = X.cpu().numpy(), TG.cpu().numpy()
+    psq = mlp.tuple_psq(dims, tuples)
+    p2 = psq.sum(1)
+    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
+    for k in range(n):
+        rows = slice(k * len(tuples), (k + 1) * len(tuples))
+        assert np.max(np.abs(X[rows] - mlp.features(psq, theta[k], k))) < 1e-6
+        kap = mlp.kappa_from(rec[k, :, 0], rec[k, :, 1], m0)
+        assert np.max(np.abs(TG[rows, 0] - m0) / np.maximum(m0, 1e-30)) < 1e-6
+        live = rec[k, :, 0] > 1e-8 * rec[k, :, 0].max()
+        assert np.max(np.abs(TG[rows, 2][live] - kap[live]) / kap[live]) < 1e-5
+
+
+def test_zero_output_network_is_plain_fa():
+    u = synth.make_config((8, 8, 8, 8), 12)
+    p = learn.init_params(3)  # zero output layer
+    r0, _, l0 = learn.solve(u)
+    r1, _, l1 = learn.solve(u, params=torch.from_numpy(p).cuda())
+    assert r1.iters == r0.iters and r1.fallbacks == 0
+    assert torch.equal(l0, l1)
+
+
+def test_fallback_rescues_corrupted_weights():
+    u = synth.make_config((8, 8, 8, 8), 13)
+    p = learn.init_params(4)
+    p[-130:-2] = 5.0  # W3: every output pushed far from zero
+    p[-2:] = 3.0
+    res, _, links = learn.solve(u, params=torch.from_numpy(p).cuda())
+    assert res.status == gf.GF_OK and res.theta < 1e-15
+    assert res.fallbacks >= 1
+    assert landau.theta(links.cpu().numpy()) < 1e-15

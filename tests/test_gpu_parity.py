@@ -60,8 +60,9 @@ def test_filter(dims):
     d = landau.divergence(u)
     want = 0.5 * ALPHA * landau.fa_filter(d)
     fx, _ = fixer_for(u)
-    out = torch.empty_like(to_dev(d))
-    gf.gf_stage_filter(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    d_dev = to_dev(d)  # held for the call: a freed temporary's block can be reused at once
+    out = torch.empty_like(d_dev)
+    gf.gf_stage_filter(fx.ctx, d_dev.data_ptr(), out.data_ptr())
     got = out.cpu().numpy()
     assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
 
@@ -75,8 +76,9 @@ def test_gauge_stage(dims, precision):
     d = landau.divergence(u)
     want = landau.gauge_from_delta(landau.fa_filter(d), ALPHA)
     fx, _ = fixer_for(u, precision)
-    out = torch.empty_like(to_dev(d))
-    gf.gf_stage_gauge(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    d_dev = to_dev(d)
+    out = torch.empty_like(d_dev)
+    gf.gf_stage_gauge(fx.ctx, d_dev.data_ptr(), out.data_ptr())
     got = out.cpu().numpy()
     tol = 1e-13 if precision.startswith("fp64") else 2e-6
     assert np.max(np.abs(got - want)) < tol
@@ -89,7 +91,8 @@ def test_update(dims):
     dt = landau.fa_filter(landau.divergence(u))
     want = landau.apply_gauge(u, landau.gauge_from_delta(dt, ALPHA))
     fx, links = fixer_for(u)
-    gf.gf_stage_update(fx.ctx, to_dev(0.5 * ALPHA * dt).data_ptr())
+    step = to_dev(0.5 * ALPHA * dt)
+    gf.gf_stage_update(fx.ctx, step.data_ptr())
     got = links.cpu().numpy()
     assert np.max(np.abs(got - want)) < 1e-13
 
@@ -224,12 +227,13 @@ def test_workload_shapes_filter_and_gauge(dims, generic, precision):
     dt = landau.fa_filter(d)
     flags = gf.FLAG_GENERIC_FFT if generic else 0
     fx, _ = fixer_for(u, precision, flags=flags)
-    out = torch.empty_like(to_dev(d))
-    gf.gf_stage_filter(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    d_dev = to_dev(d)  # held for the call: a freed temporary's block can be reused at once
+    out = torch.empty_like(d_dev)
+    gf.gf_stage_filter(fx.ctx, d_dev.data_ptr(), out.data_ptr())
     want = 0.5 * ALPHA * dt
     tol = 1e-12 if precision.startswith("fp64") else 3e-6
     assert np.max(np.abs(out.cpu().numpy() - want)) <= tol * np.max(np.abs(want))
-    gf.gf_stage_gauge(fx.ctx, to_dev(d).data_ptr(), out.data_ptr())
+    gf.gf_stage_gauge(fx.ctx, d_dev.data_ptr(), out.data_ptr())
     g_want = landau.gauge_from_delta(dt, ALPHA)
     assert np.max(np.abs(out.cpu().numpy() - g_want)) < (1e-13 if precision.startswith("fp64") else 2e-6)
 
