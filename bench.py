@@ -115,6 +115,61 @@ def mixed_workload(gf, torch, synth, dev, dims=(48, 48, 48, 8)):
     return out
 
 
+def batch_workload(gf, torch, synth, dev, n=64, tol=1e-15):
+    """64 uneven lattices (8^4, 12^4, 16^4, 24^3x8, 32^3x4), float bulk / double finish, batched vs one by one."""
+    import numpy as np
+    log(f"uneven batch: generating {n} configurations (host worker processes)")
+    t0 = time.perf_counter()
+    shapes, us = synth.batch_configs(n)
+    log(f"generated in {time.perf_counter() - t0:.1f}s")
+    vols = [int(np.prod(d)) for d in shapes]
+    base = [torch.from_numpy(u).to(dev) for u in us]
+    del us
+    out = {"configurations": n, "sites": int(sum(vols)),
+           "shapes": {f"{d[0]}x{d[1]}x{d[2]}x{d[3]}": shapes.count(d) for d in sorted(set(shapes))},
+           "precision": "mixed (float 12-real bulk to theta<1e-8, double 18-real polish)", "tol": tol}
+
+    def run_batched():
+        links = [b.clone() for b in base]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        bf = gf.BatchFixer(links, "mixed", check_every=10)
+        st, res = bf.fix_until(tol, 100000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        bf.close()
+        return dt, st, res
+
+    def run_sequential():
+        res = []
+        links = [b.clone() for b in base]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for lk in links:
+            fx = gf.GaugeFixer(lk, "mixed", check_every=10)
+            res.append(fx.fix_until(tol, 100000))
+            fx.close()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, res
+
+    bt = min((run_batched() for _ in range(2)), key=lambda x: x[0])
+    dt_b, st, res_b = bt
+    dt_s, res_s = min((run_sequential() for _ in range(2)), key=lambda x: x[0])
+    site_iters = sum(v * r.iters for v, r in zip(vols, res_b))
+    out["batched"] = {"wall_s_to_all_theta": round(dt_b, 4), "status": int(st),
+                      "site_iterations_per_s": round(site_iters / dt_b, 1),
+                      "iters_min_max": [min(r.iters for r in res_b), max(r.iters for r in res_b)],
+                      "max_theta": max(r.theta for r in res_b)}
+    out["one_by_one"] = {"wall_s_to_all_theta": round(dt_s, 4),
+                         "site_iterations_per_s": round(sum(v * r.iters for v, r in zip(vols, res_s)) / dt_s, 1),
+                         "max_theta": max(r.theta for r in res_s)}
+    out["batched_speedup"] = round(dt_s / dt_b, 3)
+    out["same_results_as_one_by_one"] = all(a.iters == b.iters and a.theta == b.theta and a.F == b.F
+                                            for a, b in zip(res_b, res_s))
+    log(f"batch: {dt_b:.3f}s batched vs {dt_s:.3f}s one by one, {site_iters / dt_b / 1e6:.1f} M site-it/s")
+    return out
+
+
 def cpu_baseline(u, budget_s=12.0):
     """The FP64 NumPy oracle's FA iterations on the same input, on the host cores."""
     from oracle import landau
@@ -144,6 +199,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and time-to-theta")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3x8 mixed-precision workload")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice uneven batch workload")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -223,6 +279,8 @@ def main():
 
     if not args.no_extras and not args.no_mixed:
         extras["mixed_48x48x48x8"] = mixed_workload(gf, torch, synth, dev)
+    if not args.no_extras and not args.no_batch:
+        extras["batch_64_uneven"] = batch_workload(gf, torch, synth, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

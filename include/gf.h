@@ -113,6 +113,41 @@ gf_status gf_iterate(gf_ctx* ctx, int64_t n, gf_result* result);
  */
 gf_status gf_fix_until(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf_result* result);
 
+/*
+ * Batches of independent lattices (many uneven configurations, one GPU).
+ * The gauge fixing of Section 1 of the paper acts on each configuration on
+ * its own (the paper fixes one lattice at a time); a batch advances every configuration of the same
+ * shape in the same kernel launches, each with its own stopping test, and
+ * retires a configuration as soon as its theta < theta_tol. params: n sets
+ * that may differ in dims only (precision, alpha, switch_theta, check_every
+ * and flags equal; GF_FLAG_LEARNED and GF_FLAG_RECORD_SPECTRA not allowed).
+ * GF_MIXED configurations iterate in float until theta < switch_theta (or the
+ * float descent stalls) and finish in double precision, as in gf_init.
+ */
+
+/* Bytes of device workspace gf_init_batch needs (0 if the parameters are invalid). */
+size_t gf_batch_workspace_bytes(int32_t n, const gf_params* params);
+
+/*
+ * Create a batch context. d_links[i]: canonical links of configuration i
+ * (V_i*36 complex double, device), read now and overwritten with the final
+ * iterate by gf_fix_until_batch. d_workspace: >= gf_batch_workspace_bytes
+ * bytes, 256-byte aligned, caller-owned. Measures theta and F of every input.
+ * A batch context takes only gf_fix_until_batch, gf_last_error and
+ * gf_destroy (GF_ESTATE otherwise).
+ */
+gf_status gf_init_batch(gf_ctx** ctx, int32_t n, const gf_params* params, double* const* d_links,
+                        void* d_workspace, size_t workspace_bytes, void* stream);
+
+/*
+ * Fix every configuration to theta < theta_tol, each within max_iter updates
+ * (float and double phases counted together). results[i] (host, n entries)
+ * receives configuration i's outcome; seconds is the wall time of the whole
+ * call. Returns GF_ENOTCONV (or GF_ENUMERIC) if any configuration failed;
+ * results and links are filled in for all of them.
+ */
+gf_status gf_fix_until_batch(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf_result* results);
+
 /* theta and F of the current links, in double precision. */
 gf_status gf_quality(gf_ctx* ctx, double* theta, double* F);
 

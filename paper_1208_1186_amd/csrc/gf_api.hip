@@ -251,6 +251,8 @@ gf_status plan_layout(const gf_params* p, Layout& L, std::string& err) {
     return plan_plain(p, L, err);
 }
 
+struct BatchState;
+
 }  // namespace
 
 struct gf_ctx {
@@ -285,6 +287,13 @@ struct gf_ctx {
     gf_ctx* child[2] = {nullptr, nullptr};
     int phase = 1;
     long long k_host;  // updates applied, as of the last read of the control block
+    // A batch driver launches the loop kernels over nact configurations at once
+    // (blockIdx.y indexes act_dev); the buffers of configuration c are c*cs
+    // bytes after this context's. Single lattices have nact 1, cs 0.
+    int nact = 1;
+    const int* act_dev = nullptr;
+    size_t cs = 0;
+    BatchState* batch = nullptr;  // set on a context made by gf_init_batch
     FftPlan plan[4];
     Ctl* h_head;  // pinned host copy of the control block's leading scalars
     std::string err;
@@ -354,6 +363,7 @@ void tstop(gf_ctx* c) {
 
 // ---------------------------------------------------------------- launches
 int cur(const gf_ctx* c) { return (int)(c->k_host & 1); }
+Batch bt(const gf_ctx* c) { return Batch{c->act_dev, c->cs}; }
 double inv3v(const gf_ctx* c) { return 1.0 / (3.0 * (double)c->L.vol); }
 double inv12v(const gf_ctx* c) { return 1.0 / (12.0 * (double)c->L.vol); }
 
@@ -389,9 +399,9 @@ bool launch_xy_ct(gf_ctx* c, const void* src, void* dst, int force, bool loop_re
     const double2* part = loop_reduce ? c->part : nullptr;
 #define GF_X(A, B, GG)                                                                                          \
     if (L.n[0] == A && L.n[1] == B && L.G == GG) {                                                              \
-        hipLaunchKernelGGL((k_fft_xy_ct<T, A, B, GG, INV>), dim3(4 * nzt / GG), dim3(ct_threads(GG * A * B, 8)), \
-                           0, c->st, s, cxp<T>(dst), L.ps, nzt, twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, part,  \
-                           L.nblk_fused, inv3v(c), inv12v(c));                                                  \
+        hipLaunchKernelGGL((k_fft_xy_ct<T, A, B, GG, INV>), dim3(4 * nzt / GG, c->nact),                          \
+                           dim3(ct_threads(GG * A * B, 8)), 0, c->st, s, cxp<T>(dst), L.ps, nzt, twp<T>(c, 0),  \
+                           twp<T>(c, 1), c->ctl, force, part, L.nblk_fused, inv3v(c), inv12v(c), bt(c));       \
         return true;                                                                                            \
     }
     GF_XY_CASES(GF_X)
@@ -405,9 +415,10 @@ bool launch_zt_ct(gf_ctx* c, void* Z, T coef, int no_fa, int force, const T* mta
     const T* s2 = reinterpret_cast<const T*>(c->sin2);
 #define GF_X(A, B, BB)                                                                                     \
     if (L.n[2] == A && L.n[3] == B && L.bx == BB) {                                                        \
-        hipLaunchKernelGGL((k_fft_zt_ct<T, A, B, BB>), dim3(4 * L.n[1] * (L.n[0] / BB)),                   \
+        hipLaunchKernelGGL((k_fft_zt_ct<T, A, B, BB>), dim3(4 * L.n[1] * (L.n[0] / BB), c->nact),           \
                            dim3(ct_threads(BB * A * B, 8)), 0, c->st, cxp<T>(Z), L.ps, L.n[0], L.n[1],     \
-                           twp<T>(c, 2), twp<T>(c, 3), s2, coef, no_fa, c->ctl, force, mtab, c->tg, spec); \
+                           twp<T>(c, 2), twp<T>(c, 3), s2, coef, no_fa, c->ctl, force, mtab, c->tg, spec,  \
+                           bt(c));                                                                         \
         return true;                                                                                       \
     }
     if constexpr (sizeof(T) == 8) {
@@ -424,10 +435,10 @@ bool launch_gauge_ct(gf_ctx* c, int force) {
     const Layout& L = c->L;
 #define GF_X(A, B)                                                                                             \
     if (L.n[0] == A && L.n[1] == B) {                                                                          \
-        hipLaunchKernelGGL((k_fft_xy_gauge_ct<T, A, B>), dim3(L.n[2] * L.n[3]),                                \
+        hipLaunchKernelGGL((k_fft_xy_gauge_ct<T, A, B>), dim3(L.n[2] * L.n[3], c->nact),                       \
                            dim3(ct_threads(4 * A * B, gauge_ept(A, B))), gauge_ct_lds(A, B, sizeof(cx<T>)),    \
                            c->st, reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps,             \
-                           twp<T>(c, 0), twp<T>(c, 1), c->ctl, force);                                         \
+                           twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c));                                  \
         return true;                                                                                           \
     }
     GF_GAUGE_CASES(GF_X)
@@ -454,10 +465,10 @@ void launch_xy(gf_ctx* c, const void* src, void* dst, int force, bool loop_reduc
         tstop(c);
         return;
     }
-    hipLaunchKernelGGL((k_fft_xy<T, kEPT, INV>), dim3(4 * nzt / L.G), dim3(L.thrA), L.ldsA, c->st,
+    hipLaunchKernelGGL((k_fft_xy<T, kEPT, INV>), dim3(4 * nzt / L.G, c->nact), dim3(L.thrA), L.ldsA, c->st,
                        reinterpret_cast<const cx<T>*>(src), cxp<T>(dst), L.ps, L.n[0], L.n[1], nzt, L.G, L.rs,
                        c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force,
-                       loop_reduce ? c->part : nullptr, L.nblk_fused, inv3v(c), inv12v(c));
+                       loop_reduce ? c->part : nullptr, L.nblk_fused, inv3v(c), inv12v(c), bt(c));
     tstop(c);
 }
 
@@ -473,10 +484,10 @@ void launch_zt(gf_ctx* c, void* Z, int force) {
         tstop(c);
         return;
     }
-    hipLaunchKernelGGL((k_fft_zt<T, kEPT>), dim3(4 * L.n[1] * (L.n[0] / L.bx)), dim3(L.thrB), L.ldsB, c->st,
-                       cxp<T>(Z), L.ps, L.n[0], L.n[1], L.n[2], L.n[3], L.bx, L.tsp, c->plan[2], c->plan[3],
+    hipLaunchKernelGGL((k_fft_zt<T, kEPT>), dim3(4 * L.n[1] * (L.n[0] / L.bx), c->nact), dim3(L.thrB), L.ldsB,
+                       c->st, cxp<T>(Z), L.ps, L.n[0], L.n[1], L.n[2], L.n[3], L.bx, L.tsp, c->plan[2], c->plan[3],
                        twp<T>(c, 2), twp<T>(c, 3), reinterpret_cast<const T*>(c->sin2), (T)coef, no_fa ? 1 : 0,
-                       c->ctl, force, mtab, c->tg, spec);
+                       c->ctl, force, mtab, c->tg, spec, bt(c));
     tstop(c);
 }
 
@@ -489,13 +500,13 @@ void launch_gauge_pass(gf_ctx* c, int force) {
         return;
     }
     if (L.eptC == kEPT)
-        hipLaunchKernelGGL((k_fft_xy_gauge<T, kEPT>), dim3(L.n[2] * L.n[3]), dim3(L.thrC), L.ldsC, c->st,
+        hipLaunchKernelGGL((k_fft_xy_gauge<T, kEPT>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
                            reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
-                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force);
+                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c));
     else
-        hipLaunchKernelGGL((k_fft_xy_gauge<T, 16>), dim3(L.n[2] * L.n[3]), dim3(L.thrC), L.ldsC, c->st,
+        hipLaunchKernelGGL((k_fft_xy_gauge<T, 16>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
                            reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
-                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force);
+                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c));
     tstop(c);
 }
 
@@ -508,7 +519,8 @@ void launch_measure_t(gf_ctx* c) {
                        cxp<T>(c->D), L.ps, c->geom, c->part);
     tstop(c);
     tstart(c, GF_K_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, L.nblk, inv3v(c), inv12v(c), c->ctl, 0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, L.nblk, inv3v(c), inv12v(c), c->ctl, 0,
+                       Batch{nullptr, 0});
     tstop(c);
 }
 
@@ -528,9 +540,9 @@ void launch_fused_t(gf_ctx* c, long long k) {
     const Layout& L = c->L;
     const int a = (int)(k & 1);
     tstart(c, GF_K_UPDATE_MEASURE);
-    hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused), dim3(kFusedThreads), 0, c->st,
+    hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused, c->nact), dim3(kFusedThreads), 0, c->st,
                        links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
-                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl, reinterpret_cast<cx<T>*>(c->Acc));
+                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl, reinterpret_cast<cx<T>*>(c->Acc), bt(c));
     tstop(c);
 }
 
@@ -587,8 +599,8 @@ gf_status one_iteration(gf_ctx* c, long long k) {
 
 gf_status loop_finalize(gf_ctx* c) {
     tstart(c, GF_K_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, c->L.nblk_fused, inv3v(c), inv12v(c),
-                       c->ctl, 1);
+    hipLaunchKernelGGL(k_finalize, dim3(1, c->nact), dim3(256), 0, c->st, c->part, c->L.nblk_fused, inv3v(c),
+                       inv12v(c), c->ctl, 1, bt(c));
     tstop(c);
     return launched(c, "finalize launch");
 }
@@ -760,8 +772,8 @@ gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r, bool u
 // Carve a plain (single-precision-class) context out of ws and set it up:
 // tables, control block, links packed from the canonical d_links, the
 // accumulated transform set to 1, and (if measure) theta and F of the input.
-gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsigned char* ws,
-                     hipStream_t st, bool measure) {
+// Point c's buffers into ws as L lays them out (no device work, no allocation).
+void carve(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsigned char* ws, hipStream_t st) {
     c->p = p;
     c->L = L;
     c->st = st;
@@ -794,6 +806,11 @@ gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_l
     c->geom.vol = L.vol;
     c->geom.stride[0] = 1;
     for (int d = 1; d < 4; ++d) c->geom.stride[d] = c->geom.stride[d - 1] * L.n[d - 1];
+}
+
+gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsigned char* ws,
+                     hipStream_t st, bool measure) {
+    carve(c, p, L, d_links, ws, st);
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_head), kHeadBytes) != hipSuccess) {
         c->h_head = nullptr;
         return fail(c, GF_EDEVICE, "hipHostMalloc of the control readback buffer failed");
@@ -834,9 +851,12 @@ gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_l
     return s;
 }
 
+void free_batch(BatchState* b);
+
 void free_ctx(gf_ctx* c) {
     if (!c) return;
     for (int i = 0; i < 2; ++i) free_ctx(c->child[i]);
+    if (c->batch) free_batch(c->batch);
     if (c->h_head) {
         (void)hipStreamSynchronize(c->st);
         (void)hipHostFree(c->h_head);
@@ -915,6 +935,249 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     return GF_OK;
 }
 
+
+// ----------------------------------------------------------------- batches
+// Independent lattices of one shape form a group. A group's configurations
+// share the compile-time FFT kernels and are advanced together: each loop
+// kernel is one launch over the group's active configurations (blockIdx.y),
+// each with its own slab of workspace, control block and stopping test.
+// GF_MIXED groups run the float phase until every configuration has reached
+// switch_theta (or stalled), hand each over to double precision, and polish.
+struct BatchGroup {
+    std::vector<int> idx;  // positions in the caller's arrays
+    int nphase = 1;        // 2 for GF_MIXED
+    gf_params q[2];
+    Layout L[2];
+    size_t cs[2] = {0, 0};   // bytes between consecutive configurations' slabs
+    size_t off[2] = {0, 0};  // workspace offset of the first slab of each phase
+    size_t off_act = 0, off_heads = 0;
+    gf_ctx* drv[2] = {nullptr, nullptr};  // launches over the active configurations
+    std::vector<gf_ctx*> view[2];         // one single-lattice context per configuration
+    int* d_act = nullptr;
+    unsigned char* d_heads = nullptr;
+    int* h_act = nullptr;              // pinned
+    unsigned char* h_heads = nullptr;  // pinned
+};
+
+struct BatchState {
+    int n = 0;
+    gf_params p{};
+    size_t total = 0;
+    std::vector<BatchGroup> g;
+};
+
+void free_batch(BatchState* b) {
+    for (auto& g : b->g) {
+        for (int p = 0; p < 2; ++p) {
+            for (gf_ctx* v : g.view[p]) free_ctx(v);
+            free_ctx(g.drv[p]);
+        }
+        if (g.h_act) (void)hipHostFree(g.h_act);
+        if (g.h_heads) (void)hipHostFree(g.h_heads);
+    }
+    delete b;
+}
+
+gf_status plan_batch(int32_t n, const gf_params* params, BatchState& b, std::string& err) {
+    if (n < 1 || !params) {
+        err = "a batch needs n >= 1 parameter sets";
+        return GF_EINVAL;
+    }
+    const gf_params& p0 = params[0];
+    for (int i = 0; i < n; ++i) {
+        const gf_params& p = params[i];
+        if (p.precision != p0.precision || p.alpha != p0.alpha || p.switch_theta != p0.switch_theta ||
+            p.check_every != p0.check_every || p.flags != p0.flags) {
+            err = "every configuration of a batch must share precision, alpha, switch_theta, check_every and flags";
+            return GF_EINVAL;
+        }
+    }
+    if (p0.flags & (GF_FLAG_LEARNED | GF_FLAG_RECORD_SPECTRA)) {
+        err = "GF_FLAG_LEARNED and GF_FLAG_RECORD_SPECTRA are not available in a batch";
+        return GF_EINVAL;
+    }
+    b.n = n;
+    b.p = p0;
+    b.g.clear();
+    for (int i = 0; i < n; ++i) {
+        BatchGroup* grp = nullptr;
+        for (auto& g : b.g)
+            if (std::equal(params[g.idx[0]].dims, params[g.idx[0]].dims + 4, params[i].dims)) grp = &g;
+        if (!grp) {
+            b.g.emplace_back();
+            grp = &b.g.back();
+        }
+        grp->idx.push_back(i);
+    }
+    size_t o = 0;
+    for (auto& g : b.g) {
+        const gf_params& p = params[g.idx[0]];
+        const int ng = (int)g.idx.size();
+        g.nphase = p.precision == GF_MIXED ? 2 : 1;
+        if (g.nphase == 2 && (!(p.switch_theta > 0.0) || !std::isfinite(p.switch_theta))) {
+            err = "switch_theta must be positive and finite";
+            return GF_EINVAL;
+        }
+        for (int ph = 0; ph < g.nphase; ++ph) {
+            g.q[ph] = g.nphase == 2 ? mixed_child(p, ph) : p;
+            gf_status s = plan_plain(&g.q[ph], g.L[ph], err);
+            if (s != GF_OK) return s;
+            g.cs[ph] = align_up(g.L[ph].total, kAlign);
+            g.off[ph] = o;
+            o += g.cs[ph] * ng;
+        }
+        g.off_act = o;
+        o = align_up(o + (size_t)ng * sizeof(int), kAlign);
+        g.off_heads = o;
+        o = align_up(o + (size_t)ng * kHeadBytes, kAlign);
+    }
+    b.total = o;
+    return GF_OK;
+}
+
+gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned char* ws, hipStream_t st) {
+    for (auto& g : b.g) {
+        const int ng = (int)g.idx.size();
+        g.d_act = reinterpret_cast<int*>(ws + g.off_act);
+        g.d_heads = ws + g.off_heads;
+        if (hipHostMalloc(reinterpret_cast<void**>(&g.h_act), ng * sizeof(int)) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&g.h_heads), ng * kHeadBytes) != hipSuccess)
+            return fail(c, GF_EDEVICE, "hipHostMalloc of the batch readback buffers failed");
+        for (int ph = 0; ph < g.nphase; ++ph) {
+            for (int i = 0; i < ng; ++i) {
+                gf_ctx* v = new (std::nothrow) gf_ctx();
+                if (!v) return fail(c, GF_EINVAL, "out of host memory");
+                g.view[ph].push_back(v);
+                // a GF_MIXED double slab keeps the input links in its buffer 0 until the hand-over
+                const gf_status s = init_plain(v, g.q[ph], g.L[ph], d_links[g.idx[i]], ws + g.off[ph] + i * g.cs[ph],
+                                               st, ph == 0);
+                if (s != GF_OK) return fail(c, s, v->err);
+            }
+            gf_ctx* d = new (std::nothrow) gf_ctx();
+            if (!d) return fail(c, GF_EINVAL, "out of host memory");
+            g.drv[ph] = d;
+            carve(d, g.q[ph], g.L[ph], nullptr, ws + g.off[ph], st);
+            d->cs = g.cs[ph];
+            d->act_dev = g.d_act;
+        }
+    }
+    return GF_OK;
+}
+
+// Read the control blocks of every configuration of phase ph into their views.
+gf_status gather_heads(gf_ctx* c, BatchGroup& g, int ph) {
+    const int ng = (int)g.idx.size();
+    hipLaunchKernelGGL(k_gather_heads, dim3(ng), dim3(64), 0, c->st,
+                       reinterpret_cast<const unsigned char*>(g.view[ph][0]->ctl), g.cs[ph], (int)(kHeadBytes / 8),
+                       reinterpret_cast<unsigned long long*>(g.d_heads));
+    gf_status s = launched(c, "gather launch");
+    if (s != GF_OK) return s;
+    GF_TRY_HIP(c, hipMemcpyAsync(g.h_heads, g.d_heads, ng * kHeadBytes, hipMemcpyDeviceToHost, c->st));
+    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    for (int i = 0; i < ng; ++i) {
+        gf_ctx* v = g.view[ph][i];
+        std::memcpy(v->h_head, g.h_heads + (size_t)i * kHeadBytes, kHeadBytes);
+        v->k_host = v->h_head->iters;
+    }
+    return GF_OK;
+}
+
+struct BatchOutcome {
+    gf_result r{};
+    gf_status s = GF_OK;
+    bool finished = false;
+};
+
+gf_status finish_config(gf_ctx* c, gf_ctx* v, int phase, long long iters_before, BatchOutcome& out, bool converged) {
+    gf_status s = unpack_links(v, v->links_user);
+    if (s != GF_OK) return fail(c, s, v->err);
+    out.r.iters = iters_before + v->h_head->iters;
+    out.r.theta = v->h_head->theta;
+    out.r.F = v->h_head->F;
+    out.r.phase = phase;
+    out.r.fallbacks = 0;
+    out.s = v->h_head->numeric ? GF_ENUMERIC : (converged ? GF_OK : GF_ENOTCONV);
+    out.finished = true;
+    return GF_OK;
+}
+
+gf_status run_group(gf_ctx* c, BatchGroup& g, double tol, int64_t max_iter, std::vector<BatchOutcome>& out) {
+    const int ng = (int)g.idx.size();
+    const bool mixed = g.nphase == 2;
+    int64_t left = max_iter;
+    std::vector<long long> it0(ng, 0);  // float-phase updates of each configuration
+    std::vector<char> stalled(ng, 0);
+    gf_status s = GF_OK;
+    for (int ph = 0; ph < g.nphase; ++ph) {
+        const double tp = (mixed && ph == 0) ? std::max(c->p.switch_theta, tol) : tol;
+        gf_ctx* drv = g.drv[ph];
+        for (int i = 0; i < ng && s == GF_OK; ++i)
+            if (!out[g.idx[i]].finished) s = set_tol(g.view[ph][i], tp);
+        if (s == GF_OK) s = gather_heads(c, g, ph);
+        if (s != GF_OK) return s;
+        std::vector<int> act;
+        std::vector<double> last(ng, 0.0);
+        for (int i = 0; i < ng; ++i) {
+            const Ctl* h = g.view[ph][i]->h_head;
+            last[i] = h->theta;
+            if (!out[g.idx[i]].finished && !h->done) act.push_back(i);
+        }
+        long long k = 0;  // every active configuration of the phase has applied k updates
+        while (!act.empty() && left > 0) {
+            std::copy(act.begin(), act.end(), g.h_act);
+            GF_TRY_HIP(c, hipMemcpyAsync(g.d_act, g.h_act, act.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
+            drv->nact = (int)act.size();
+            const int64_t n_it = std::min<int64_t>(left, c->p.check_every);
+            for (int64_t j = 0; j < n_it && s == GF_OK; ++j) s = one_iteration(drv, k + j);
+            if (s == GF_OK) s = loop_finalize(drv);
+            if (s == GF_OK) s = gather_heads(c, g, ph);
+            if (s != GF_OK) return fail(c, s, drv->err);
+            k += n_it;
+            left -= n_it;
+            std::vector<int> next;
+            for (int i : act) {
+                const Ctl* h = g.view[ph][i]->h_head;
+                if (h->done || h->numeric) continue;
+                if (h->iters != k) return fail(c, GF_EDEVICE, "batch configurations fell out of step");
+                if (mixed && ph == 0) {
+                    const double th = h->theta;
+                    stalled[i] = th < kStallTheta && th > kStallRatio * last[i];
+                    last[i] = th;
+                    if (stalled[i]) continue;
+                }
+                next.push_back(i);
+            }
+            act.swap(next);
+        }
+        for (int i = 0; i < ng; ++i) {
+            BatchOutcome& o = out[g.idx[i]];
+            if (o.finished) continue;
+            gf_ctx* v = g.view[ph][i];
+            const Ctl* h = v->h_head;
+            if (mixed && ph == 0) {
+                it0[i] = h->iters;
+                const bool reached = h->theta < tp;
+                if (h->numeric || (tol > 0.0 && h->theta < tol) || (!reached && !stalled[i])) {
+                    // converged in float, not finite, or out of iterations before the hand-over
+                    s = finish_config(c, v, 0, 0, o, h->theta < tol);
+                    if (s != GF_OK) return s;
+                    continue;
+                }
+                gf_ctx* w = g.view[1][i];
+                hipLaunchKernelGGL(k_apply_accumulated<9>, dim3(w->L.nblk), dim3(kSiteThreads), 0, w->st,
+                                   links_of<double, 9>(w, 0), reinterpret_cast<const cx<float>*>(v->Acc), v->L.ps,
+                                   reinterpret_cast<cx<double>*>(w->Acc), w->L.ps, w->geom);
+                s = launched(w, "hand-over launch");
+                if (s == GF_OK) s = launch_measure(w);
+                if (s != GF_OK) return fail(c, s, w->err);
+            } else {
+                s = finish_config(c, v, mixed ? 1 : (v->L.fp32 ? 0 : 1), mixed ? it0[i] : 0, o, h->done != 0);
+                if (s != GF_OK) return s;
+            }
+        }
+    }
+    return GF_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -998,6 +1261,7 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
 
 gf_status gf_iterate(gf_ctx* c, int64_t n, gf_result* r) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (n < 0) return fail(c, GF_EINVAL, "n must be >= 0");
     try {
         if (c->L.mixed) return mixed_run(c, -1.0, n, r);
@@ -1009,6 +1273,7 @@ gf_status gf_iterate(gf_ctx* c, int64_t n, gf_result* r) {
 
 gf_status gf_fix_until(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (!(tol > 0.0)) return fail(c, GF_EINVAL, "theta_tol must be > 0");
     if (max_iter < 0) return fail(c, GF_EINVAL, "max_iter must be >= 0");
     try {
@@ -1022,8 +1287,118 @@ gf_status gf_fix_until(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     }
 }
 
+size_t gf_batch_workspace_bytes(int32_t n, const gf_params* params) {
+    try {
+        BatchState b;
+        std::string err;
+        return plan_batch(n, params, b, err) == GF_OK ? b.total : 0;
+    } catch (...) {
+        return 0;
+    }
+}
+
+gf_status gf_init_batch(gf_ctx** out, int32_t n, const gf_params* params, double* const* d_links, void* d_workspace,
+                        size_t workspace_bytes, void* stream) {
+    try {
+        if (!out) {
+            g_init_error = "ctx output pointer is NULL";
+            return GF_EINVAL;
+        }
+        *out = nullptr;
+        BatchState* b = new (std::nothrow) BatchState();
+        if (!b) {
+            g_init_error = "out of host memory";
+            return GF_EINVAL;
+        }
+        std::string err;
+        gf_status s = plan_batch(n, params, *b, err);
+        if (s == GF_OK) {
+            // every lattice shape must plan on its own too (extents, plane sizes)
+            for (int i = 0; i < n && s == GF_OK; ++i) {
+                Layout L;
+                s = plan_layout(&params[i], L, err);
+            }
+        }
+        if (s == GF_OK && (!d_links || !d_workspace)) {
+            err = "links or workspace pointer is NULL";
+            s = GF_EINVAL;
+        }
+        for (int i = 0; s == GF_OK && i < n; ++i)
+            if (!d_links[i]) {
+                err = "links pointer " + std::to_string(i) + " is NULL";
+                s = GF_EINVAL;
+            }
+        if (s == GF_OK && workspace_bytes < b->total) {
+            err = "workspace too small: need " + std::to_string(b->total) + " bytes";
+            s = GF_EINVAL;
+        }
+        if (s == GF_OK && (reinterpret_cast<uintptr_t>(d_workspace) % kAlign) != 0) {
+            err = "workspace must be 256-byte aligned";
+            s = GF_EINVAL;
+        }
+        if (s != GF_OK) {
+            g_init_error = err;
+            delete b;
+            return s;
+        }
+        gf_ctx* c = new (std::nothrow) gf_ctx();
+        if (!c) {
+            delete b;
+            g_init_error = "out of host memory";
+            return GF_EINVAL;
+        }
+        c->batch = b;
+        c->p = b->p;
+        c->st = reinterpret_cast<hipStream_t>(stream);
+        s = init_batch(c, *b, d_links, reinterpret_cast<unsigned char*>(d_workspace), c->st);
+        if (s != GF_OK) {
+            g_init_error = c->err;
+            free_ctx(c);
+            return s;
+        }
+        *out = c;
+        return GF_OK;
+    } catch (...) {
+        g_init_error = "unexpected host exception";
+        return GF_EINVAL;
+    }
+}
+
+gf_status gf_fix_until_batch(gf_ctx* c, double tol, int64_t max_iter, gf_result* results) {
+    if (!c) return GF_EINVAL;
+    if (!c->batch) return fail(c, GF_ESTATE, "not a batch context");
+    if (!(tol > 0.0)) return fail(c, GF_EINVAL, "theta_tol must be > 0");
+    if (max_iter < 0) return fail(c, GF_EINVAL, "max_iter must be >= 0");
+    if (!results) return fail(c, GF_EINVAL, "results is NULL");
+    try {
+        const auto t0 = std::chrono::steady_clock::now();
+        BatchState& b = *c->batch;
+        std::vector<BatchOutcome> out(b.n);
+        for (auto& g : b.g) {
+            gf_status s = run_group(c, g, tol, max_iter, out);
+            if (s != GF_OK) return s;
+        }
+        gf_status s = check_hip(c, hipStreamSynchronize(c->st), "sync");
+        if (s != GF_OK) return s;
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        gf_status worst = GF_OK;
+        for (int i = 0; i < b.n; ++i) {
+            results[i] = out[i].r;
+            results[i].seconds = secs;
+            if (out[i].s == GF_ENUMERIC) worst = GF_ENUMERIC;
+            else if (out[i].s == GF_ENOTCONV && worst == GF_OK) worst = GF_ENOTCONV;
+        }
+        if (worst == GF_ENUMERIC) return fail(c, worst, "theta is not finite for at least one configuration");
+        if (worst == GF_ENOTCONV) return fail(c, worst, "max_iter reached before theta < tol for at least one configuration");
+        return GF_OK;
+    } catch (...) {
+        return fail(c, GF_EINVAL, "unexpected host exception");
+    }
+}
+
 gf_status gf_quality(gf_ctx* c, double* theta, double* F) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (!theta || !F) return fail(c, GF_EINVAL, "null output");
     gf_ctx* a = active(c);
     gf_status s = read_head(a);
@@ -1035,6 +1410,7 @@ gf_status gf_quality(gf_ctx* c, double* theta, double* F) {
 
 gf_status gf_get_links(gf_ctx* c, void* d_out) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
     if (c->L.mixed) c = active(c);
     gf_status s = unpack_links(c, reinterpret_cast<double*>(d_out));
@@ -1044,6 +1420,7 @@ gf_status gf_get_links(gf_ctx* c, void* d_out) {
 
 gf_status gf_history(gf_ctx* c, int64_t n, double* h_theta, double* h_F) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (!h_theta || !h_F) return fail(c, GF_EINVAL, "null output");
     if (c->L.mixed) c = active(c);
     gf_status s = read_head(c);
@@ -1064,6 +1441,7 @@ gf_status gf_history(gf_ctx* c, int64_t n, double* h_theta, double* h_F) {
 
 gf_status gf_stage_divergence(gf_ctx* c, void* d_delta) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed) c = active(c);
     if (!d_delta) return fail(c, GF_EINVAL, "d_delta is NULL");
     gf_status s = launch_measure(c);
@@ -1079,6 +1457,7 @@ gf_status gf_stage_divergence(gf_ctx* c, void* d_delta) {
 
 gf_status gf_stage_filter(gf_ctx* c, const void* d_in, void* d_out) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed) c = active(c);
     if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
     if (c->L.fp32) {
@@ -1097,6 +1476,7 @@ gf_status gf_stage_filter(gf_ctx* c, const void* d_in, void* d_out) {
 
 gf_status gf_stage_gauge(gf_ctx* c, const void* d_in, void* d_out) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed) c = active(c);
     if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
     if (c->L.fp32) {
@@ -1115,6 +1495,7 @@ gf_status gf_stage_gauge(gf_ctx* c, const void* d_in, void* d_out) {
 
 gf_status gf_stage_update(gf_ctx* c, const void* d_scaled) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed) c = active(c);
     if (!d_scaled) return fail(c, GF_EINVAL, "null pointer");
     if (c->L.fp32)
@@ -1131,6 +1512,7 @@ gf_status gf_stage_update(gf_ctx* c, const void* d_scaled) {
 
 gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed) {
         for (int i = 0; i < 2; ++i) {
             gf_status s = gf_set_timing(c->child[i], enable);
@@ -1150,6 +1532,7 @@ gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
 
 gf_status gf_kernel_times(gf_ctx* c, int32_t n, double* h_ms_total, int64_t* h_counts) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (!h_ms_total || !h_counts || n < 0 || n > GF_NKERNELS) return fail(c, GF_EINVAL, "bad arguments");
     if (c->L.mixed) {
         double ms[GF_NKERNELS];
@@ -1181,6 +1564,7 @@ const char* gf_last_error(const gf_ctx* c) { return c ? c->err.c_str() : g_init_
 
 gf_status gf_get_gauge(gf_ctx* c, void* d_out) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
     gf_ctx* a = active(c);
     if (!a->Acc) return fail(c, GF_ESTATE, "the accumulated gauge transform is not kept (GF_FLAG_ACCUMULATE_GAUGE)");
@@ -1199,6 +1583,7 @@ gf_status gf_get_gauge(gf_ctx* c, void* d_out) {
 
 gf_status gf_mlp_set_weights(gf_ctx* c, const float* d_params, int32_t enable) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed || !c->mlp) return fail(c, GF_ESTATE, "context was created without GF_FLAG_LEARNED");
     if (enable && !d_params) return fail(c, GF_EINVAL, "d_params is NULL");
     if (d_params) GF_TRY_HIP(c, hipMemcpyAsync(c->mlp, d_params, kMlpParams * sizeof(float), hipMemcpyDeviceToDevice, c->st));
@@ -1210,6 +1595,7 @@ gf_status gf_mlp_set_weights(gf_ctx* c, const float* d_params, int32_t enable) {
 
 gf_status gf_record_spectra(gf_ctx* c, int64_t n, double* d_records, double* h_theta) {
     if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed || !c->rec) return fail(c, GF_ESTATE, "context was created without GF_FLAG_RECORD_SPECTRA");
     if (n < 1 || !d_records || !h_theta) return fail(c, GF_EINVAL, "bad arguments");
     if (n + 1 > kHist) return fail(c, GF_EINVAL, "n too large");

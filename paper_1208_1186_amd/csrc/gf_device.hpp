@@ -220,6 +220,25 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Batch of equally shaped lattices: the buffers of configuration c sit c*cs
+// bytes after those of configuration 0, and blockIdx.y picks the configuration
+// (through the list of active ones when act is set). A single lattice has cs 0.
+struct Batch {
+    const int* act;
+    size_t cs;
+};
+
+__device__ __forceinline__ size_t boff(const Batch& b) {
+    if (b.cs == 0) return 0;
+    const int c = b.act ? b.act[blockIdx.y] : (int)blockIdx.y;
+    return (size_t)c * b.cs;
+}
+
+template <typename P>
+__device__ __forceinline__ P* bshift(P* p, size_t o) {
+    return p ? reinterpret_cast<P*>(reinterpret_cast<uintptr_t>(p) + o) : p;
+}
+
 // ------------------------------------------------------------- reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

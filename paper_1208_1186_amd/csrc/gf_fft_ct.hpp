@@ -20,8 +20,17 @@ template <typename T, int NX, int NY, int G, bool INV>
 __global__ void __launch_bounds__(ct_threads(G * NX * NY, 8))
     k_fft_xy_ct(const cx<T>* src, cx<T>* dst, size_t zps, int nzt, const cx<T>* __restrict__ twgx,
                 const cx<T>* __restrict__ twgy, Ctl* ctl, int force, const double2* __restrict__ part, int npart,
-                double inv3v, double inv12v) {
+                double inv3v, double inv12v, Batch bt) {
     constexpr int RS = NX + 1, E = G * NX * NY, NT = ct_threads(E, 8);
+    {
+        const size_t bo = boff(bt);
+        src = bshift(src, bo);
+        dst = bshift(dst, bo);
+        twgx = bshift(twgx, bo);
+        twgy = bshift(twgy, bo);
+        ctl = bshift(ctl, bo);
+        part = bshift(part, bo);
+    }
     if (part != nullptr && blockIdx.x == 0 && ctl->pending) {
         reduce_partials(part, npart, inv3v, inv12v, ctl, 1);
         __syncthreads();
@@ -56,8 +65,16 @@ __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     k_fft_zt_ct(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, const cx<T>* __restrict__ twgz,
                 const cx<T>* __restrict__ twgt, const T* __restrict__ sin2, T coef, int no_fa,
                 const Ctl* __restrict__ ctl, int force, const T* __restrict__ mtab, TupleGeom tg,
-                cx<T>* __restrict__ spec) {
+                cx<T>* __restrict__ spec, Batch bt) {
     constexpr int TSP = NZ * BX + 1, E = BX * NZ * NTT, NT = ct_threads(E, 8);
+    {
+        const size_t bo = boff(bt);
+        Z = bshift(Z, bo);
+        twgz = bshift(twgz, bo);
+        twgt = bshift(twgt, bo);
+        sin2 = bshift(sin2, bo);
+        ctl = bshift(ctl, bo);
+    }
     if (!force && ctl->done) return;
     __shared__ cx<T> twz[NZ], twt[NTT], buf[NTT * TSP];
     for (int i = threadIdx.x; i < NZ; i += NT) twz[i] = twgz[i];
@@ -124,9 +141,17 @@ template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
     k_fft_xy_gauge_ct(const cx<T>* __restrict__ Q, size_t zps, cx<T>* __restrict__ G, size_t gps,
                       const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
-                      int force) {
+                      int force, Batch bt) {
     constexpr int RS = NX + 1, P = NX * NY, PL = NY * RS, E = 4 * P;
     constexpr int NT = ct_threads(E, gauge_ept(NX, NY));
+    {
+        const size_t bo = boff(bt);
+        Q = bshift(Q, bo);
+        G = bshift(G, bo);
+        twgx = bshift(twgx, bo);
+        twgy = bshift(twgy, bo);
+        ctl = bshift(ctl, bo);
+    }
     if (!force && ctl->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* twx = reinterpret_cast<cx<T>*>(smem);

@@ -204,9 +204,19 @@ __device__ __forceinline__ void reduce_partials(const double2* __restrict__ part
 // mode 0: reduce a standalone measurement of the current links;
 // mode 1: reduce the loop kernel's partials if they are still pending.
 __global__ void __launch_bounds__(256) k_finalize(const double2* __restrict__ part, int n, double inv3v,
-                                                  double inv12v, Ctl* ctl, int mode) {
+                                                  double inv12v, Ctl* ctl, int mode, Batch bt) {
+    const size_t bo = boff(bt);
+    part = bshift(part, bo);
+    ctl = bshift(ctl, bo);
     if (mode == 1 && !ctl->pending) return;
     reduce_partials(part, n, inv3v, inv12v, ctl, mode);
+}
+
+// Copy the leading words of n control blocks (cs bytes apart) into a dense array.
+__global__ void __launch_bounds__(64) k_gather_heads(const unsigned char* __restrict__ ctl0, size_t cs, int words,
+                                                     unsigned long long* __restrict__ out) {
+    const unsigned long long* src = reinterpret_cast<const unsigned long long*>(ctl0 + (size_t)blockIdx.x * cs);
+    for (int i = threadIdx.x; i < words; i += 64) out[(size_t)blockIdx.x * words + i] = src[i];
 }
 
 // Forget a rejected update: the count goes back to k (the links of step k are
@@ -360,7 +370,17 @@ template <typename T, int NE>
 __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> Lin, Links<T, NE> Lout,
                                                                   const cx<T>* __restrict__ G, cx<T>* __restrict__ D,
                                                                   size_t ps, Geom g, double2* __restrict__ part,
-                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g) {
+                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g, Batch bt) {
+    {
+        const size_t bo = boff(bt);
+        Lin.p = bshift(Lin.p, bo);
+        Lout.p = bshift(Lout.p, bo);
+        G = bshift(G, bo);
+        D = bshift(D, bo);
+        part = bshift(part, bo);
+        ctl = bshift(ctl, bo);
+        acc_g = bshift(acc_g, bo);
+    }
     if (ctl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
@@ -502,7 +522,16 @@ __global__ void __launch_bounds__(1024) k_fft_xy(const cx<T>* src, cx<T>* dst, s
                                                  int nzt, int G, int rs, FftPlan px, FftPlan py,
                                                  const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
                                                  Ctl* ctl, int force, const double2* __restrict__ part, int npart,
-                                                 double inv3v, double inv12v) {
+                                                 double inv3v, double inv12v, Batch bt) {
+    {
+        const size_t bo = boff(bt);
+        src = bshift(src, bo);
+        dst = bshift(dst, bo);
+        twgx = bshift(twgx, bo);
+        twgy = bshift(twgy, bo);
+        ctl = bshift(ctl, bo);
+        part = bshift(part, bo);
+    }
     if (part != nullptr && blockIdx.x == 0 && ctl->pending) {
         reduce_partials(part, npart, inv3v, inv12v, ctl, 1);
         __syncthreads();
@@ -544,7 +573,15 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
                                                  const cx<T>* __restrict__ twgz, const cx<T>* __restrict__ twgt,
                                                  const T* __restrict__ sin2, T coef, int no_fa,
                                                  const Ctl* __restrict__ ctl, int force, const T* __restrict__ mtab,
-                                                 TupleGeom tg, cx<T>* __restrict__ spec) {
+                                                 TupleGeom tg, cx<T>* __restrict__ spec, Batch bt) {
+    {
+        const size_t bo = boff(bt);
+        Z = bshift(Z, bo);
+        twgz = bshift(twgz, bo);
+        twgt = bshift(twgt, bo);
+        sin2 = bshift(sin2, bo);
+        ctl = bshift(ctl, bo);
+    }
     if (!force && ctl->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* twz = reinterpret_cast<cx<T>*>(smem);
@@ -606,7 +643,15 @@ __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const c
                                                        cx<T>* __restrict__ G, size_t gps, int nx, int ny, int rs,
                                                        FftPlan px, FftPlan py, const cx<T>* __restrict__ twgx,
                                                        const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
-                                                       int force) {
+                                                       int force, Batch bt) {
+    {
+        const size_t bo = boff(bt);
+        Q = bshift(Q, bo);
+        G = bshift(G, bo);
+        twgx = bshift(twgx, bo);
+        twgy = bshift(twgy, bo);
+        ctl = bshift(ctl, bo);
+    }
     if (!force && ctl->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* twx = reinterpret_cast<cx<T>*>(smem);

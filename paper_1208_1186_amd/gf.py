@@ -58,6 +58,9 @@ def _signatures(lib):
         "gf_init": (i32, [ctypes.POINTER(_P), pp, _P, _P, sz, _P]),
         "gf_iterate": (i32, [_P, i64, pr]),
         "gf_fix_until": (i32, [_P, dbl, i64, pr]),
+        "gf_batch_workspace_bytes": (sz, [i32, _P]),
+        "gf_init_batch": (i32, [ctypes.POINTER(_P), i32, _P, _P, _P, sz, _P]),
+        "gf_fix_until_batch": (i32, [_P, dbl, i64, _P]),
         "gf_quality": (i32, [_P, pd, pd]),
         "gf_get_links": (i32, [_P, _P]),
         "gf_get_gauge": (i32, [_P, _P]),
@@ -155,6 +158,37 @@ def gf_fix_until(ctx, tol, max_iter):
     st = _check(ctx, load().gf_fix_until(ctx, float(tol), int(max_iter), ctypes.byref(r)),
                 allow=(GF_OK, GF_ENOTCONV))
     return st, r
+
+
+def _params_array(params):
+    arr = (gf_params * len(params))()
+    for i, p in enumerate(params):
+        arr[i] = p
+    return arr
+
+
+def gf_batch_workspace_bytes(params):
+    arr = _params_array(params)
+    return load().gf_batch_workspace_bytes(len(params), ctypes.cast(arr, _P))
+
+
+def gf_init_batch(params, d_links, d_workspace, workspace_bytes, stream=0):
+    """params: sequence of gf_params; d_links: sequence of device pointers (canonical links)."""
+    arr = _params_array(params)
+    ptrs = (_P * len(params))(*[_P(int(p)) for p in d_links])
+    ctx = _P()
+    st = load().gf_init_batch(ctypes.byref(ctx), len(params), ctypes.cast(arr, _P), ctypes.cast(ptrs, _P),
+                              _P(d_workspace), workspace_bytes, _P(stream))
+    if st != GF_OK:
+        raise GfError(st, gf_last_error(None))
+    return ctx
+
+
+def gf_fix_until_batch(ctx, tol, max_iter, n):
+    res = (gf_result * n)()
+    st = _check(ctx, load().gf_fix_until_batch(ctx, float(tol), int(max_iter), ctypes.cast(res, _P)),
+                allow=(GF_OK, GF_ENOTCONV))
+    return st, list(res)
 
 
 def gf_quality(ctx):
@@ -362,6 +396,51 @@ class GaugeFixer:
             out = torch.empty(self.links.shape[:4] + (3, 3), dtype=torch.complex128, device=self.links.device)
         gf_get_gauge(self.ctx, out.data_ptr())
         return out
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            gf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchFixer:
+    """Owns a libgf batch context over a list of complex128 CUDA link tensors of any supported shapes.
+
+    fix_until() drives every lattice to theta < tol and writes the results back into the tensors.
+    """
+
+    def __init__(self, links_list, precision="mixed", alpha=0.08, check_every=10, switch_theta=1e-8, flags=0,
+                 stream=None):
+        import torch
+        if len(links_list) == 0:
+            raise ValueError("empty batch")
+        self.links = list(links_list)
+        self.params = []
+        for t in self.links:
+            if not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous() or t.dim() != 7:
+                raise ValueError("every lattice must be a contiguous complex128 CUDA tensor (Nt, Nz, Ny, Nx, 4, 3, 3)")
+            nt, nz, ny, nx = t.shape[:4]
+            self.params.append(make_params((nx, ny, nz, nt), precision, alpha, switch_theta, check_every, flags))
+        nbytes = gf_batch_workspace_bytes(self.params)
+        if nbytes == 0:
+            raise GfError(GF_EINVAL, "invalid batch parameters")
+        dev = self.links[0].device
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.ctx = gf_init_batch(self.params, [t.data_ptr() for t in self.links], base + off, nbytes,
+                                 self.stream.cuda_stream)
+
+    def fix_until(self, tol=1e-15, max_iter=100000):
+        st, rs = gf_fix_until_batch(self.ctx, tol, max_iter, len(self.links))
+        return st, [_res(GF_OK, r) for r in rs]
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -27,6 +27,8 @@ array axis ``3 - mu``; site index s = x + Nx * (y + Ny * (z + Nz * t)).
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 EPS_P059 = 0.4395
@@ -115,6 +117,33 @@ def batch_shapes(n=64, seed=64):
     """Shapes of the uneven batch: indices drawn uniformly from BATCH_SHAPES."""
     idx = np.random.default_rng(seed).integers(0, len(BATCH_SHAPES), n)
     return [BATCH_SHAPES[i] for i in idx]
+
+
+BATCH_SEED0 = 1000  # configuration i of the uneven batch uses seed BATCH_SEED0 + i
+
+
+def _make_one(args):
+    dims, seed, eps = args
+    return make_config(dims, seed, eps)
+
+
+def make_configs(shapes, seeds, eps=EPS_P059, workers=None):
+    """make_config over many (shape, seed) pairs, in worker processes when workers > 1."""
+    jobs = [(tuple(d), int(s), eps) for d, s in zip(shapes, seeds)]
+    workers = min(16, os.cpu_count() or 1) if workers is None else workers
+    if workers <= 1 or len(jobs) < 2:
+        return [_make_one(j) for j in jobs]
+    import concurrent.futures
+    import multiprocessing
+    ctx = multiprocessing.get_context("spawn")  # no fork of a process that may hold a GPU context
+    with concurrent.futures.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        return list(ex.map(_make_one, jobs))
+
+
+def batch_configs(n=64, seed=64, workers=None):
+    """The uneven batch: (shapes, configurations) with configuration i seeded BATCH_SEED0 + i."""
+    shapes = batch_shapes(n, seed)
+    return shapes, make_configs(shapes, [BATCH_SEED0 + i for i in range(n)], workers=workers)
 
 
 def to_canonical(u):

@@ -75,3 +75,47 @@ def test_workspace_scales_with_precision(lib):
         sizes[prec] = lib.gf_workspace_bytes(ctypes.byref(gf.make_params((16, 16, 16, 16), prec)))
     assert sizes["fp64_18"] > sizes["fp64_12"] > sizes["fp32_12"]
     assert sizes["fp64_18"] > sizes["fp32_18"] > sizes["fp32_12"]
+
+
+def _batch_init(lib, params, ws=256, nbytes=1 << 40, links=256):
+    arr = gf._params_array(params)
+    ptrs = (gf._P * len(params))(*[gf._P(links)] * len(params))
+    ctx = gf._P()
+    st = lib.gf_init_batch(ctypes.byref(ctx), len(params), ctypes.cast(arr, gf._P), ctypes.cast(ptrs, gf._P),
+                           gf._P(ws), nbytes, None)
+    return st, ctx
+
+
+def test_batch_workspace_grows_with_members(lib):
+    a = [gf.make_params((8, 8, 8, 8), "mixed")]
+    b = a + [gf.make_params((12, 12, 12, 12), "mixed")]
+    c = b + [gf.make_params((8, 8, 8, 8), "mixed")]
+    na, nb, nc = (gf.gf_batch_workspace_bytes(x) for x in (a, b, c))
+    assert 0 < na < nb < nc
+    # a batch of one holds at least what the single context needs
+    assert na >= lib.gf_workspace_bytes(ctypes.byref(a[0]))
+
+
+def test_batch_rejects_bad_parameters_before_device(lib):
+    ok = gf.make_params((8, 8, 8, 8), "mixed")
+    bad_sets = [
+        [ok, gf.make_params((8, 8, 8, 8), "fp64_18")],                      # precisions differ
+        [ok, gf.make_params((8, 8, 8, 8), "mixed", alpha=0.1)],             # alpha differs
+        [gf.make_params((8, 8, 8, 8), "mixed", flags=gf.FLAG_LEARNED)],     # learned not in batches
+        [gf.make_params((8, 8, 8, 8), "fp64_18", flags=gf.FLAG_RECORD_SPECTRA)],
+        [gf.make_params((8, 8, 8, 8), "mixed", switch_theta=0.0)],
+    ]
+    for params in bad_sets:
+        assert gf.gf_batch_workspace_bytes(params) == 0
+        st, ctx = _batch_init(lib, params)
+        assert st == gf.GF_EINVAL and not ctx.value
+        assert gf.gf_last_error(None)
+    st, ctx = _batch_init(lib, [ok, gf.make_params((8, 8, 8, 10), "mixed")])
+    assert st == gf.GF_ENOTSUP and not ctx.value
+    need = gf.gf_batch_workspace_bytes([ok])
+    assert _batch_init(lib, [ok], nbytes=need - 1)[0] == gf.GF_EINVAL
+    assert _batch_init(lib, [ok], ws=264, nbytes=need)[0] == gf.GF_EINVAL
+    assert _batch_init(lib, [ok], links=0, nbytes=need)[0] == gf.GF_EINVAL
+    ctx = gf._P()
+    assert lib.gf_init_batch(ctypes.byref(ctx), 0, None, None, gf._P(256), 1 << 40, None) == gf.GF_EINVAL
+    assert lib.gf_fix_until_batch(None, 1e-15, 10, None) == gf.GF_EINVAL
