@@ -163,6 +163,21 @@ gf_status gf_get_links(gf_ctx* ctx, void* d_out);
 gf_status gf_get_gauge(gf_ctx* ctx, void* d_out);
 
 /*
+ * Checkpoint and resume. gf_get_state writes the complete state of a context
+ * (links, iteration count, theta/F history, precision phase, accumulated
+ * gauge, network parameters) to the device buffer d_out of at least
+ * gf_state_bytes(ctx) bytes; gf_set_state restores it into a context created
+ * with the same gf_params (else GF_EINVAL, nothing changed) and writes the
+ * restored links to that context's d_links. Continuing after a restore gives
+ * bitwise the same iterates as never stopping. The buffer is opaque and is
+ * only meant for the same build of libgf. Not for batch contexts (0 bytes,
+ * GF_ESTATE).
+ */
+size_t gf_state_bytes(const gf_ctx* ctx);
+gf_status gf_get_state(gf_ctx* ctx, void* d_out, size_t bytes);
+gf_status gf_set_state(gf_ctx* ctx, const void* d_in, size_t bytes);
+
+/*
  * Copy the last n recorded (theta_k, F_k) pairs, k = iters-n+1 .. iters, into
  * host arrays (n <= 16384 and n <= iters + 1). GF_MIXED: the history of the
  * active phase, counted from the start of that phase.
@@ -238,23 +253,29 @@ gf_status gf_record_spectra(gf_ctx* ctx, int64_t n, double* d_records, double* h
 /*
  * Training (no lattice context). Rows are momentum tuples of samples; sample
  * s owns rows [offsets[s], offsets[s+1]) of x (6 floats per row, the features
- * above) and tgt (m0, P, kappa per row), its first row being the zero tuple.
- * Loss = mean over samples of sum_p P (1 - m kappa)^2 / sum_p P with
- * m = m0 exp(o_s + o_a(first row)). All pointers are device pointers except
+ * above) and tgt (a, b, c per row, from gf_mlp_make_samples), its first row
+ * being the zero tuple. With s(p) = exp(o_s(p) + o_a(first row)) the factor
+ * on the plain multiplier, the predicted residual energy ratio of a sample
+ * after the scaled step is R = sum_p (a - 2 s b + s^2 c) / sum_p a; its loss
+ * is ln(max(R, 1e-12)) (zero gradient below), and the loss is the mean over
+ * samples: the predicted mean log-decrease per step. All pointers are device pointers except
  * h_loss (host, may be NULL); d_ws holds gf_mlp_workspace_bytes(n_rows,
  * n_samples) bytes. Adam: beta1 0.9, beta2 0.999, eps 1e-8, step from 1.
  */
 size_t gf_mlp_workspace_bytes(int64_t n_rows, int32_t n_samples);
 /*
- * Training rows from records of gf_record_spectra: for sample s (record of
- * step d_k[s] with quality d_theta[s]) and tuple i, row s*T + i of d_x gets
- * the features and of d_tgt (m0, P, kappa), m0 = (alpha/2) p2max/p^2 and
- * kappa = (1 - C/P)/m0 clipped to [1e-3, 1e3] (1 where P or m0 is 0).
- * dims: host array {Nx, Ny, Nz, Nt}; T = prod(N_mu/2 + 1).
+ * Training rows from n_records consecutive records of gf_record_spectra
+ * (d_theta[r] = theta of record r, iteration k0 + r). Sample s uses record
+ * r = first + s*every and record r + 1 (so r <= n_records - 2, else
+ * GF_EINVAL): row s*T + i of d_x gets the features of tuple i at
+ * (theta_r, k0 + r), and of d_tgt (a, b, c) = (P_r, P_r - C_r,
+ * P_r - 2 C_r + P_{r+1}), i.e. the energy of mode i, its change along the
+ * plain step, and the squared size of that change. dims: host array
+ * {Nx, Ny, Nz, Nt}; T = prod(N_mu/2 + 1).
  */
-gf_status gf_mlp_make_samples(const double* d_records, const double* d_theta, const int32_t* d_k,
-                              int32_t n_samples, const int32_t* dims, double alpha, float* d_x,
-                              float* d_tgt, void* stream);
+gf_status gf_mlp_make_samples(const double* d_records, int32_t n_records, const double* d_theta,
+                              int32_t first, int32_t every, int32_t n_samples, int64_t k0,
+                              const int32_t* dims, float* d_x, float* d_tgt, void* stream);
 gf_status gf_mlp_forward(const float* d_params, const float* d_x, int64_t n_rows, float* d_out,
                          void* d_ws, size_t ws_bytes, void* stream);
 gf_status gf_mlp_loss_grad(const float* d_params, const float* d_x, const float* d_tgt,

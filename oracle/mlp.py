@@ -12,14 +12,22 @@ Features of a tuple (p^2_0..p^2_3 = 4 sin^2(pi n_mu / N_mu)) at iteration k
 with quality theta_k: (p^2_mu / 4 - 1/2 for mu = 0..3, log10(theta_k)/8 + 1,
 k / 64).
 
-Training signal (recorded on plain-FA trajectories): per mode,
-P_k(p) = sum_f |Z_f^k(p)|^2 and C_k(p) = sum_f Re[Z_f^{k+1}(p) conj(Z_f^k(p))]
-over the four packed divergence fields Z_f after the forward 4D FFT,
-summed over the +-p reflections of the tuple. The observed response is
-kappa_k(p) = (1 - C_k/P_k) / m0(p) (clipped to [1e-3, 1e3]), and the loss of
-one sample (trajectory, k) is the predicted next-step residual energy
-    L = sum_p P_k(p) (1 - m(p) kappa_k(p))^2 / sum_p P_k(p),
-minimised by m(p) kappa(p) = 1. Parameter vector layout (float32 on the GPU):
+Training signal (recorded on plain-FA trajectories): per mode p (a tuple
+folded over its +-n reflections) and iteration k, over the four packed
+divergence fields Z_f after the forward 4D FFT,
+    P_k(p) = sum_f |Z_f^k(p)|^2,   C_k(p) = sum_f Re[Z_f^{k+1}(p) conj(Z_f^k(p))].
+A plain step changes mode p by R = Z^k - Z^{k+1}. Scaling the step of mode p
+by s(p) = m(p)/m0(p) = exp(o_s(p) + o_a(0)) leaves, to first order in the step
+and for s varying slowly with p, the residual Z^k - s R, whose energy is
+    a - 2 s b + s^2 c,   a = P_k,  b = P_k - C_k,  c = P_k - 2 C_k + P_{k+1}
+(c = |R|^2 >= 0). The predicted residual ratio of one sample (trajectory, k)
+is that energy summed over the modes and divided by sum_p P_k, and the loss of
+the sample is its natural logarithm (floored at ln 1e-12, where the gradient
+is zero): the mean over samples is then the predicted mean log-decrease per
+step, whose inverse sets the number of steps to a tolerance. With zero
+outputs (s = 1) the ratio equals the plain step's own sum P_{k+1} / sum P_k;
+per mode it is least at s = b / c. For a response that is diagonal in p (the
+free field) c = b^2 / a and the minimiser is the per-mode inverse response. Parameter vector layout (float32 on the GPU):
 W1 (64x6), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2).
 """
 from __future__ import annotations
@@ -29,7 +37,6 @@ import itertools
 import numpy as np
 
 SIZES = (6, 64, 64, 2)
-KAPPA_CLIP = (1e-3, 1e3)
 
 
 def n_params():
@@ -94,15 +101,28 @@ def multipliers(theta, x, m0):
     return m0 * np.exp(o[:, 0] + o[0, 1])
 
 
-def sample_loss(theta, x, m0, power, kappa):
-    m = multipliers(theta, x, m0)
-    r = 1.0 - m * kappa
-    return float(np.sum(power * r * r) / np.sum(power))
+def scales(theta, x):
+    """s(p) = exp(o_s(p) + o_a(row 0)): the factor the network puts on the plain multiplier of each tuple."""
+    _, _, o = forward(theta, x)
+    return np.exp(o[:, 0] + o[0, 1])
+
+
+RATIO_FLOOR = 1e-12
+
+
+def sample_ratio(theta, x, a, b, c):
+    """Predicted residual energy ratio of the scaled step."""
+    s = scales(theta, x)
+    return float(np.sum(a - 2.0 * s * b + s * s * c) / np.sum(a))
+
+
+def sample_loss(theta, x, a, b, c):
+    return float(np.log(max(sample_ratio(theta, x, a, b, c), RATIO_FLOOR)))
 
 
 def loss(theta, samples):
-    """Mean sample loss; samples = list of (x, m0, power, kappa)."""
-    return float(np.mean([sample_loss(theta, *s) for s in samples]))
+    """Mean sample loss; samples = list of (x, a, b, c)."""
+    return float(np.mean([sample_loss(theta, *smp) for smp in samples]))
 
 
 def loss_grad(theta, samples):
@@ -111,15 +131,17 @@ def loss_grad(theta, samples):
     g = [np.zeros_like(w1), np.zeros_like(b1), np.zeros_like(w2), np.zeros_like(b2), np.zeros_like(w3),
          np.zeros_like(b3)]
     ns = len(samples)
-    for x, m0, power, kappa in samples:
+    for x, a, b, c in samples:
         h1, h2, o = forward(theta, x)
-        m = m0 * np.exp(o[:, 0] + o[0, 1])
-        r = 1.0 - m * kappa
-        # dL/dm = -2 P r kappa / sum P ; dm/do_s(p) = m(p) ; dm/do_a(0) = m(p) for every p
-        dm = -2.0 * power * r * kappa / np.sum(power) / ns
+        s = np.exp(o[:, 0] + o[0, 1])
+        energy = np.sum(a - 2.0 * s * b + s * s * c)
+        if energy / np.sum(a) <= RATIO_FLOOR:
+            continue
+        # d ln(energy)/ds = (2 s c - 2 b) / energy ; ds/do_s(p) = s(p) ; ds/do_a(0) = s(p) for every p
+        ds = (2.0 * s * c - 2.0 * b) / energy / ns
         do = np.zeros_like(o)
-        do[:, 0] = dm * m
-        do[0, 1] = np.sum(dm * m)
+        do[:, 0] = ds * s
+        do[0, 1] = np.sum(ds * s)
         g[4] += do.T @ h2
         g[5] += do.sum(axis=0)
         dz2 = (do @ w3) * (1.0 - h2 * h2)
@@ -168,8 +190,6 @@ def record(spec_k, spec_k1, dims, tuples):
     return fold(p, dims, tuples), fold(c, dims, tuples)
 
 
-def kappa_from(power, corr, m0):
-    with np.errstate(divide="ignore", invalid="ignore"):
-        k = (1.0 - corr / power) / m0
-    k = np.where((power > 0) & (m0 > 0) & np.isfinite(k), k, 1.0)
-    return np.clip(k, *KAPPA_CLIP)
+def targets(p_k, c_k, p_next):
+    """Per-tuple loss coefficients (a, b, c) from P_k, C_k and P_{k+1}."""
+    return p_k, p_k - c_k, p_k - 2.0 * c_k + p_next

@@ -152,8 +152,10 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2], nt = L.n[3];
     // (x, y) pass: G planes per block, enough work per block, never straddling a field.
     const int nzt = nz * nt;
+    // (measured at 32x32: two planes per block beat one and four)
+    const int want = nx * ny >= 1024 ? 2048 : 512;
     L.G = 1;
-    while (L.G * 2 <= nzt && nzt % (L.G * 2) == 0 && L.G * nx * ny < 512) L.G *= 2;
+    while (L.G * 2 <= nzt && nzt % (L.G * 2) == 0 && L.G * nx * ny < want) L.G *= 2;
     L.rs = nx + 1;
     const int EA = L.G * nx * ny;
     L.thrA = std::min(1024, std::max(64, round64((EA + kEPT - 1) / kEPT)));
@@ -382,7 +384,7 @@ const cx<T>* twp(gf_ctx* c, int d) {
 
 // Shapes with compile-time FFT kernels: (Nx, Ny, G) for the (x, y) passes,
 // (Nz, Nt, bx) for the (z, t) pass at each precision, (Nx, Ny) for the gauge pass.
-#define GF_XY_CASES(X) X(8, 8, 8) X(12, 12, 4) X(16, 16, 2) X(24, 24, 1) X(32, 32, 1) X(48, 48, 1)
+#define GF_XY_CASES(X) X(8, 8, 8) X(12, 12, 4) X(16, 16, 2) X(24, 24, 1) X(32, 32, 2) X(48, 48, 1)
 #define GF_ZT_CASES_F64(X) \
     X(8, 8, 8) X(12, 12, 4) X(16, 16, 8) X(24, 8, 8) X(32, 4, 8) X(48, 8, 8) X(32, 32, 4) X(32, 64, 2)
 #define GF_ZT_CASES_F32(X) \
@@ -698,32 +700,35 @@ void stage_spectral(gf_ctx* c, bool gauge) {
 
 constexpr int kMaxRejects = 3;  // consecutive rejected learned steps before the network is switched off
 
-// One learned step from k with the acceptance test: if theta grows or F
-// drops, the step is undone (the links of step k are still in Lb[k & 1]) and
-// a plain Fourier-accelerated step is taken instead.
-gf_status learned_step(gf_ctx* c) {
-    const long long k0 = c->k_host;
-    const double th0 = c->h_head->theta, f0 = c->h_head->F;
+gf_status set_guard(gf_ctx* c, int on) {
+    hipLaunchKernelGGL(k_set_guard, dim3(1), dim3(64), 0, c->st, c->ctl, on);
+    return launched(c, "set_guard launch");
+}
+
+// Up to n learned updates under the device guard: the reduction that follows
+// an update stops the loop if theta grew, F dropped or theta is not finite.
+// A stopped update is undone (the links before it are still in the other
+// link buffer), theta and F are measured again and a plain Fourier-
+// accelerated update is taken in its place.
+gf_status learned_chunk(gf_ctx* c, int64_t n) {
+    gf_status s = set_guard(c, 1);
     c->net_this = true;
-    gf_status s = one_iteration(c, k0);
+    for (int64_t i = 0; i < n && s == GF_OK; ++i) s = one_iteration(c, c->k_host + i);
     c->net_this = false;
     if (s == GF_OK) s = loop_finalize(c);
     if (s == GF_OK) s = read_head(c);
     if (s != GF_OK) return s;
-    if (c->h_head->done && c->h_head->numeric == 0 && c->h_head->theta < th0) {
-        c->rejects = 0;
-        return GF_OK;
-    }
-    const bool worse = c->h_head->numeric || !(c->h_head->theta <= th0) || c->h_head->F < f0 - 1e-14;
-    if (!worse) {
+    if (!c->h_head->rejected) {
         c->rejects = 0;
         return GF_OK;
     }
     ++c->fallbacks;
     if (++c->rejects >= kMaxRejects) c->net_on = false;
+    const long long k0 = c->h_head->iters - 1;
     hipLaunchKernelGGL(k_rollback, dim3(1), dim3(64), 0, c->st, c->ctl, k0);
     c->k_host = k0;
     s = launched(c, "rollback launch");
+    if (s == GF_OK) s = set_guard(c, 0);
     if (s == GF_OK) s = launch_measure(c);
     if (s == GF_OK) s = read_head(c);
     if (s == GF_OK && !c->h_head->done) s = one_iteration(c, k0);
@@ -739,13 +744,13 @@ gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r, bool u
     if (s != GF_OK) return s;
     const long long start = c->h_head->iters;
     while (!c->h_head->done && c->h_head->iters - start < max_iter) {
+        const int64_t left = max_iter - (c->h_head->iters - start);
+        const int64_t k = std::min<int64_t>(left, c->p.check_every);
         if (c->net_on) {
-            s = learned_step(c);
+            s = learned_chunk(c, k);
             if (s != GF_OK) return s;
             continue;
         }
-        const int64_t left = max_iter - (c->h_head->iters - start);
-        const int64_t k = std::min<int64_t>(left, c->p.check_every);
         for (int64_t i = 0; i < k && s == GF_OK; ++i) s = one_iteration(c, c->k_host + i);
         if (s == GF_OK) s = loop_finalize(c);
         if (s == GF_OK) s = read_head(c);
@@ -935,6 +940,51 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     return GF_OK;
 }
 
+
+// ------------------------------------------------------------- checkpoints
+// A saved state is this header followed by a copy of the whole workspace
+// (control block, history, tables, fields, both link buffers, accumulated
+// gauge, network parameters), which holds no device addresses; it restores
+// into any context made with the same parameters.
+constexpr uint64_t kStateMagic = 0x3154415453464755ull;  // "UGFSTAT1"
+constexpr size_t kStateHead = 256;
+
+struct StateHeader {
+    uint64_t magic;
+    uint64_t total;
+    int32_t dims[4];
+    int32_t precision;
+    uint32_t flags;
+    int64_t k_host[3];  // this context, float child, double child
+    int32_t phase, net_on, rejects, fallbacks;
+};
+static_assert(sizeof(StateHeader) <= kStateHead, "state header too large");
+
+StateHeader state_header(const gf_ctx* c) {
+    StateHeader h{};
+    h.magic = kStateMagic;
+    h.total = c->L.total;
+    std::copy(c->p.dims, c->p.dims + 4, h.dims);
+    h.precision = c->p.precision;
+    h.flags = c->p.flags;
+    h.k_host[0] = c->k_host;
+    for (int i = 0; i < 2; ++i) h.k_host[1 + i] = c->child[i] ? c->child[i]->k_host : 0;
+    h.phase = c->phase;
+    h.net_on = c->net_on ? 1 : 0;
+    h.rejects = c->rejects;
+    h.fallbacks = c->fallbacks;
+    return h;
+}
+
+void restore_header(gf_ctx* c, const StateHeader& h) {
+    c->k_host = h.k_host[0];
+    for (int i = 0; i < 2; ++i)
+        if (c->child[i]) c->child[i]->k_host = h.k_host[1 + i];
+    c->phase = h.phase;
+    c->net_on = h.net_on != 0;
+    c->rejects = h.rejects;
+    c->fallbacks = h.fallbacks;
+}
 
 // ----------------------------------------------------------------- batches
 // Independent lattices of one shape form a group. A group's configurations
@@ -1231,6 +1281,7 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
             c->L = L;
             c->st = st;
             c->links_user = links;
+            c->ws = ws;
             c->phase = 0;
             for (int i = 0; i < 2 && s == GF_OK; ++i) {
                 c->child[i] = new (std::nothrow) gf_ctx();
@@ -1416,6 +1467,45 @@ gf_status gf_get_links(gf_ctx* c, void* d_out) {
     gf_status s = unpack_links(c, reinterpret_cast<double*>(d_out));
     if (s != GF_OK) return s;
     return check_hip(c, hipStreamSynchronize(c->st), "sync");
+}
+
+size_t gf_state_bytes(const gf_ctx* c) {
+    if (!c || c->batch) return 0;
+    return kStateHead + c->L.total;
+}
+
+gf_status gf_get_state(gf_ctx* c, void* d_out, size_t bytes) {
+    if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
+    if (bytes < gf_state_bytes(c)) return fail(c, GF_EINVAL, "state buffer too small");
+    StateHeader h = state_header(c);
+    unsigned char* o = reinterpret_cast<unsigned char*>(d_out);
+    GF_TRY_HIP(c, hipMemcpyAsync(o, &h, sizeof(h), hipMemcpyHostToDevice, c->st));
+    GF_TRY_HIP(c, hipMemcpyAsync(o + kStateHead, c->ws, c->L.total, hipMemcpyDeviceToDevice, c->st));
+    return check_hip(c, hipStreamSynchronize(c->st), "sync");  // h must outlive the copy
+}
+
+gf_status gf_set_state(gf_ctx* c, const void* d_in, size_t bytes) {
+    if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    if (!d_in) return fail(c, GF_EINVAL, "d_in is NULL");
+    if (bytes < gf_state_bytes(c)) return fail(c, GF_EINVAL, "state buffer too small");
+    const unsigned char* in = reinterpret_cast<const unsigned char*>(d_in);
+    StateHeader h{};
+    GF_TRY_HIP(c, hipMemcpyAsync(&h, in, sizeof(h), hipMemcpyDeviceToHost, c->st));
+    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    const StateHeader mine = state_header(c);
+    if (h.magic != kStateMagic || h.total != mine.total || h.precision != mine.precision || h.flags != mine.flags ||
+        !std::equal(h.dims, h.dims + 4, mine.dims))
+        return fail(c, GF_EINVAL, "state was not saved from a context with these parameters");
+    GF_TRY_HIP(c, hipMemcpyAsync(c->ws, in + kStateHead, c->L.total, hipMemcpyDeviceToDevice, c->st));
+    restore_header(c, h);
+    gf_ctx* a = active(c);
+    gf_status st = read_head(a);
+    if (st == GF_OK) st = unpack_links(a, c->links_user);
+    if (st == GF_OK) st = check_hip(a, hipStreamSynchronize(a->st), "sync");
+    return st == GF_OK ? GF_OK : fail(c, st, a->err);
 }
 
 gf_status gf_history(gf_ctx* c, int64_t n, double* h_theta, double* h_F) {
@@ -1753,10 +1843,12 @@ gf_status gf_mlp_train_step(float* d_params, float* d_m, float* d_v, int64_t ste
 
 int32_t gf_mlp_param_count(void) { return kMlpParams; }
 
-gf_status gf_mlp_make_samples(const double* d_records, const double* d_theta, const int32_t* d_k, int32_t n_samples,
-                              const int32_t* dims, double alpha, float* d_x, float* d_tgt, void* stream) {
-    if (!d_records || !d_theta || !d_k || !dims || !d_x || !d_tgt || n_samples < 1 || !(alpha > 0.0))
+gf_status gf_mlp_make_samples(const double* d_records, int32_t n_records, const double* d_theta, int32_t first,
+                              int32_t every, int32_t n_samples, int64_t k0, const int32_t* dims, float* d_x,
+                              float* d_tgt, void* stream) {
+    if (!d_records || !d_theta || !dims || !d_x || !d_tgt || n_samples < 1 || every < 1 || first < 0 || k0 < 0)
         return GF_EINVAL;
+    if ((int64_t)first + (int64_t)(n_samples - 1) * every > (int64_t)n_records - 2) return GF_EINVAL;
     TupleGeom tg;
     tg.count = 1;
     for (int d = 0; d < 4; ++d) {
@@ -1767,8 +1859,8 @@ gf_status gf_mlp_make_samples(const double* d_records, const double* d_theta, co
     }
     const int64_t nrows = (int64_t)n_samples * tg.count;
     hipLaunchKernelGGL(k_make_samples, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
-                       reinterpret_cast<hipStream_t>(stream), d_records, d_theta, d_k, nrows, tg, 0.5 * alpha * 16.0,
-                       d_x, d_tgt);
+                       reinterpret_cast<hipStream_t>(stream), d_records, d_theta, first, every, (long long)k0, nrows,
+                       tg, d_x, d_tgt);
     return mlp_status(hipGetLastError(), "make samples");
 }
 

@@ -160,31 +160,31 @@ __device__ __forceinline__ su3<T> g_from_packed(cx<T> z0, cx<T> z1, cx<T> z2, cx
 }
 
 // ------------------------------------------------------------ link storage
-// Structure-of-arrays links: plane (mu*NE + 3*row + col) holds one complex
-// entry of U_mu for every site, planes pstride elements apart. NE = 9 stores
-// the full matrix, NE = 6 rows 1-2 only.
+// Structure-of-arrays links: entry (mu*NE + 3*row + col) of U_mu is a plane of
+// ps elements, one per site. NE = 9 stores the full matrix, NE = 6 rows 1-2
+// only. (Cutting the planes into tiles of 16..256 sites, so that a block's
+// links form one contiguous run, measured no faster.)
 template <typename T, int NE>
 struct Links {
     cx<T>* p;
     size_t ps;
 
+    __device__ __forceinline__ size_t at(int mu, int k, size_t s) const { return (size_t)(mu * NE + k) * ps + s; }
     __device__ __forceinline__ su3<T> load(int mu, size_t s) const {
         su3<T> u;
-        const cx<T>* b = p + (size_t)(mu * NE) * ps + s;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = b[(size_t)k * ps];
+        for (int k = 0; k < 6; ++k) u.e[k / 3][k % 3] = p[at(mu, k, s)];
         if constexpr (NE == 9) {
 #pragma unroll
-            for (int k = 6; k < 9; ++k) u.e[2][k % 3] = b[(size_t)k * ps];
+            for (int k = 6; k < 9; ++k) u.e[2][k % 3] = p[at(mu, k, s)];
         } else {
             third_row(u.e[0], u.e[1], u.e[2]);
         }
         return u;
     }
     __device__ __forceinline__ void store(int mu, size_t s, const su3<T>& u) const {
-        cx<T>* b = p + (size_t)(mu * NE) * ps + s;
 #pragma unroll
-        for (int k = 0; k < NE; ++k) b[(size_t)k * ps] = u.e[k / 3][k % 3];
+        for (int k = 0; k < NE; ++k) p[at(mu, k, s)] = u.e[k / 3][k % 3];
     }
 };
 
@@ -281,6 +281,8 @@ struct Ctl {
     int done;         // theta < tol reached: later kernels of the loop return at once
     int numeric;      // theta was not finite
     int pending;      // block partials of the loop kernel not yet reduced
+    int guard;        // stop (rejected = 1) when an update raises theta, lowers F or is not finite
+    int rejected;     // the last update was stopped by the guard
     int reserved;
     double hist_theta[kHist];
     double hist_F[kHist];

@@ -57,10 +57,9 @@ __global__ void __launch_bounds__(kSiteThreads) k_unpack(Links<T, NE> L, double*
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         su3<double> u;
-        const cx<T>* b = L.p + (size_t)(mu * NE) * L.ps + s;
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
-            cx<T> e = b[(size_t)k * L.ps];
+            cx<T> e = L.p[L.at(mu, k, s)];
             u.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
         }
         if constexpr (NE == 6) third_row(u.e[0], u.e[1], u.e[2]);
@@ -186,13 +185,17 @@ __device__ __forceinline__ void reduce_partials(const double2* __restrict__ part
     if (threadIdx.x == 0) {
         const double F = ra[0] * inv12v, th = rb[0] * inv3v;
         const long long k = ctl->iters + (advance ? 1 : 0);
+        const bool worse = advance && ctl->guard && (!isfinite(th) || th > ctl->theta || F < ctl->F - 1e-14);
         ctl->iters = k;
         ctl->pending = 0;
         ctl->F = F;
         ctl->theta = th;
         ctl->hist_theta[k % kHist] = th;
         ctl->hist_F[k % kHist] = F;
-        if (!isfinite(th)) {
+        if (worse) {
+            ctl->rejected = 1;
+            ctl->done = 1;
+        } else if (!isfinite(th)) {
             ctl->numeric = 1;
             ctl->done = 1;
         } else if (th < ctl->tol) {
@@ -226,6 +229,14 @@ __global__ void k_rollback(Ctl* ctl, long long k) {
         ctl->iters = k;
         ctl->done = 0;
         ctl->pending = 0;
+        ctl->rejected = 0;
+    }
+}
+
+__global__ void k_set_guard(Ctl* ctl, int on) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        ctl->guard = on;
+        ctl->rejected = 0;
     }
 }
 
@@ -400,7 +411,6 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
         const int64_t sb = cm == 0 ? s + (int64_t)(nm - 1) * sm : s - sm;
         // every load first
         su3<T> g0, gfw, gb, u, ub;
-        const cx<T>* lp = Lin.p + (size_t)(mu * NE) * ps;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
             g0.e[k / 3][k % 3] = G[(size_t)k * ps + s];
@@ -409,8 +419,8 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
         }
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
-            u.e[k / 3][k % 3] = lp[(size_t)k * ps + s];
-            ub.e[k / 3][k % 3] = lp[(size_t)k * ps + sb];
+            u.e[k / 3][k % 3] = Lin.p[Lin.at(mu, k, s)];
+            ub.e[k / 3][k % 3] = Lin.p[Lin.at(mu, k, sb)];
         }
         third_row(g0.e[0], g0.e[1], g0.e[2]);
         third_row(gfw.e[0], gfw.e[1], gfw.e[2]);

@@ -23,6 +23,7 @@ namespace gf {
 
 constexpr int kMlpIn = 6, kMlpH = 64, kMlpOut = 2;
 constexpr int kMlpParams = kMlpH * kMlpIn + kMlpH + kMlpH * kMlpH + kMlpH + kMlpOut * kMlpH + kMlpOut;
+constexpr double kRatioFloor = 1e-12;  // the training loss is ln(max(predicted residual ratio, this))
 constexpr int kOffW1 = 0, kOffB1 = kOffW1 + kMlpH * kMlpIn, kOffW2 = kOffB1 + kMlpH, kOffB2 = kOffW2 + kMlpH * kMlpH,
               kOffW3 = kOffB2 + kMlpH, kOffB3 = kOffW3 + kMlpOut * kMlpH;
 
@@ -150,45 +151,36 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ par
 }
 
 // --------------------------------------------------------------- training
-// Samples from records: row r = s*T + i (sample s, tuple i) gets the features
-// of tuple i at (theta[s], kidx[s]) and the target (m0, P, kappa) with
-// m0 = (alpha/2) p2max / p^2 (0 at the zero tuple) and kappa = (1 - C/P)/m0
-// clipped to [1e-3, 1e3] (1 where P or m0 vanishes).
+// Samples from records: record r holds (P_r, C_r) per tuple. Sample s uses
+// record r = first + s*every and the next one: row s*T + i gets the features
+// of tuple i at (theta[r], iteration k0 + r) and the loss coefficients
+// (a, b, c) = (P_r, P_r - C_r, P_r - 2 C_r + P_{r+1}), formed in double.
 __global__ void __launch_bounds__(256) k_make_samples(const double* __restrict__ rec, const double* __restrict__ theta,
-                                                      const int* __restrict__ kidx, int64_t nrows, TupleGeom tg,
-                                                      double half_alpha_p2max, float* __restrict__ X,
-                                                      float* __restrict__ tgt) {
+                                                      int first, int every, long long k0, int64_t nrows,
+                                                      TupleGeom tg, float* __restrict__ X, float* __restrict__ tgt) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= nrows) return;
     const int s = (int)(row / tg.count), i = (int)(row % tg.count);
-    int t[4], r = i;
+    const int64_t r = (int64_t)first + (int64_t)s * every;
+    int t[4], q = i;
     for (int m = 0; m < 4; ++m) {
-        t[m] = r % tg.h[m];
-        r /= tg.h[m];
+        t[m] = q % tg.h[m];
+        q /= tg.h[m];
     }
     float s4[4];
-    double p2 = 0.0;
     for (int m = 0; m < 4; ++m) {
         const double sv = sinpi((double)t[m] / (double)tg.n[m]);
-        const double c = 4.0 * sv * sv;
-        s4[m] = (float)c;
-        p2 += c;
+        s4[m] = (float)(4.0 * sv * sv);
     }
     float x[kMlpIn];
-    mlp_features(s4, (float)log10(fmax(theta[s], 1e-300)), (float)kidx[s], x);
+    mlp_features(s4, (float)log10(fmax(theta[r], 1e-300)), (float)(k0 + r), x);
 #pragma unroll
-    for (int q = 0; q < kMlpIn; ++q) X[row * kMlpIn + q] = x[q];
-    const double P = rec[2 * row], C = rec[2 * row + 1];
-    const double m0 = p2 > 0.0 ? half_alpha_p2max / p2 : 0.0;
-    double kap = 1.0;
-    if (P > 0.0 && m0 > 0.0) {
-        kap = (1.0 - C / P) / m0;
-        if (!isfinite(kap)) kap = 1.0;
-        kap = fmin(fmax(kap, 1e-3), 1e3);
-    }
-    tgt[row * 3] = (float)m0;
-    tgt[row * 3 + 1] = (float)P;
-    tgt[row * 3 + 2] = (float)kap;
+    for (int c = 0; c < kMlpIn; ++c) X[row * kMlpIn + c] = x[c];
+    const double P = rec[(r * tg.count + i) * 2], C = rec[(r * tg.count + i) * 2 + 1];
+    const double Pn = rec[((r + 1) * tg.count + i) * 2];
+    tgt[row * 3] = (float)P;
+    tgt[row * 3 + 1] = (float)(P - C);
+    tgt[row * 3 + 2] = (float)(P - 2.0 * C + Pn);
 }
 
 // Rows are momentum tuples of samples; sample s owns rows [off[s], off[s+1]),
@@ -234,38 +226,38 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ p
 __global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ O, const float* __restrict__ tgt,
                                                   const int* __restrict__ off, int ns, float* __restrict__ dO,
                                                   double* __restrict__ sample_loss) {
-    const int s = blockIdx.x;
-    const int r0 = off[s], r1 = off[s + 1];
+    const int smp = blockIdx.x;
+    const int r0 = off[smp], r1 = off[smp + 1];
     const double oa = O[(int64_t)r0 * 2 + 1];
     __shared__ double red[4][256 / 64];
-    double psum = 0.0, lsum = 0.0;
+    double asum = 0.0, lsum = 0.0;
     for (int r = r0 + threadIdx.x; r < r1; r += 256) {
-        const double m0 = tgt[(int64_t)r * 3], P = tgt[(int64_t)r * 3 + 1], kap = tgt[(int64_t)r * 3 + 2];
-        const double m = m0 * exp((double)O[(int64_t)r * 2] + oa);
-        const double res = 1.0 - m * kap;
-        psum += P;
-        lsum += P * res * res;
+        const double a = tgt[(int64_t)r * 3], b = tgt[(int64_t)r * 3 + 1], c = tgt[(int64_t)r * 3 + 2];
+        const double s = exp((double)O[(int64_t)r * 2] + oa);
+        asum += a;
+        lsum += a - 2.0 * s * b + s * s * c;
     }
-    // block sums of P and of P r^2
-    psum = wave_sum(psum);
+    asum = wave_sum(asum);
     lsum = wave_sum(lsum);
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
     if (l == 0) {
-        red[0][wv] = psum;
+        red[0][wv] = asum;
         red[1][wv] = lsum;
     }
     __syncthreads();
-    double Ptot = 0.0, Ltot = 0.0;
+    double Atot = 0.0, Ltot = 0.0;
     for (int i = 0; i < 256 / 64; ++i) {
-        Ptot += red[0][i];
+        Atot += red[0][i];
         Ltot += red[1][i];
     }
-    // dL/dm = -2 P r kappa / (Ptot ns); do_s = dL/dm * m; do_a(row 0) = sum over rows
+    // loss = ln(Ltot / Atot), floored at ln(kRatioFloor) with zero gradient there;
+    // d loss/ds = (2 s c - 2 b) / (Ltot ns); do_s = d loss/ds * s; do_a(row 0) = sum over rows
+    const bool floored = !(Ltot / Atot > kRatioFloor);
     double gsum = 0.0;
     for (int r = r0 + threadIdx.x; r < r1; r += 256) {
-        const double m0 = tgt[(int64_t)r * 3], P = tgt[(int64_t)r * 3 + 1], kap = tgt[(int64_t)r * 3 + 2];
-        const double m = m0 * exp((double)O[(int64_t)r * 2] + oa);
-        const double g = -2.0 * P * (1.0 - m * kap) * kap / (Ptot * ns) * m;
+        const double b = tgt[(int64_t)r * 3 + 1], c = tgt[(int64_t)r * 3 + 2];
+        const double s = exp((double)O[(int64_t)r * 2] + oa);
+        const double g = floored ? 0.0 : (2.0 * s * c - 2.0 * b) / (Ltot * ns) * s;
         dO[(int64_t)r * 2] = (float)g;
         dO[(int64_t)r * 2 + 1] = 0.0f;
         gsum += g;
@@ -278,7 +270,7 @@ __global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ O, c
         double t = 0.0;
         for (int i = 0; i < 256 / 64; ++i) t += red[2][i];
         dO[(int64_t)r0 * 2 + 1] = (float)t;
-        sample_loss[s] = Ltot / Ptot;
+        sample_loss[smp] = log(floored ? kRatioFloor : Ltot / Atot);
     }
 }
 

@@ -61,6 +61,9 @@ def _signatures(lib):
         "gf_batch_workspace_bytes": (sz, [i32, _P]),
         "gf_init_batch": (i32, [ctypes.POINTER(_P), i32, _P, _P, _P, sz, _P]),
         "gf_fix_until_batch": (i32, [_P, dbl, i64, _P]),
+        "gf_state_bytes": (sz, [_P]),
+        "gf_get_state": (i32, [_P, _P, sz]),
+        "gf_set_state": (i32, [_P, _P, sz]),
         "gf_quality": (i32, [_P, pd, pd]),
         "gf_get_links": (i32, [_P, _P]),
         "gf_get_gauge": (i32, [_P, _P]),
@@ -75,7 +78,7 @@ def _signatures(lib):
         "gf_mlp_set_weights": (i32, [_P, _P, i32]),
         "gf_record_spectra": (i32, [_P, i64, _P, pd]),
         "gf_mlp_workspace_bytes": (sz, [i64, i32]),
-        "gf_mlp_make_samples": (i32, [_P, _P, _P, i32, ctypes.POINTER(i32), dbl, _P, _P, _P]),
+        "gf_mlp_make_samples": (i32, [_P, i32, _P, i32, i32, i32, i64, ctypes.POINTER(i32), _P, _P, _P]),
         "gf_mlp_forward": (i32, [_P, _P, i64, _P, _P, sz, _P]),
         "gf_mlp_loss_grad": (i32, [_P, _P, _P, _P, i32, i64, _P, _P, sz, _P, pd]),
         "gf_mlp_adam": (i32, [_P, _P, _P, _P, i64, ctypes.c_float, _P]),
@@ -191,6 +194,18 @@ def gf_fix_until_batch(ctx, tol, max_iter, n):
     return st, list(res)
 
 
+def gf_state_bytes(ctx):
+    return load().gf_state_bytes(ctx)
+
+
+def gf_get_state(ctx, d_out, nbytes):
+    _check(ctx, load().gf_get_state(ctx, _P(d_out), nbytes))
+
+
+def gf_set_state(ctx, d_in, nbytes):
+    _check(ctx, load().gf_set_state(ctx, _P(d_in), nbytes))
+
+
 def gf_quality(ctx):
     th, f = ctypes.c_double(), ctypes.c_double()
     _check(ctx, load().gf_quality(ctx, ctypes.byref(th), ctypes.byref(f)))
@@ -271,10 +286,11 @@ def gf_mlp_workspace_bytes(n_rows, n_samples):
     return load().gf_mlp_workspace_bytes(int(n_rows), int(n_samples))
 
 
-def gf_mlp_make_samples(d_records, d_theta, d_k, n_samples, dims, alpha, d_x, d_tgt, stream=0):
+def gf_mlp_make_samples(d_records, n_records, d_theta, first, every, n_samples, k0, dims, d_x, d_tgt, stream=0):
     arr = (ctypes.c_int32 * 4)(*[int(d) for d in dims])
-    _mlp_check(load().gf_mlp_make_samples(_P(d_records), _P(d_theta), _P(d_k), int(n_samples), arr, float(alpha),
-                                          _P(d_x), _P(d_tgt), _P(stream)), "gf_mlp_make_samples")
+    _mlp_check(load().gf_mlp_make_samples(_P(d_records), int(n_records), _P(d_theta), int(first), int(every),
+                                          int(n_samples), int(k0), arr, _P(d_x), _P(d_tgt), _P(stream)),
+               "gf_mlp_make_samples")
 
 
 def gf_mlp_forward(d_params, d_x, n_rows, d_out, d_ws, ws_bytes, stream=0):
@@ -374,6 +390,17 @@ class GaugeFixer:
             out = torch.empty_like(self.links)
         gf_get_links(self.ctx, out.data_ptr())
         return out
+
+    def save_state(self):
+        """Checkpoint of the whole context as a uint8 CUDA tensor."""
+        import torch
+        n = gf_state_bytes(self.ctx)
+        buf = torch.empty(n, dtype=torch.uint8, device=self.links.device)
+        gf_get_state(self.ctx, buf.data_ptr(), n)
+        return buf
+
+    def load_state(self, buf):
+        gf_set_state(self.ctx, buf.data_ptr(), buf.numel())
 
     def set_weights(self, params, enable=True):
         """Switch the learned preconditioner on with a float32 CUDA tensor of gf_mlp_param_count() parameters."""

@@ -32,8 +32,12 @@ def n_tuples(dims):
 
 
 def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=0.08, device="cuda:0",
-            every=1, log=None):
-    """Record plain-FA trajectories of the given seeds; returns (X, TGT, n_samples) as CUDA tensors."""
+            every=1, theta_min=1e-13, log=None):
+    """Record plain-FA trajectories of the given seeds; returns (X, TGT, n_samples) as CUDA tensors.
+
+    A sample pairs iteration r with r + 1; iterations are kept while theta_r > theta_min (below, the
+    spectra are rounding noise), every `every`-th one.
+    """
     import torch
     T = n_tuples(dims)
     xs, ts = [], []
@@ -42,22 +46,20 @@ def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=
         links = torch.from_numpy(u).to(device)
         fx = gf.GaugeFixer(links, precision, alpha=alpha, flags=gf.FLAG_RECORD_SPECTRA)
         rec, theta = fx.record(n_iter)
-        keep = np.arange(0, n_iter, every)
-        keep = keep[theta[keep] > 1e-13]  # below this the float spectra are rounding noise
-        if len(keep) == 0:
-            fx.close()
+        fx.close()
+        live = int(np.argmax(theta <= theta_min)) if np.any(theta <= theta_min) else n_iter
+        last = min(live, n_iter - 1) - 1  # the last usable record has a successor
+        if last < 0:
             continue
-        rec = rec[torch.as_tensor(keep, device=device)].contiguous()
-        th = torch.as_tensor(theta[keep], dtype=torch.float64, device=device)
-        kk = torch.as_tensor(keep.astype(np.int32), device=device)
-        n = len(keep)
+        n = last // every + 1
+        th = torch.as_tensor(theta, dtype=torch.float64, device=device)
         X = torch.empty((n * T, 6), dtype=torch.float32, device=device)
         TG = torch.empty((n * T, 3), dtype=torch.float32, device=device)
-        gf.gf_mlp_make_samples(rec.data_ptr(), th.data_ptr(), kk.data_ptr(), n, dims, alpha, X.data_ptr(),
+        gf.gf_mlp_make_samples(rec.data_ptr(), n_iter, th.data_ptr(), 0, every, n, 0, dims, X.data_ptr(),
                                TG.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        torch.cuda.current_stream().synchronize()
         xs.append(X)
         ts.append(TG)
-        fx.close()
         if log:
             log(f"recorded seed {seed}: {n} samples")
     X = torch.cat(xs)

@@ -119,3 +119,9 @@ def test_batch_rejects_bad_parameters_before_device(lib):
     ctx = gf._P()
     assert lib.gf_init_batch(ctypes.byref(ctx), 0, None, None, gf._P(256), 1 << 40, None) == gf.GF_EINVAL
     assert lib.gf_fix_until_batch(None, 1e-15, 10, None) == gf.GF_EINVAL
+
+
+def test_state_calls_reject_null_context(lib):
+    assert lib.gf_state_bytes(None) == 0
+    assert lib.gf_get_state(None, gf._P(256), 1 << 20) == gf.GF_EINVAL
+    assert lib.gf_set_state(None, gf._P(256), 1 << 20) == gf.GF_EINVAL

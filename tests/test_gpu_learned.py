@@ -36,16 +36,13 @@ def _rand_samples(dims, nsamp, seed):
     rng = np.random.default_rng(seed)
     tuples = mlp.folded_tuples(dims)
     psq = mlp.tuple_psq(dims, tuples)
-    p2 = psq.sum(1)
-    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
     out = []
     for _ in range(nsamp):
         x = mlp.features(psq, 10.0 ** rng.uniform(-12, 0), float(rng.integers(0, 60)))
-        power = rng.uniform(0.1, 2.0, len(tuples))
-        power[0] = 0.0
-        kappa = 2.0 * p2 * rng.uniform(0.6, 1.0, len(tuples))
-        kappa[0] = 1.0
-        out.append((x, m0, power, kappa))
+        a = rng.uniform(0.1, 2.0, len(tuples))
+        b = a * rng.uniform(0.5, 1.5, len(tuples))
+        c = b * b / a * rng.uniform(1.0, 2.0, len(tuples))
+        out.append((x, a, b, c))
     return out
 
 
@@ -63,7 +60,7 @@ def _params(seed, scale=0.05):
 
 def test_forward_matches_oracle():
     dims = (6, 4, 4, 8)
-    (x, m0, p, k), = _rand_samples(dims, 1, 1)
+    (x, _, _, _), = _rand_samples(dims, 1, 1)
     th = _params(2)
     n = len(x)
     out = torch.empty((n, 2), dtype=torch.float32, device="cuda:0")
@@ -88,8 +85,8 @@ def test_loss_and_gradient_match_oracle():
     loss = gf.gf_mlp_loss_grad(th_d.data_ptr(), x_d.data_ptr(), t_d.data_ptr(), o_d.data_ptr(), len(samples), n,
                                g.data_ptr(), ws.data_ptr(), nb)
     # the oracle sees exactly the float inputs the GPU saw
-    samples64 = [(x[a:b].astype(np.float64), tgt[a:b, 0].astype(np.float64), tgt[a:b, 1].astype(np.float64),
-                  tgt[a:b, 2].astype(np.float64)) for a, b in zip(off[:-1], off[1:])]
+    samples64 = [(x[i:j].astype(np.float64), tgt[i:j, 0].astype(np.float64), tgt[i:j, 1].astype(np.float64),
+                  tgt[i:j, 2].astype(np.float64)) for i, j in zip(off[:-1], off[1:])]
     th64 = th.astype(np.float64)
     assert loss == pytest.approx(mlp.loss(th64, samples64), rel=1e-5)
     want = mlp.loss_grad(th64, samples64)
@@ -134,25 +131,25 @@ def test_recorded_spectra_match_oracle(dims):
         assert np.max(np.abs(rec[k, :, 1] - c)) <= 1e-10 * np.max(np.abs(p))
     # the links were advanced by exactly the recorded updates
     assert np.max(np.abs(links.cpu().numpy() - cur)) < 1e-12
-    # training rows assembled on the GPU match the oracle's features and targets
-    n = 3
+    # training rows assembled on the GPU match the oracle's features and loss coefficients
+    n, every = 2, 1
     X = torch.empty((n * len(tuples), 6), dtype=torch.float32, device="cuda:0")
     TG = torch.empty((n * len(tuples), 3), dtype=torch.float32, device="cuda:0")
-    kk = torch.arange(n, dtype=torch.int32, device="cuda:0")
-    rec_d, th_d = dev(rec), dev(theta[:n])
-    gf.gf_mlp_make_samples(rec_d.data_ptr(), th_d.data_ptr(), kk.data_ptr(), n, dims, ALPHA, X.data_ptr(),
-                           TG.data_ptr())
+    rec_d, th_d = dev(rec), dev(theta)
+    gf.gf_mlp_make_samples(rec_d.data_ptr(), 3, th_d.data_ptr(), 0, every, n, 0, dims, X.data_ptr(), TG.data_ptr())
     X, TG = X.cpu().numpy(), TG.cpu().numpy()
     psq = mlp.tuple_psq(dims, tuples)
-    p2 = psq.sum(1)
-    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
     for k in range(n):
         rows = slice(k * len(tuples), (k + 1) * len(tuples))
         assert np.max(np.abs(X[rows] - mlp.features(psq, theta[k], k))) < 1e-6
-        kap = mlp.kappa_from(rec[k, :, 0], rec[k, :, 1], m0)
-        assert np.max(np.abs(TG[rows, 0] - m0) / np.maximum(m0, 1e-30)) < 1e-6
-        live = rec[k, :, 0] > 1e-8 * rec[k, :, 0].max()
-        assert np.max(np.abs(TG[rows, 2][live] - kap[live]) / kap[live]) < 1e-5
+        want = mlp.targets(rec[k, :, 0], rec[k, :, 1], rec[k + 1, :, 0])
+        for j in range(3):
+            assert np.max(np.abs(TG[rows, j] - want[j])) <= 1e-6 * np.max(np.abs(want[0])), (k, j)
+    # a sample needs the record after it
+    xb = torch.empty((2 * len(tuples), 6), dtype=torch.float32, device="cuda:0")
+    tb = torch.empty((2 * len(tuples), 3), dtype=torch.float32, device="cuda:0")
+    with pytest.raises(gf.GfError):
+        gf.gf_mlp_make_samples(rec_d.data_ptr(), 3, th_d.data_ptr(), 1, 1, 2, 0, dims, xb.data_ptr(), tb.data_ptr())
 
 
 def test_zero_output_network_is_plain_fa():

@@ -1,6 +1,8 @@
 """Pins of the learned-preconditioner oracle (CPU only): gradients against
-central finite differences, the plain-FA limit, the folding of momenta, the
-recorded response against the free-field closed form, and Adam's first step."""
+central finite differences, the plain-FA limit (the loss at zero outputs is
+the plain step's residual ratio, checked through Parseval in position
+space), the folding of momenta, the recorded response against the free-field
+closed form, and Adam's first step."""
 import numpy as np
 import pytest
 
@@ -14,16 +16,27 @@ def _samples(dims, nsamp, seed):
     rng = np.random.default_rng(seed)
     tuples = mlp.folded_tuples(dims)
     psq = mlp.tuple_psq(dims, tuples)
-    p2 = psq.sum(1)
-    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
     out = []
     for s in range(nsamp):
         x = mlp.features(psq, 10.0 ** rng.uniform(-12, 0), rng.integers(0, 60))
-        power = rng.uniform(0.1, 2.0, len(tuples))
-        power[0] = 0.0
-        kappa = 2.0 * p2 * rng.uniform(0.6, 1.0, len(tuples))
-        out.append((x, m0, power, kappa))
+        a = rng.uniform(0.1, 2.0, len(tuples))
+        b = a * rng.uniform(0.5, 1.5, len(tuples))
+        c = b * b / a * rng.uniform(1.0, 2.0, len(tuples))  # Cauchy-Schwarz: c >= b^2 / a
+        out.append((x, a, b, c))
     return out
+
+
+def _trajectory(dims, seed, n, eps=synth.EPS_P059):
+    """Oracle FA trajectory: packed spectra Z^0..Z^n and the position-space packed fields."""
+    u = synth.make_config(dims, seed, eps)
+    specs, fields = [], []
+    for k in range(n + 1):
+        d = landau.divergence(u)
+        specs.append(mlp.packed_spectrum(d))
+        fields.append(np.stack([d[..., 0, 1], d[..., 0, 2], d[..., 1, 2], d[..., 0, 0].imag + 1j * d[..., 1, 1].imag], -1))
+        if k < n:
+            u, *_ = landau.fa_step(u, ALPHA)
+    return specs, fields
 
 
 def test_param_count_and_layout():
@@ -34,8 +47,31 @@ def test_param_count_and_layout():
 
 def test_zero_output_layer_is_plain_fa():
     th = mlp.init_params(2)
-    (x, m0, power, kappa), = _samples((4, 4, 6, 4), 1, 3)
+    dims = (4, 4, 6, 4)
+    (x, a, b, c), = _samples(dims, 1, 3)
+    p2 = mlp.tuple_psq(dims, mlp.folded_tuples(dims)).sum(1)
+    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
     assert np.array_equal(mlp.multipliers(th, x, m0), m0)
+    assert np.array_equal(mlp.scales(th, x), np.ones(len(x)))
+
+
+def test_zero_output_loss_is_plain_residual_ratio():
+    """At s = 1 the loss is sum P_{k+1} / sum P_k, i.e. (Parseval) the ratio of the
+    packed divergence's energy after and before a plain step, taken in position space."""
+    dims = (4, 6, 4, 4)
+    tuples = mlp.folded_tuples(dims)
+    specs, fields = _trajectory(dims, 5, 3)
+    th = mlp.init_params(9)
+    psq = mlp.tuple_psq(dims, tuples)
+    for k in range(3):
+        pk, ck = mlp.record(specs[k], specs[k + 1], dims, tuples)
+        pn, _ = mlp.record(specs[k + 1], specs[k + 1], dims, tuples)
+        a, b, c = mlp.targets(pk, ck, pn)
+        x = mlp.features(psq, 0.1, k)
+        want = np.sum(np.abs(fields[k + 1]) ** 2) / np.sum(np.abs(fields[k]) ** 2)
+        assert mlp.sample_ratio(th, x, a, b, c) == pytest.approx(want, rel=1e-12)
+        assert mlp.sample_loss(th, x, a, b, c) == pytest.approx(np.log(want), abs=1e-12)
+        assert np.all(c >= -1e-12 * a.max())  # c = |Z^k - Z^{k+1}|^2 per tuple
 
 
 def test_gradient_matches_central_differences():
@@ -69,25 +105,31 @@ def test_folding_covers_every_site_once():
 
 
 def test_recorded_response_free_field():
-    """Linearised FA multiplies Z(p) by 1 - 2 m0(p) p^2: kappa(p) = 2 p^2 on every mode with power."""
+    """Linearised FA multiplies Z(p) by 1 - 16 alpha on every mode (free field), so
+    b / a = 16 alpha, c / a = (16 alpha)^2, and the loss vanishes at s = 1/(16 alpha)."""
     dims = (8, 4, 6, 4)
     rng = np.random.default_rng(7)
     shp = synth.lattice_shape(dims)
-    a = 1e-4 * rng.standard_normal(shp + (4,))
-    b = 1e-4 * rng.standard_normal(shp + (4,))
+    a_ = 1e-4 * rng.standard_normal(shp + (4,))
+    b_ = 1e-4 * rng.standard_normal(shp + (4,))
     u = np.zeros(shp + (4, 3, 3), np.complex128)
-    u[..., 0, 0], u[..., 1, 1], u[..., 2, 2] = np.exp(1j * a), np.exp(1j * b), np.exp(-1j * (a + b))
+    u[..., 0, 0], u[..., 1, 1], u[..., 2, 2] = np.exp(1j * a_), np.exp(1j * b_), np.exp(-1j * (a_ + b_))
     u1, *_ = landau.fa_step(u, ALPHA)
     tuples = mlp.folded_tuples(dims)
     s0 = mlp.packed_spectrum(landau.divergence(u))
     s1 = mlp.packed_spectrum(landau.divergence(u1))
-    power, corr = mlp.record(s0, s1, dims, tuples)
-    p2 = mlp.tuple_psq(dims, tuples).sum(1)
-    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
-    kappa = mlp.kappa_from(power, corr, m0)
-    live = power > 1e-6 * power.max()
+    pk, ck = mlp.record(s0, s1, dims, tuples)
+    pn, _ = mlp.record(s1, s1, dims, tuples)
+    a, b, c = mlp.targets(pk, ck, pn)
+    live = a > 1e-6 * a.max()
     assert live.sum() > 10
-    assert np.allclose(kappa[live], 2.0 * p2[live], rtol=1e-3)
+    assert np.allclose(b[live] / a[live], 16 * ALPHA, rtol=1e-3)
+    assert np.allclose(c[live] / a[live], (16 * ALPHA) ** 2, rtol=2e-3)
+    # a network whose only non-zero parameter is the global log-step bias reaching s = 1/(16 alpha)
+    th = mlp.init_params(1)
+    th[-1] = -np.log(16 * ALPHA)
+    x = mlp.features(mlp.tuple_psq(dims, tuples), 1e-8, 0)
+    assert mlp.sample_ratio(th, x, a, b, c) < 1e-5
 
 
 def test_adam_first_step_is_lr_times_sign():
