@@ -48,6 +48,53 @@ def kernel_bytes(name, vol, L, S, nblk):
 STORAGE = {"fp64_18": (18, 8), "fp64_12": (12, 8), "fp32_12": (12, 4), "fp32_18": (18, 4)}
 
 
+PMC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                           "update_measure_{prec}_{dims}_pmc.md")
+KERNEL_SOURCES = ["paper_1208_1186_amd/csrc/gf_device.hpp", "paper_1208_1186_amd/csrc/gf_kernels.hpp"]
+
+
+def counted_traffic(prec, dims):
+    """HBM bytes per launch of the loop kernel from the committed rocprofv3 FETCH/WRITE passes, scaled by
+    the copy calibration; None if there is no such profile or the kernel sources changed since."""
+    import hashlib
+    import re
+    path = PMC_PROFILE.format(prec=prec, dims="x".join(str(d) for d in dims))
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(root, f), "rb").read())
+    if h.hexdigest() not in text:
+        return None
+    vals = {}
+    for key in ["fetch_scale", "write_scale", "fetch_kib_per_dispatch", "write_kib_per_dispatch"]:
+        m = re.search(rf"^{key}:\s*([0-9.eE+-]+)", text, re.M)
+        if not m:
+            return None
+        vals[key] = float(m.group(1))
+    return round(1024.0 * (vals["fetch_kib_per_dispatch"] * vals["fetch_scale"]
+                           + vals["write_kib_per_dispatch"] * vals["write_scale"]))
+
+
+def copy_ceiling(torch, dev, mib=1024, reps=10):
+    """Device-to-device copy rate (read + write bytes per second) of a plain 1 GiB copy on this GPU."""
+    a = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return round(gbps, 1)
+
+
 def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events):
     links = u_dev.clone()
     fx = gf.GaugeFixer(links, precision, check_every=max(steps, warmup, 1))
@@ -170,6 +217,45 @@ def batch_workload(gf, torch, synth, dev, n=64, tol=1e-15):
     return out
 
 
+def learned_workload(gf, torch, synth, n_train=64, n_iter=120, epochs=60):
+    """Train the spectral-preconditioner network on 16^4 plain-FA trajectories (on the GPU, with the
+    library's kernels), then compare iterations and wall time to theta < 1e-15 against plain FA."""
+    from paper_1208_1186_amd import learn
+    import numpy as np
+    log(f"learned preconditioner: recording {n_train} 16^4 trajectories")
+    t0 = time.perf_counter()
+    dims_tr = (16, 16, 16, 16)
+    X, TG, ns = learn.collect(dims_tr, range(100, 100 + n_train), n_iter)
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, hist = learn.train(X, TG, learn.n_tuples(dims_tr), ns, epochs=epochs, batch=32, lr=1e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    out = {"train": {"lattice": list(dims_tr), "trajectories": n_train, "samples": int(ns),
+                     "record_s": round(t_rec, 2), "train_s": round(t_train, 2), "epochs": epochs,
+                     "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}, "eval": []}
+    tot = {"plain_iters": 0, "learned_iters": 0, "plain_s": 0.0, "learned_s": 0.0}
+    for dims, seeds, eps in [((32, 32, 32, 32), range(10000, 10004), synth.EPS_P059),
+                             ((48, 48, 48, 8), range(20000, 20004), synth.EPS_P060)]:
+        for seed in seeds:
+            u = synth.make_config(dims, seed, eps)
+            r0, t_0, _ = learn.solve(u)
+            r1, t_1, _ = learn.solve(u, params=params)
+            out["eval"].append({"lattice": list(dims), "seed": seed, "plain_iters": int(r0.iters),
+                                "learned_iters": int(r1.iters), "plain_s": round(t_0, 4), "learned_s": round(t_1, 4),
+                                "fallbacks": int(r1.fallbacks), "theta": [r0.theta, r1.theta]})
+            tot["plain_iters"] += int(r0.iters)
+            tot["learned_iters"] += int(r1.iters)
+            tot["plain_s"] += t_0
+            tot["learned_s"] += t_1
+    out["total"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in tot.items()}
+    out["iteration_ratio_learned_vs_plain"] = round(tot["learned_iters"] / tot["plain_iters"], 4)
+    out["wall_ratio_learned_vs_plain"] = round(tot["learned_s"] / tot["plain_s"], 4)
+    log(f"learned: {tot['learned_iters']} vs {tot['plain_iters']} iterations, "
+        f"{tot['learned_s']:.3f}s vs {tot['plain_s']:.3f}s")
+    return out
+
+
 def cpu_baseline(u, budget_s=12.0):
     """The FP64 NumPy oracle's FA iterations on the same input, on the host cores."""
     from oracle import landau
@@ -200,6 +286,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the other precisions and time-to-theta")
     ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3x8 mixed-precision workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice uneven batch workload")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner workload")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -255,13 +342,16 @@ def main():
                           "alg_GBps": round(by / (avg * 1e-3) / 1e9, 1)}
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
     dk = kern[dom]
+    traffic = counted_traffic(prec, dims) if dom == "update_measure" else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["alg_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(dk["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": dk["alg_bytes"], "avg_launch_ms": dk["avg_ms"]}
     events_ms = sum(v["avg_ms"] * v["launches"] for v in kern.values()) / args.steps
 
     extras = {}
     if not args.no_extras:
+        extras["copy_ceiling_GBps"] = copy_ceiling(torch, dev)
+        log(f"plain 1 GiB device copy: {extras['copy_ceiling_GBps']} GB/s")
         for p2 in ["fp64_12", "fp32_12"]:
             if p2 == prec:
                 continue
@@ -281,6 +371,8 @@ def main():
         extras["mixed_48x48x48x8"] = mixed_workload(gf, torch, synth, dev)
     if not args.no_extras and not args.no_batch:
         extras["batch_64_uneven"] = batch_workload(gf, torch, synth, dev)
+    if not args.no_extras and not args.no_learned:
+        extras["learned_preconditioner"] = learned_workload(gf, torch, synth)
 
     cpu = None
     if not args.no_cpu_baseline:
