@@ -241,14 +241,27 @@ int32_t gf_mlp_param_count(void);
 gf_status gf_mlp_set_weights(gf_ctx* ctx, const float* d_params, int32_t enable);
 
 /*
- * Apply n plain Fourier-accelerated updates and record, for every step k
- * and every momentum tuple i (n_mu in [0, N_mu/2], first axis fastest),
- * d_records[(k*T + i)*2 + 0] = P_k = sum over the tuple's +-n reflections and
- * the four packed divergence fields of |Z_k(p)|^2 after the forward FFT, and
- * [.. + 1] = C_k = the same sum of Re[Z_{k+1}(p) conj(Z_k(p))] (T tuples,
- * double). h_theta[k] = theta_k. Needs GF_FLAG_RECORD_SPECTRA.
+ * Write the multiplier table the network gives at the current theta and
+ * iteration count to d_out (device; T entries over the folded tuples, first
+ * axis fastest; double for FP64 contexts, float for FP32):
+ * d_out[i] = (alpha/2) p2max / (V p^2_i) * exp(o_s(i) + o_a(0)), 0 at the zero
+ * tuple, the 1/V of the inverse FFT included. Needs GF_FLAG_LEARNED.
  */
-gf_status gf_record_spectra(gf_ctx* ctx, int64_t n, double* d_records, double* h_theta);
+gf_status gf_mlp_multipliers(gf_ctx* ctx, void* d_out);
+
+/*
+ * Apply n plain Fourier-accelerated updates and record, for every step k and
+ * every momentum tuple i (n_mu in [0, N_mu/2], first axis fastest), summed
+ * over the tuple's +-n reflections and the four packed divergence fields
+ * after the forward FFT (T tuples, double):
+ *   d_records[(k*T + i)*3 + 0] = P_k = sum |Z_k(p)|^2,
+ *   [.. + 1] = C_k = sum Re[Z_{k+1}(p) conj(Z_k(p))],
+ *   [.. + 2] = E_k = sum |Z'_k(p)|^2, Z' the divergence after a probe update
+ *              from step k with every multiplier times probe_scale (in (0, 1)),
+ *              which is then undone.
+ * h_theta[k] = theta_k. Needs GF_FLAG_RECORD_SPECTRA; the network is not used.
+ */
+gf_status gf_record_spectra(gf_ctx* ctx, int64_t n, double probe_scale, double* d_records, double* h_theta);
 
 /*
  * Training (no lattice context). Rows are momentum tuples of samples; sample
@@ -256,7 +269,8 @@ gf_status gf_record_spectra(gf_ctx* ctx, int64_t n, double* d_records, double* h
  * above) and tgt (a, b, c per row, from gf_mlp_make_samples), its first row
  * being the zero tuple. With s(p) = exp(o_s(p) + o_a(first row)) the factor
  * on the plain multiplier, the predicted residual energy ratio of a sample
- * after the scaled step is R = sum_p (a - 2 s b + s^2 c) / sum_p a; its loss
+ * after the scaled step is R = sum_p e_p(s_p) / sum_p a = sum_p (a - 2 s b +
+ * s^2 c) / sum_p a; its loss
  * is ln(max(R, 1e-12)) (zero gradient below), and the loss is the mean over
  * samples: the predicted mean log-decrease per step. All pointers are device pointers except
  * h_loss (host, may be NULL); d_ws holds gf_mlp_workspace_bytes(n_rows,
@@ -264,18 +278,20 @@ gf_status gf_record_spectra(gf_ctx* ctx, int64_t n, double* d_records, double* h
  */
 size_t gf_mlp_workspace_bytes(int64_t n_rows, int32_t n_samples);
 /*
- * Training rows from n_records consecutive records of gf_record_spectra
- * (d_theta[r] = theta of record r, iteration k0 + r). Sample s uses record
- * r = first + s*every and record r + 1 (so r <= n_records - 2, else
- * GF_EINVAL): row s*T + i of d_x gets the features of tuple i at
- * (theta_r, k0 + r), and of d_tgt (a, b, c) = (P_r, P_r - C_r,
- * P_r - 2 C_r + P_{r+1}), i.e. the energy of mode i, its change along the
- * plain step, and the squared size of that change. dims: host array
- * {Nx, Ny, Nz, Nt}; T = prod(N_mu/2 + 1).
+ * Training rows from n_records consecutive records of gf_record_spectra made
+ * with probe_scale sigma (d_theta[r] = theta of record r, iteration k0 + r).
+ * Sample s uses record r = first + s*every and record r + 1 (so
+ * r <= n_records - 2, else GF_EINVAL): row s*T + i of d_x gets the features
+ * of tuple i at (theta_r, k0 + r), and of d_tgt (a, b, c), the coefficients
+ * of the quadratic e(x) = a - 2 b x + c x^2 through the residual energies of
+ * the mode after the step scaled by x: e(0) = P_r, e(sigma) = E_r,
+ * e(1) = P_{r+1} (c raised to b^2/a where needed, so that e >= 0).
+ * dims: host array {Nx, Ny, Nz, Nt}; T = prod(N_mu/2 + 1).
  */
 gf_status gf_mlp_make_samples(const double* d_records, int32_t n_records, const double* d_theta,
                               int32_t first, int32_t every, int32_t n_samples, int64_t k0,
-                              const int32_t* dims, float* d_x, float* d_tgt, void* stream);
+                              double probe_scale, const int32_t* dims, float* d_x, float* d_tgt,
+                              void* stream);
 gf_status gf_mlp_forward(const float* d_params, const float* d_x, int64_t n_rows, float* d_out,
                          void* d_ws, size_t ws_bytes, void* stream);
 gf_status gf_mlp_loss_grad(const float* d_params, const float* d_x, const float* d_tgt,

@@ -14,20 +14,22 @@ k / 64).
 
 Training signal (recorded on plain-FA trajectories): per mode p (a tuple
 folded over its +-n reflections) and iteration k, over the four packed
-divergence fields Z_f after the forward 4D FFT,
-    P_k(p) = sum_f |Z_f^k(p)|^2,   C_k(p) = sum_f Re[Z_f^{k+1}(p) conj(Z_f^k(p))].
-A plain step changes mode p by R = Z^k - Z^{k+1}. Scaling the step of mode p
-by s(p) = m(p)/m0(p) = exp(o_s(p) + o_a(0)) leaves, to first order in the step
-and for s varying slowly with p, the residual Z^k - s R, whose energy is
-    a - 2 s b + s^2 c,   a = P_k,  b = P_k - C_k,  c = P_k - 2 C_k + P_{k+1}
-(c = |R|^2 >= 0). The predicted residual ratio of one sample (trajectory, k)
-is that energy summed over the modes and divided by sum_p P_k, and the loss of
-the sample is its natural logarithm (floored at ln 1e-12, where the gradient
-is zero): the mean over samples is then the predicted mean log-decrease per
-step, whose inverse sets the number of steps to a tolerance. With zero
-outputs (s = 1) the ratio equals the plain step's own sum P_{k+1} / sum P_k;
-per mode it is least at s = b / c. For a response that is diagonal in p (the
-free field) c = b^2 / a and the minimiser is the per-mode inverse response. Parameter vector layout (float32 on the GPU):
+divergence fields Z_f after the forward 4D FFT, the residual energy e_p(x)
+left in the mode by the step with every multiplier scaled by x is measured
+at three points: e(0) = P_k = sum_f |Z_f^k|^2, e(1) = P_{k+1} (the plain
+step) and e(sigma) = E_k (a probe step with all multipliers times sigma,
+undone afterwards). The quadratic through them, e(x) = a - 2 b x + c x^2, is
+the model of the mode's response to the network's scale s(p) =
+m(p)/m0(p) = exp(o_s(p) + o_a(0)) (c is raised to b^2/a where needed so that
+e >= 0). The predicted residual ratio of one sample (trajectory, k) is
+sum_p e_p(s_p) / sum_p a, and the loss of the sample is its natural
+logarithm (floored at ln 1e-12, where the gradient is zero): the mean over
+samples is the predicted mean log-decrease per step, whose inverse sets the
+number of steps to a tolerance. With zero outputs (s = 1) the ratio is the
+plain step's own sum P_{k+1} / sum P_k. For a linear response (the free
+field) e is exactly quadratic with b = (1 - r) a, c = (1 - r)^2 a, r the
+plain step's contraction, and the minimiser is the per-mode inverse response.
+Parameter vector layout (float32 on the GPU):
 W1 (64x6), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2).
 """
 from __future__ import annotations
@@ -190,6 +192,10 @@ def record(spec_k, spec_k1, dims, tuples):
     return fold(p, dims, tuples), fold(c, dims, tuples)
 
 
-def targets(p_k, c_k, p_next):
-    """Per-tuple loss coefficients (a, b, c) from P_k, C_k and P_{k+1}."""
-    return p_k, p_k - c_k, p_k - 2.0 * c_k + p_next
+def targets(p_k, p_next, p_probe, sigma):
+    """Coefficients (a, b, c) of the quadratic a - 2 b x + c x^2 through (0, P_k), (sigma, E_k), (1, P_{k+1})."""
+    v = (p_probe - p_k - sigma * (p_next - p_k)) / (sigma * sigma - sigma)
+    b = -0.5 * (p_next - p_k - v)
+    safe = np.where(p_k > 0, p_k, 1.0)
+    c = np.where(p_k > 0, np.maximum(v, b * b / safe), v)
+    return p_k, b, c

@@ -95,7 +95,7 @@ struct Layout {
     int ntuples;      // distinct momentum tuples (N_mu/2 + 1 per axis)
     // workspace offsets
     size_t off_ctl, off_part, off_sin2, off_tw, off_d, off_q, off_g, off_acc, off_links[2], off_mlp, off_mtab,
-        off_spec[2], off_rec, total;
+        off_spec[4], off_rec, total;
     // GF_MIXED: a float child (bulk) and a double child (polish) share the workspace
     bool mixed;
     size_t child_off[2];
@@ -214,12 +214,12 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     if (L.learned) o = align_up(o + kMlpParams * sizeof(float), kAlign);
     L.off_mtab = o;
     if (L.learned) o = align_up(o + (size_t)L.ntuples * csz / 2, kAlign);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < 4; ++i) {
         L.off_spec[i] = o;
         if (L.record) o = align_up(o + 4 * L.ps * csz, kAlign);
     }
     L.off_rec = o;
-    if (L.record) o = align_up(o + (size_t)L.ntuples * 2 * sizeof(double), kAlign);
+    if (L.record) o = align_up(o + (size_t)L.ntuples * 3 * sizeof(double), kAlign);
     L.total = o;
     return GF_OK;
 }
@@ -282,7 +282,8 @@ struct gf_ctx {
     int rejects = 0;           // consecutive rejected learned steps
     int fallbacks = 0;         // rejected learned steps in total
     // spectrum recording
-    void* spec[2];
+    void* spec[4];  // spectra of the plain iterates (0, 1) and of the probe steps (2, 3)
+    double coef_scale = 1.0;  // factor on the plain multiplier (the recorder's probe step)
     double* rec;
     void* spec_capture = nullptr;  // where the (z, t) pass writes the spectrum, if anywhere
     // GF_MIXED parent: the float and double children, and the active phase
@@ -478,7 +479,7 @@ template <typename T>
 void launch_zt(gf_ctx* c, void* Z, int force) {
     const Layout& L = c->L;
     const bool no_fa = (c->p.flags & GF_FLAG_NO_FA) != 0;
-    const double coef = 0.5 * c->p.alpha * (no_fa ? 1.0 : 16.0) / (double)L.vol;
+    const double coef = 0.5 * c->p.alpha * (no_fa ? 1.0 : 16.0) / (double)L.vol * c->coef_scale;
     tstart(c, GF_K_FFT_ZT);
     const T* mtab = c->net_this ? reinterpret_cast<const T*>(c->mtab) : nullptr;
     cx<T>* spec = reinterpret_cast<cx<T>*>(c->spec_capture);
@@ -581,16 +582,16 @@ gf_status one_iteration(gf_ctx* c, long long k) {
     if (c->L.fp32) {
         launch_xy<float, false>(c, c->D, c->Q, 0, true);
         if (c->net_this)
-            hipLaunchKernelGGL(k_mlp_table<float>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st, c->mlp,
-                               reinterpret_cast<const float*>(c->sin2), c->tg, coef, c->ctl,
+            hipLaunchKernelGGL(k_mlp_table<float>, dim3((c->L.ntuples + kTableTuplesPerBlock - 1) / kTableTuplesPerBlock), dim3(256), 0, c->st, c->mlp,
+                               reinterpret_cast<const float*>(c->sin2), c->tg, coef, c->ctl, 0,
                                reinterpret_cast<float*>(c->mtab));
         launch_zt<float>(c, c->Q, 0);
         launch_gauge_pass<float>(c, 0);
     } else {
         launch_xy<double, false>(c, c->D, c->Q, 0, true);
         if (c->net_this)
-            hipLaunchKernelGGL(k_mlp_table<double>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st, c->mlp,
-                               reinterpret_cast<const double*>(c->sin2), c->tg, coef, c->ctl,
+            hipLaunchKernelGGL(k_mlp_table<double>, dim3((c->L.ntuples + kTableTuplesPerBlock - 1) / kTableTuplesPerBlock), dim3(256), 0, c->st, c->mlp,
+                               reinterpret_cast<const double*>(c->sin2), c->tg, coef, c->ctl, 0,
                                reinterpret_cast<double*>(c->mtab));
         launch_zt<double>(c, c->Q, 0);
         launch_gauge_pass<double>(c, 0);
@@ -794,7 +795,7 @@ void carve(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsi
     c->Acc = L.acc ? ws + L.off_acc : nullptr;
     c->mlp = L.learned ? reinterpret_cast<float*>(ws + L.off_mlp) : nullptr;
     c->mtab = L.learned ? ws + L.off_mtab : nullptr;
-    for (int i = 0; i < 2; ++i) c->spec[i] = L.record ? ws + L.off_spec[i] : nullptr;
+    for (int i = 0; i < 4; ++i) c->spec[i] = L.record ? ws + L.off_spec[i] : nullptr;
     c->rec = L.record ? reinterpret_cast<double*>(ws + L.off_rec) : nullptr;
     for (int d = 0; d < 4; ++d) {
         c->tg.n[d] = L.n[d];
@@ -1683,48 +1684,91 @@ gf_status gf_mlp_set_weights(gf_ctx* c, const float* d_params, int32_t enable) {
     return GF_OK;
 }
 
-gf_status gf_record_spectra(gf_ctx* c, int64_t n, double* d_records, double* h_theta) {
+gf_status gf_mlp_multipliers(gf_ctx* c, void* d_out) {
+    if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    if (c->L.mixed || !c->mlp) return fail(c, GF_ESTATE, "context was created without GF_FLAG_LEARNED");
+    if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
+    const double coef = 0.5 * c->p.alpha * 16.0 / (double)c->L.vol;
+    const dim3 grid((unsigned)((c->L.ntuples + kTableTuplesPerBlock - 1) / kTableTuplesPerBlock));
+    if (c->L.fp32)
+        hipLaunchKernelGGL(k_mlp_table<float>, grid, dim3(256), 0, c->st, c->mlp,
+                           reinterpret_cast<const float*>(c->sin2), c->tg, coef, c->ctl, 1,
+                           reinterpret_cast<float*>(d_out));
+    else
+        hipLaunchKernelGGL(k_mlp_table<double>, grid, dim3(256), 0, c->st, c->mlp,
+                           reinterpret_cast<const double*>(c->sin2), c->tg, coef, c->ctl, 1,
+                           reinterpret_cast<double*>(d_out));
+    gf_status s = launched(c, "table launch");
+    if (s == GF_OK) s = check_hip(c, hipStreamSynchronize(c->st), "sync");
+    return s;
+}
+
+gf_status gf_record_spectra(gf_ctx* c, int64_t n, double probe_scale, double* d_records, double* h_theta) {
     if (!c) return GF_EINVAL;
     if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed || !c->rec) return fail(c, GF_ESTATE, "context was created without GF_FLAG_RECORD_SPECTRA");
     if (n < 1 || !d_records || !h_theta) return fail(c, GF_EINVAL, "bad arguments");
+    if (!(probe_scale > 0.0) || !(probe_scale < 1.0)) return fail(c, GF_EINVAL, "probe_scale must be in (0, 1)");
     if (n + 1 > kHist) return fail(c, GF_EINVAL, "n too large");
     const bool was_on = c->net_on;
     c->net_on = false;
     gf_status s = set_tol(c, -1.0);
+    if (s == GF_OK) s = set_guard(c, 0);
     if (s == GF_OK) s = read_head(c);
     const long long k0 = c->k_host;
-    const size_t recn = (size_t)c->L.ntuples * 2;
+    const size_t recn = (size_t)c->L.ntuples * 3;
+    auto forward_passes = [&]() {  // spectrum of D into spec_capture (forward (x, y) and (z, t) passes into Q)
+        if (c->L.fp32) {
+            launch_xy<float, false>(c, c->D, c->Q, 1, true);
+            launch_zt<float>(c, c->Q, 1);
+        } else {
+            launch_xy<double, false>(c, c->D, c->Q, 1, true);
+            launch_zt<double>(c, c->Q, 1);
+        }
+        return launched(c, "spectrum launch");
+    };
     for (int64_t i = 0; i <= n && s == GF_OK; ++i) {
+        const long long k = k0 + i;
         c->spec_capture = c->spec[i & 1];
         if (i < n) {
-            s = one_iteration(c, c->k_host + i);
-        } else {  // spectrum of the last iterate only: forward (x, y) and (z, t) passes into Q
-            if (c->L.fp32) {
-                launch_xy<float, false>(c, c->D, c->Q, 1, true);
-                launch_zt<float>(c, c->Q, 1);
-            } else {
-                launch_xy<double, false>(c, c->D, c->Q, 1, true);
-                launch_zt<double>(c, c->Q, 1);
+            // probe: the update with every multiplier times probe_scale (captures the spectrum of step i) ...
+            c->coef_scale = probe_scale;
+            s = one_iteration(c, k);
+            c->coef_scale = 1.0;
+            c->spec_capture = c->spec[2 + (i & 1)];
+            if (s == GF_OK) s = forward_passes();  // ... and the spectrum of its result
+            c->spec_capture = nullptr;
+            // undo it (the links of step i are still in the other buffer), re-measure, take the plain step
+            if (s == GF_OK) {
+                hipLaunchKernelGGL(k_rollback, dim3(1), dim3(64), 0, c->st, c->ctl, k);
+                s = launched(c, "rollback launch");
             }
-            s = launched(c, "spectrum launch");
+            c->k_host = k;
+            if (s == GF_OK) s = launch_measure(c);
+            if (s == GF_OK) s = one_iteration(c, k);
+        } else {
+            s = forward_passes();  // spectrum of the last iterate only
         }
         c->spec_capture = nullptr;
         if (s == GF_OK && i >= 1) {
-            const int a = (i - 1) & 1, b = i & 1;
+            const int a = (i - 1) & 1, b = i & 1, pb = 2 + ((i - 1) & 1);
             if (c->L.fp32)
                 hipLaunchKernelGGL(k_record_tuples<float>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st,
                                    reinterpret_cast<const cx<float>*>(c->spec[a]),
-                                   reinterpret_cast<const cx<float>*>(c->spec[b]), c->L.ps, c->tg,
+                                   reinterpret_cast<const cx<float>*>(c->spec[b]),
+                                   reinterpret_cast<const cx<float>*>(c->spec[pb]), c->L.ps, c->tg,
                                    d_records + (size_t)(i - 1) * recn);
             else
                 hipLaunchKernelGGL(k_record_tuples<double>, dim3((c->L.ntuples + 255) / 256), dim3(256), 0, c->st,
                                    reinterpret_cast<const cx<double>*>(c->spec[a]),
-                                   reinterpret_cast<const cx<double>*>(c->spec[b]), c->L.ps, c->tg,
+                                   reinterpret_cast<const cx<double>*>(c->spec[b]),
+                                   reinterpret_cast<const cx<double>*>(c->spec[pb]), c->L.ps, c->tg,
                                    d_records + (size_t)(i - 1) * recn);
             s = launched(c, "record launch");
         }
     }
+    c->k_host = k0 + n;
     if (s == GF_OK) s = loop_finalize(c);
     if (s == GF_OK) s = read_head(c);
     if (s == GF_OK) s = unpack_links(c, c->links_user);
@@ -1844,10 +1888,11 @@ gf_status gf_mlp_train_step(float* d_params, float* d_m, float* d_v, int64_t ste
 int32_t gf_mlp_param_count(void) { return kMlpParams; }
 
 gf_status gf_mlp_make_samples(const double* d_records, int32_t n_records, const double* d_theta, int32_t first,
-                              int32_t every, int32_t n_samples, int64_t k0, const int32_t* dims, float* d_x,
-                              float* d_tgt, void* stream) {
+                              int32_t every, int32_t n_samples, int64_t k0, double probe_scale, const int32_t* dims,
+                              float* d_x, float* d_tgt, void* stream) {
     if (!d_records || !d_theta || !dims || !d_x || !d_tgt || n_samples < 1 || every < 1 || first < 0 || k0 < 0)
         return GF_EINVAL;
+    if (!(probe_scale > 0.0) || !(probe_scale < 1.0)) return GF_EINVAL;
     if ((int64_t)first + (int64_t)(n_samples - 1) * every > (int64_t)n_records - 2) return GF_EINVAL;
     TupleGeom tg;
     tg.count = 1;
@@ -1859,8 +1904,8 @@ gf_status gf_mlp_make_samples(const double* d_records, int32_t n_records, const 
     }
     const int64_t nrows = (int64_t)n_samples * tg.count;
     hipLaunchKernelGGL(k_make_samples, dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0,
-                       reinterpret_cast<hipStream_t>(stream), d_records, d_theta, first, every, (long long)k0, nrows,
-                       tg, d_x, d_tgt);
+                       reinterpret_cast<hipStream_t>(stream), d_records, d_theta, first, every, (long long)k0,
+                       probe_scale, nrows, tg, d_x, d_tgt);
     return mlp_status(hipGetLastError(), "make samples");
 }
 

@@ -41,12 +41,14 @@ __device__ __forceinline__ int tuple_index(const TupleGeom& tg, int nx, int ny, 
 }
 
 // -------------------------------------------------------------- recording
-// Per tuple: P from spectrum Sk and C from Sk, Sk1 (both full 4D spectra of
-// the four packed fields, planes ps apart), summed over the tuple's +-n
-// reflections; out[2*i] = P, out[2*i+1] = C (double).
+// Per tuple, summed over the tuple's +-n reflections and the four packed
+// fields (full 4D spectra, planes ps apart): out[3i] = P = |Sk|^2,
+// out[3i+1] = C = Re Sk1 conj(Sk) (Sk1: after the plain step),
+// out[3i+2] = E = |Sp|^2 (Sp: after the probe step). Double.
 template <typename T>
 __global__ void __launch_bounds__(256) k_record_tuples(const cx<T>* __restrict__ Sk, const cx<T>* __restrict__ Sk1,
-                                                       size_t ps, TupleGeom tg, double* __restrict__ out) {
+                                                       const cx<T>* __restrict__ Sp, size_t ps, TupleGeom tg,
+                                                       double* __restrict__ out) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= tg.count) return;
     int t[4], r = i;
@@ -54,7 +56,7 @@ __global__ void __launch_bounds__(256) k_record_tuples(const cx<T>* __restrict__
         t[m] = r % tg.h[m];
         r /= tg.h[m];
     }
-    double P = 0.0, C = 0.0;
+    double P = 0.0, C = 0.0, E = 0.0;
     for (int a = 0; a < 16; ++a) {
         int q[4];
         bool dup = false;
@@ -66,13 +68,15 @@ __global__ void __launch_bounds__(256) k_record_tuples(const cx<T>* __restrict__
         if (dup) continue;
         const size_t s = (size_t)q[0] + (size_t)tg.n[0] * (q[1] + (size_t)tg.n[1] * (q[2] + (size_t)tg.n[2] * q[3]));
         for (int f = 0; f < 4; ++f) {
-            const cx<T> z0 = Sk[(size_t)f * ps + s], z1 = Sk1[(size_t)f * ps + s];
+            const cx<T> z0 = Sk[(size_t)f * ps + s], z1 = Sk1[(size_t)f * ps + s], zp = Sp[(size_t)f * ps + s];
             P += (double)z0.re * z0.re + (double)z0.im * z0.im;
             C += (double)z1.re * z0.re + (double)z1.im * z0.im;
+            E += (double)zp.re * zp.re + (double)zp.im * zp.im;
         }
     }
-    out[2 * i] = P;
-    out[2 * i + 1] = C;
+    out[3 * i] = P;
+    out[3 * i + 1] = C;
+    out[3 * i + 2] = E;
 }
 
 // ------------------------------------------------------------ inference
@@ -83,81 +87,144 @@ __device__ __forceinline__ void mlp_features(const float* sin2_4, float log10_th
     x[5] = k * (1.0f / 64.0f);
 }
 
-// One row through the network with weights in LDS; returns both outputs.
-__device__ __forceinline__ void mlp_row(const float* __restrict__ w, const float x[kMlpIn], float& o0, float& o1) {
-    float h1[kMlpH];
-#pragma unroll
-    for (int j = 0; j < kMlpH; ++j) {
-        float a = w[kOffB1 + j];
-#pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) a = fmaf(w[kOffW1 + j * kMlpIn + i], x[i], a);
-        h1[j] = tanhf(a);
-    }
-    float a0 = w[kOffB3], a1 = w[kOffB3 + 1];
-    for (int j = 0; j < kMlpH; ++j) {
-        float a = w[kOffB2 + j];
-#pragma unroll
-        for (int i = 0; i < kMlpH; ++i) a = fmaf(w[kOffW2 + j * kMlpH + i], h1[i], a);
-        const float h2 = tanhf(a);
-        a0 = fmaf(w[kOffW3 + j], h2, a0);
-        a1 = fmaf(w[kOffW3 + kMlpH + j], h2, a1);
-    }
-    o0 = a0;
-    o1 = a1;
-}
-
 // Multiplier table for the current iteration: mtab[i] = coef / p^2 *
-// exp(o_s(i) + o_a(0)) (coef = (alpha/2) p2max / V), 0 at the zero tuple.
-// theta and the iteration count come from the control block.
+// exp(o_s(i) + o_a(0)) (coef = (alpha/2) p2max / V), 0 at the zero tuple;
+// theta and the iteration count come from the control block. The hidden
+// layer 64 x 64 is a dense contraction over the tuples and runs on the matrix
+// cores: a wave takes kTableGroups groups of 16 tuples; for each, every lane
+// evaluates layer 1 for the 16 hidden units k = l/16 + 4m of tuple l%16 (its
+// A operand), v_mfma_f32_16x16x4f32 forms the 16 x 64 pre-activations of
+// layer 2 in four 16 x 16 tiles over K = 64 (16 steps), and layer 3 is a sum
+// across the 16 lanes that hold one tuple's hidden units. The lanes' W2
+// operands stay in registers for all groups. o_a is evaluated once per block
+// at the zero tuple, one hidden unit per lane of wave 0.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kTableGroups = 4;
+constexpr int kTableTuplesPerBlock = 4 * 16 * kTableGroups;
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ params, const T* __restrict__ sin2,
                                                    TupleGeom tg, double coef, const Ctl* __restrict__ ctl,
-                                                   T* __restrict__ mtab) {
-    if (ctl->done) return;
-    __shared__ float w[kMlpParams];
-    for (int i = threadIdx.x; i < kMlpParams; i += 256) w[i] = params[i];
+                                                   int force, T* __restrict__ mtab) {
+    if (!force && ctl->done) return;
+    constexpr int W2S = kMlpH + 1;  // padded row stride of W2 in LDS
+    __shared__ float w1[kMlpH * kMlpIn], b1[kMlpH], w2[kMlpH * W2S], b2[kMlpH], w3[2 * kMlpH], h1z[kMlpH];
+    __shared__ float oa_s;
+    for (int i = threadIdx.x; i < kMlpH * kMlpIn; i += 256) w1[i] = params[kOffW1 + i];
+    for (int i = threadIdx.x; i < kMlpH * kMlpH; i += 256) w2[(i / kMlpH) * W2S + i % kMlpH] = params[kOffW2 + i];
+    for (int i = threadIdx.x; i < kMlpH; i += 256) {
+        b1[i] = params[kOffB1 + i];
+        b2[i] = params[kOffB2 + i];
+        w3[i] = params[kOffW3 + i];
+        w3[kMlpH + i] = params[kOffW3 + kMlpH + i];
+    }
     __syncthreads();
     const float lt = (float)log10(fmax(ctl->theta, 1e-300));
     const float kk = (float)ctl->iters;
-    // global log step: second output at the zero tuple (every block computes the same value)
-    __shared__ float oa_s;
-    if (threadIdx.x == 0 && blockIdx.x != 0) {
-        float zx[kMlpIn], zs[4] = {0.f, 0.f, 0.f, 0.f}, o0, o1;
+    const float b30 = params[kOffB3], b31 = params[kOffB3 + 1];
+    if (threadIdx.x < kMlpH) {  // o_a: layer 1 of the zero tuple
+        const int j = threadIdx.x;
+        float zx[kMlpIn];
+        const float zs[4] = {0.f, 0.f, 0.f, 0.f};
         mlp_features(zs, lt, kk, zx);
-        mlp_row(w, zx, o0, o1);
-        oa_s = o1;
+        float a = b1[j];
+#pragma unroll
+        for (int i = 0; i < kMlpIn; ++i) a = fmaf(w1[j * kMlpIn + i], zx[i], a);
+        h1z[j] = tanhf(a);
     }
     __syncthreads();
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    int t[4], r = i < tg.count ? i : 0;
-    for (int m = 0; m < 4; ++m) {
-        t[m] = r % tg.h[m];
-        r /= tg.h[m];
+    if (threadIdx.x < kMlpH) {  // layers 2 and 3 of the zero tuple, second output
+        const int j = threadIdx.x;
+        float a = b2[j];
+        for (int i = 0; i < kMlpH; ++i) a = fmaf(w2[j * W2S + i], h1z[i], a);
+        float p = w3[kMlpH + j] * tanhf(a);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
+        if (j == 0) oa_s = p + b31;
     }
+    __syncthreads();
+    const double oa = (double)oa_s;
+    const int l = threadIdx.x & 63, kq = l >> 4, lc = l & 15;
+    // B operands: W2[unit n*16 + lc][input 4m + kq]
+    float bw[4][16];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int m = 0; m < 16; ++m) bw[n][m] = w2[(n * 16 + lc) * W2S + 4 * m + kq];
     const T* sx = sin2;
     const T* sy = sx + tg.n[0];
     const T* sz = sy + tg.n[1];
     const T* st = sz + tg.n[2];
-    float s4[4] = {(float)sx[t[0]], (float)sy[t[1]], (float)sz[t[2]], (float)st[t[3]]};
-    const double p2 = (double)sx[t[0]] + (double)sy[t[1]] + (double)sz[t[2]] + (double)st[t[3]];
-    float x[kMlpIn], o0 = 0.f, o1 = 0.f;
-    if (i < tg.count) {
+    for (int grp = 0; grp < kTableGroups; ++grp) {
+        const int t0 = blockIdx.x * kTableTuplesPerBlock + ((threadIdx.x >> 6) * kTableGroups + grp) * 16;
+        // layer 1 for tuple t0 + lc, hidden units kq + 4m
+        int ti = t0 + lc;
+        if (ti >= tg.count) ti = 0;
+        int c4[4], r = ti;
+        for (int m = 0; m < 4; ++m) {
+            c4[m] = r % tg.h[m];
+            r /= tg.h[m];
+        }
+        const float s4[4] = {(float)sx[c4[0]], (float)sy[c4[1]], (float)sz[c4[2]], (float)st[c4[3]]};
+        float x[kMlpIn];
         mlp_features(s4, lt, kk, x);
-        mlp_row(w, x, o0, o1);
+        float h1[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = kq + 4 * m;
+            float a = b1[j];
+#pragma unroll
+            for (int i = 0; i < kMlpIn; ++i) a = fmaf(w1[j * kMlpIn + i], x[i], a);
+            h1[m] = tanhf(a);
+        }
+        // layer 2: acc[n] holds rows 4*kq + q (tuples t0 + 4*kq + q), unit n*16 + lc
+        f32x4 acc[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int m = 0; m < 16; ++m) acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(h1[m], bw[n][m], acc[n], 0, 0, 0);
+        }
+        // layer 3, first output: partial sums over this lane's units, then over the 16 lanes of the group
+        float o0[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const int j = n * 16 + lc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o0[q] = fmaf(w3[j], tanhf(acc[n][q] + b2[j]), o0[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) o0[q] += __shfl_xor(o0[q], o, 64);
+        if (lc < 4) {
+            const int t = t0 + 4 * kq + lc;
+            const float os = lc == 0 ? o0[0] : lc == 1 ? o0[1] : lc == 2 ? o0[2] : o0[3];
+            if (t < tg.count) {
+                int r2 = t, d4[4];
+                for (int m = 0; m < 4; ++m) {
+                    d4[m] = r2 % tg.h[m];
+                    r2 /= tg.h[m];
+                }
+                const double p2 = (double)sx[d4[0]] + (double)sy[d4[1]] + (double)sz[d4[2]] + (double)st[d4[3]];
+                mtab[t] = p2 > 0.0 ? (T)(coef / p2 * exp((double)(os + b30) + oa)) : T(0);
+            }
+        }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) oa_s = o1;  // row 0 is the zero tuple
-    __syncthreads();
-    if (i < tg.count) mtab[i] = p2 > 0.0 ? (T)(coef / p2 * exp((double)o0 + (double)oa_s)) : T(0);
 }
 
 // --------------------------------------------------------------- training
-// Samples from records: record r holds (P_r, C_r) per tuple. Sample s uses
+// Samples from records: record r holds (P_r, C_r, E_r) per tuple, E_r the
+// energy after the probe step (every multiplier times sigma). Sample s uses
 // record r = first + s*every and the next one: row s*T + i gets the features
-// of tuple i at (theta[r], iteration k0 + r) and the loss coefficients
-// (a, b, c) = (P_r, P_r - C_r, P_r - 2 C_r + P_{r+1}), formed in double.
+// of tuple i at (theta[r], iteration k0 + r) and the coefficients (a, b, c)
+// of the quadratic e(x) = a - 2 b x + c x^2 through the residual energies
+// e(0) = P_r, e(sigma) = E_r and e(1) = P_{r+1}, with c raised to b^2/a where
+// needed so that e stays >= 0; formed in double.
 __global__ void __launch_bounds__(256) k_make_samples(const double* __restrict__ rec, const double* __restrict__ theta,
-                                                      int first, int every, long long k0, int64_t nrows,
-                                                      TupleGeom tg, float* __restrict__ X, float* __restrict__ tgt) {
+                                                      int first, int every, long long k0, double sigma,
+                                                      int64_t nrows, TupleGeom tg, float* __restrict__ X,
+                                                      float* __restrict__ tgt) {
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= nrows) return;
     const int s = (int)(row / tg.count), i = (int)(row % tg.count);
@@ -176,11 +243,14 @@ __global__ void __launch_bounds__(256) k_make_samples(const double* __restrict__
     mlp_features(s4, (float)log10(fmax(theta[r], 1e-300)), (float)(k0 + r), x);
 #pragma unroll
     for (int c = 0; c < kMlpIn; ++c) X[row * kMlpIn + c] = x[c];
-    const double P = rec[(r * tg.count + i) * 2], C = rec[(r * tg.count + i) * 2 + 1];
-    const double Pn = rec[((r + 1) * tg.count + i) * 2];
+    const double P = rec[(r * tg.count + i) * 3], E = rec[(r * tg.count + i) * 3 + 2];
+    const double Pn = rec[((r + 1) * tg.count + i) * 3];
+    const double v = (E - P - sigma * (Pn - P)) / (sigma * sigma - sigma);
+    const double b = -0.5 * (Pn - P - v);
+    const double c = P > 0.0 ? fmax(v, b * b / P) : v;
     tgt[row * 3] = (float)P;
-    tgt[row * 3 + 1] = (float)(P - C);
-    tgt[row * 3 + 2] = (float)(P - 2.0 * C + Pn);
+    tgt[row * 3 + 1] = (float)b;
+    tgt[row * 3 + 2] = (float)c;
 }
 
 // Rows are momentum tuples of samples; sample s owns rows [off[s], off[s+1]),

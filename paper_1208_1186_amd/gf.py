@@ -76,9 +76,10 @@ def _signatures(lib):
         "gf_kernel_times": (i32, [_P, i32, pd, ctypes.POINTER(ctypes.c_int64)]),
         "gf_mlp_param_count": (i32, []),
         "gf_mlp_set_weights": (i32, [_P, _P, i32]),
-        "gf_record_spectra": (i32, [_P, i64, _P, pd]),
+        "gf_mlp_multipliers": (i32, [_P, _P]),
+        "gf_record_spectra": (i32, [_P, i64, dbl, _P, pd]),
         "gf_mlp_workspace_bytes": (sz, [i64, i32]),
-        "gf_mlp_make_samples": (i32, [_P, i32, _P, i32, i32, i32, i64, ctypes.POINTER(i32), _P, _P, _P]),
+        "gf_mlp_make_samples": (i32, [_P, i32, _P, i32, i32, i32, i64, dbl, ctypes.POINTER(i32), _P, _P, _P]),
         "gf_mlp_forward": (i32, [_P, _P, i64, _P, _P, sz, _P]),
         "gf_mlp_loss_grad": (i32, [_P, _P, _P, _P, i32, i64, _P, _P, sz, _P, pd]),
         "gf_mlp_adam": (i32, [_P, _P, _P, _P, i64, ctypes.c_float, _P]),
@@ -269,11 +270,15 @@ def gf_mlp_set_weights(ctx, d_params, enable=True):
     _check(ctx, load().gf_mlp_set_weights(ctx, _P(d_params), 1 if enable else 0))
 
 
-def gf_record_spectra(ctx, n, d_records):
-    """Run n plain FA updates recording per-tuple (P_k, C_k) into d_records; returns theta_k (numpy)."""
+def gf_mlp_multipliers(ctx, d_out):
+    _check(ctx, load().gf_mlp_multipliers(ctx, _P(d_out)))
+
+
+def gf_record_spectra(ctx, n, d_records, probe_scale=0.7):
     import numpy as np
     th = np.zeros(n)
-    _check(ctx, load().gf_record_spectra(ctx, int(n), _P(d_records), th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    _check(ctx, load().gf_record_spectra(ctx, int(n), float(probe_scale), _P(d_records),
+                                         th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return th
 
 
@@ -286,10 +291,12 @@ def gf_mlp_workspace_bytes(n_rows, n_samples):
     return load().gf_mlp_workspace_bytes(int(n_rows), int(n_samples))
 
 
-def gf_mlp_make_samples(d_records, n_records, d_theta, first, every, n_samples, k0, dims, d_x, d_tgt, stream=0):
+def gf_mlp_make_samples(d_records, n_records, d_theta, first, every, n_samples, k0, probe_scale, dims, d_x, d_tgt,
+                        stream=0):
     arr = (ctypes.c_int32 * 4)(*[int(d) for d in dims])
     _mlp_check(load().gf_mlp_make_samples(_P(d_records), int(n_records), _P(d_theta), int(first), int(every),
-                                          int(n_samples), int(k0), arr, _P(d_x), _P(d_tgt), _P(stream)),
+                                          int(n_samples), int(k0), float(probe_scale), arr, _P(d_x), _P(d_tgt),
+                                          _P(stream)),
                "gf_mlp_make_samples")
 
 
@@ -407,13 +414,13 @@ class GaugeFixer:
         self._mlp = params.contiguous()
         gf_mlp_set_weights(self.ctx, self._mlp.data_ptr(), enable)
 
-    def record(self, n):
-        """n plain FA updates; returns (records tensor (n, tuples, 2) float64, theta_k numpy)."""
+    def record(self, n, probe_scale=0.7):
+        """n plain FA updates with probe steps; returns (records tensor (n, tuples, 3) float64, theta_k numpy)."""
         import torch
         nt, nz, ny, nx = self.links.shape[:4]
         ntup = (nx // 2 + 1) * (ny // 2 + 1) * (nz // 2 + 1) * (nt // 2 + 1)
-        rec = torch.empty((n, ntup, 2), dtype=torch.float64, device=self.links.device)
-        th = gf_record_spectra(self.ctx, n, rec.data_ptr())
+        rec = torch.empty((n, ntup, 3), dtype=torch.float64, device=self.links.device)
+        th = gf_record_spectra(self.ctx, n, rec.data_ptr(), probe_scale)
         return rec, th
 
     def get_gauge(self, out=None):

@@ -31,8 +31,11 @@ def n_tuples(dims):
     return int(np.prod([d // 2 + 1 for d in dims]))
 
 
+PROBE_SCALE = 0.7  # the recorder's probe step scales every multiplier by this
+
+
 def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=0.08, device="cuda:0",
-            every=1, theta_min=1e-13, log=None):
+            every=1, theta_min=1e-13, probe_scale=PROBE_SCALE, log=None):
     """Record plain-FA trajectories of the given seeds; returns (X, TGT, n_samples) as CUDA tensors.
 
     A sample pairs iteration r with r + 1; iterations are kept while theta_r > theta_min (below, the
@@ -45,7 +48,7 @@ def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=
         u = synth.make_config(dims, seed, eps)
         links = torch.from_numpy(u).to(device)
         fx = gf.GaugeFixer(links, precision, alpha=alpha, flags=gf.FLAG_RECORD_SPECTRA)
-        rec, theta = fx.record(n_iter)
+        rec, theta = fx.record(n_iter, probe_scale)
         fx.close()
         live = int(np.argmax(theta <= theta_min)) if np.any(theta <= theta_min) else n_iter
         last = min(live, n_iter - 1) - 1  # the last usable record has a successor
@@ -55,8 +58,8 @@ def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=
         th = torch.as_tensor(theta, dtype=torch.float64, device=device)
         X = torch.empty((n * T, 6), dtype=torch.float32, device=device)
         TG = torch.empty((n * T, 3), dtype=torch.float32, device=device)
-        gf.gf_mlp_make_samples(rec.data_ptr(), n_iter, th.data_ptr(), 0, every, n, 0, dims, X.data_ptr(),
-                               TG.data_ptr(), torch.cuda.current_stream().cuda_stream)
+        gf.gf_mlp_make_samples(rec.data_ptr(), n_iter, th.data_ptr(), 0, every, n, 0, probe_scale, dims,
+                               X.data_ptr(), TG.data_ptr(), torch.cuda.current_stream().cuda_stream)
         torch.cuda.current_stream().synchronize()
         xs.append(X)
         ts.append(TG)

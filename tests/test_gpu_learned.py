@@ -112,44 +112,78 @@ def test_adam_step_matches_oracle():
 
 @pytest.mark.parametrize("dims", [(8, 4, 6, 4), (8, 8, 8, 8)])
 def test_recorded_spectra_match_oracle(dims):
+    sig = 0.7
     u = synth.make_config(dims, 11)
     links = dev(u)
     fx = gf.GaugeFixer(links, "fp64_18", flags=gf.FLAG_RECORD_SPECTRA)
-    rec, theta = fx.record(3)
+    rec, theta = fx.record(3, sig)
     rec = rec.cpu().numpy()
     tuples = mlp.folded_tuples(dims)
+    kern = landau.fa_kernel(dims) * sig
     cur = u
-    specs = []
+    specs, probes = [], []
     for k in range(4):
         specs.append(mlp.packed_spectrum(landau.divergence(cur)))
         if k < 3:
             assert theta[k] == pytest.approx(landau.theta(cur), rel=1e-12)
+            up, *_ = landau.fa_step(cur, ALPHA, kernel=kern)
+            probes.append(mlp.packed_spectrum(landau.divergence(up)))
             cur, *_ = landau.fa_step(cur, ALPHA)
     for k in range(3):
         p, c = mlp.record(specs[k], specs[k + 1], dims, tuples)
-        assert np.max(np.abs(rec[k, :, 0] - p)) <= 1e-10 * np.max(np.abs(p))
-        assert np.max(np.abs(rec[k, :, 1] - c)) <= 1e-10 * np.max(np.abs(p))
-    # the links were advanced by exactly the recorded updates
+        e, _ = mlp.record(probes[k], probes[k], dims, tuples)
+        scale = np.max(np.abs(p))
+        assert np.max(np.abs(rec[k, :, 0] - p)) <= 1e-10 * scale
+        assert np.max(np.abs(rec[k, :, 1] - c)) <= 1e-10 * scale
+        assert np.max(np.abs(rec[k, :, 2] - e)) <= 1e-10 * scale
+    # the probe steps were undone: the links were advanced by exactly the plain updates
     assert np.max(np.abs(links.cpu().numpy() - cur)) < 1e-12
     # training rows assembled on the GPU match the oracle's features and loss coefficients
     n, every = 2, 1
     X = torch.empty((n * len(tuples), 6), dtype=torch.float32, device="cuda:0")
     TG = torch.empty((n * len(tuples), 3), dtype=torch.float32, device="cuda:0")
     rec_d, th_d = dev(rec), dev(theta)
-    gf.gf_mlp_make_samples(rec_d.data_ptr(), 3, th_d.data_ptr(), 0, every, n, 0, dims, X.data_ptr(), TG.data_ptr())
+    gf.gf_mlp_make_samples(rec_d.data_ptr(), 3, th_d.data_ptr(), 0, every, n, 0, sig, dims, X.data_ptr(),
+                           TG.data_ptr())
     X, TG = X.cpu().numpy(), TG.cpu().numpy()
     psq = mlp.tuple_psq(dims, tuples)
     for k in range(n):
         rows = slice(k * len(tuples), (k + 1) * len(tuples))
         assert np.max(np.abs(X[rows] - mlp.features(psq, theta[k], k))) < 1e-6
-        want = mlp.targets(rec[k, :, 0], rec[k, :, 1], rec[k + 1, :, 0])
+        want = mlp.targets(rec[k, :, 0], rec[k + 1, :, 0], rec[k, :, 2], sig)
         for j in range(3):
             assert np.max(np.abs(TG[rows, j] - want[j])) <= 1e-6 * np.max(np.abs(want[0])), (k, j)
     # a sample needs the record after it
     xb = torch.empty((2 * len(tuples), 6), dtype=torch.float32, device="cuda:0")
     tb = torch.empty((2 * len(tuples), 3), dtype=torch.float32, device="cuda:0")
     with pytest.raises(gf.GfError):
-        gf.gf_mlp_make_samples(rec_d.data_ptr(), 3, th_d.data_ptr(), 1, 1, 2, 0, dims, xb.data_ptr(), tb.data_ptr())
+        gf.gf_mlp_make_samples(rec_d.data_ptr(), 3, th_d.data_ptr(), 1, 1, 2, 0, sig, dims, xb.data_ptr(),
+                               tb.data_ptr())
+
+
+@pytest.mark.parametrize("dims", [(8, 8, 8, 8), (12, 8, 6, 4), (32, 32, 32, 32)])
+def test_multiplier_table_matches_oracle(dims):
+    """The inference table (matrix-core layer 2) against the oracle's multipliers at the current theta, k."""
+    u = synth.make_config(dims, 14)
+    links = dev(u)
+    fx = gf.GaugeFixer(links, "fp64_18", flags=gf.FLAG_LEARNED)
+    p = _params(15, scale=0.2)
+    p_d = dev(p)
+    fx.set_weights(p_d, enable=False)
+    fx.iterate(2)
+    theta, _ = fx.quality()
+    tuples = mlp.folded_tuples(dims)
+    out = torch.empty(len(tuples), dtype=torch.float64, device="cuda:0")
+    gf.gf_mlp_multipliers(fx.ctx, out.data_ptr())
+    got = out.cpu().numpy() * np.prod(dims)  # the table includes the inverse FFT's 1/V
+    psq = mlp.tuple_psq(dims, tuples)
+    p2 = psq.sum(1)
+    m0 = np.where(p2 > 0, 0.5 * ALPHA * 16.0 / np.where(p2 > 0, p2, 1.0), 0.0)
+    x = mlp.features(psq, theta, 2).astype(np.float32).astype(np.float64)
+    want = mlp.multipliers(p.astype(np.float64), x, m0)
+    assert got[0] == 0.0
+    rel = np.abs(got[1:] - want[1:]) / want[1:]
+    assert rel.max() < 2e-5, rel.max()
 
 
 def test_zero_output_network_is_plain_fa():

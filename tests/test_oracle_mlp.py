@@ -55,8 +55,22 @@ def test_zero_output_layer_is_plain_fa():
     assert np.array_equal(mlp.scales(th, x), np.ones(len(x)))
 
 
+def test_targets_interpolate_the_three_measured_energies():
+    rng = np.random.default_rng(11)
+    p = rng.uniform(1.0, 2.0, 50)
+    e1 = p * rng.uniform(0.05, 0.5, 50)
+    sig = 0.7
+    es = p * rng.uniform(0.3, 0.6, 50)
+    a, b, c = mlp.targets(p, e1, es, sig)
+    raised = c > (es - p - sig * (e1 - p)) / (sig * sig - sig) + 1e-12
+    for x, want in [(0.0, p), (1.0, e1), (sig, es)]:
+        got = a - 2 * b * x + c * x * x
+        assert np.allclose(got[~raised], want[~raised], rtol=1e-12)
+    assert np.all(a * c - b * b >= -1e-12 * a * a)  # e(x) >= 0 everywhere
+
+
 def test_zero_output_loss_is_plain_residual_ratio():
-    """At s = 1 the loss is sum P_{k+1} / sum P_k, i.e. (Parseval) the ratio of the
+    """At s = 1 the ratio is sum P_{k+1} / sum P_k, i.e. (Parseval) the ratio of the
     packed divergence's energy after and before a plain step, taken in position space."""
     dims = (4, 6, 4, 4)
     tuples = mlp.folded_tuples(dims)
@@ -64,14 +78,16 @@ def test_zero_output_loss_is_plain_residual_ratio():
     th = mlp.init_params(9)
     psq = mlp.tuple_psq(dims, tuples)
     for k in range(3):
-        pk, ck = mlp.record(specs[k], specs[k + 1], dims, tuples)
+        pk, _ = mlp.record(specs[k], specs[k + 1], dims, tuples)
         pn, _ = mlp.record(specs[k + 1], specs[k + 1], dims, tuples)
-        a, b, c = mlp.targets(pk, ck, pn)
+        sig = 0.7
+        probe = pk * (1 - sig) ** 2 + pn * sig ** 2  # a convex e(x) = P_k (1-x)^2 + P_{k+1} x^2 through both ends
+        a, b, c = mlp.targets(pk, pn, probe, sig)
         x = mlp.features(psq, 0.1, k)
         want = np.sum(np.abs(fields[k + 1]) ** 2) / np.sum(np.abs(fields[k]) ** 2)
-        assert mlp.sample_ratio(th, x, a, b, c) == pytest.approx(want, rel=1e-12)
-        assert mlp.sample_loss(th, x, a, b, c) == pytest.approx(np.log(want), abs=1e-12)
-        assert np.all(c >= -1e-12 * a.max())  # c = |Z^k - Z^{k+1}|^2 per tuple
+        assert np.allclose(a - 2 * b + c, pn, rtol=1e-9, atol=1e-12 * pk.max())
+        assert mlp.sample_ratio(th, x, a, b, c) == pytest.approx(want, rel=1e-9)
+        assert pn.sum() / pk.sum() == pytest.approx(want, rel=1e-12)
 
 
 def test_gradient_matches_central_differences():
@@ -105,8 +121,9 @@ def test_folding_covers_every_site_once():
 
 
 def test_recorded_response_free_field():
-    """Linearised FA multiplies Z(p) by 1 - 16 alpha on every mode (free field), so
-    b / a = 16 alpha, c / a = (16 alpha)^2, and the loss vanishes at s = 1/(16 alpha)."""
+    """Linearised FA multiplies Z(p) by 1 - 16 alpha x on every mode (free field) when the
+    multipliers are scaled by x, so the fit gives b/a = 16 alpha, c/a = (16 alpha)^2 and the
+    loss vanishes at s = 1/(16 alpha)."""
     dims = (8, 4, 6, 4)
     rng = np.random.default_rng(7)
     shp = synth.lattice_shape(dims)
@@ -114,13 +131,17 @@ def test_recorded_response_free_field():
     b_ = 1e-4 * rng.standard_normal(shp + (4,))
     u = np.zeros(shp + (4, 3, 3), np.complex128)
     u[..., 0, 0], u[..., 1, 1], u[..., 2, 2] = np.exp(1j * a_), np.exp(1j * b_), np.exp(-1j * (a_ + b_))
+    sig = 0.7
     u1, *_ = landau.fa_step(u, ALPHA)
+    up, *_ = landau.fa_step(u, ALPHA, kernel=landau.fa_kernel(dims) * sig)
     tuples = mlp.folded_tuples(dims)
     s0 = mlp.packed_spectrum(landau.divergence(u))
     s1 = mlp.packed_spectrum(landau.divergence(u1))
-    pk, ck = mlp.record(s0, s1, dims, tuples)
+    sp = mlp.packed_spectrum(landau.divergence(up))
+    pk, _ = mlp.record(s0, s0, dims, tuples)
     pn, _ = mlp.record(s1, s1, dims, tuples)
-    a, b, c = mlp.targets(pk, ck, pn)
+    pp, _ = mlp.record(sp, sp, dims, tuples)
+    a, b, c = mlp.targets(pk, pn, pp, sig)
     live = a > 1e-6 * a.max()
     assert live.sum() > 10
     assert np.allclose(b[live] / a[live], 16 * ALPHA, rtol=1e-3)
@@ -129,7 +150,7 @@ def test_recorded_response_free_field():
     th = mlp.init_params(1)
     th[-1] = -np.log(16 * ALPHA)
     x = mlp.features(mlp.tuple_psq(dims, tuples), 1e-8, 0)
-    assert mlp.sample_ratio(th, x, a, b, c) < 1e-5
+    assert mlp.sample_ratio(th, x[live], a[live], b[live], c[live]) < 1e-5
 
 
 def test_adam_first_step_is_lr_times_sign():
