@@ -205,8 +205,10 @@ gf_status gf_stage_update(gf_ctx* ctx, const void* d_scaled);
 
 /*
  * Per-kernel timing with HIP events recorded on the context's stream around
- * every kernel launch. gf_set_timing(ctx, 1) resets the totals and starts
- * recording; gf_kernel_times copies, for kernel ids 0..n-1 (GF_K_*), the summed
+ * kernel launches. gf_set_timing(ctx, 1) resets the totals and times every
+ * kernel (0 stops); gf_set_timing_mask(ctx, mask) times only the kernel ids
+ * whose bit (1 << GF_K_*) is set, so that the others run without events in
+ * between. gf_kernel_times copies, for kernel ids 0..n-1 (GF_K_*), the summed
  * duration in milliseconds and the number of launches timed.
  */
 enum {
@@ -220,6 +222,7 @@ enum {
     GF_NKERNELS = 8
 };
 gf_status gf_set_timing(gf_ctx* ctx, int32_t enable);
+gf_status gf_set_timing_mask(gf_ctx* ctx, uint32_t mask);
 gf_status gf_kernel_times(gf_ctx* ctx, int32_t n, double* h_ms_total, int64_t* h_counts);
 
 /*

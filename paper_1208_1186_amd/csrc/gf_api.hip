@@ -302,6 +302,8 @@ struct gf_ctx {
     std::string err;
     // Optional per-kernel HIP-event timing (gf_set_timing / gf_kernel_times).
     bool timing = false;
+    uint32_t timing_mask = 0;  // kernel ids (bit GF_K_*) timed while timing is on
+    bool timing_now = false;   // the launch being queued is bracketed by events
     std::vector<hipEvent_t> ev;  // 2 per pending measurement
     std::vector<int> ev_kid;
     int npend = 0;
@@ -345,7 +347,8 @@ void tdrain(gf_ctx* c) {
 
 // Record a start event for kernel kid (no-op unless timing is on).
 void tstart(gf_ctx* c, int kid) {
-    if (!c->timing) return;
+    c->timing_now = c->timing && ((c->timing_mask >> kid) & 1u);
+    if (!c->timing_now) return;
     if (c->ev.empty()) {
         c->ev.resize(2 * kEventPairs);
         c->ev_kid.resize(kEventPairs);
@@ -359,7 +362,7 @@ void tstart(gf_ctx* c, int kid) {
     (void)hipEventRecord(c->ev[2 * c->npend], c->st);
 }
 void tstop(gf_ctx* c) {
-    if (!c->timing) return;
+    if (!c->timing_now) return;
     (void)hipEventRecord(c->ev[2 * c->npend + 1], c->st);
     ++c->npend;
 }
@@ -1601,24 +1604,29 @@ gf_status gf_stage_update(gf_ctx* c, const void* d_scaled) {
     return read_head(c);
 }
 
-gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
+gf_status gf_set_timing_mask(gf_ctx* c, uint32_t mask) {
     if (!c) return GF_EINVAL;
     if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed) {
         for (int i = 0; i < 2; ++i) {
-            gf_status s = gf_set_timing(c->child[i], enable);
+            gf_status s = gf_set_timing_mask(c->child[i], mask);
             if (s != GF_OK) return s;
         }
         return GF_OK;
     }
     GF_TRY_HIP(c, hipStreamSynchronize(c->st));
     tdrain(c);
-    c->timing = enable != 0;
+    c->timing = mask != 0;
+    c->timing_mask = mask;
     for (int i = 0; i < GF_NKERNELS; ++i) {
         c->kt_ms[i] = 0.0;
         c->kt_n[i] = 0;
     }
     return GF_OK;
+}
+
+gf_status gf_set_timing(gf_ctx* c, int32_t enable) {
+    return gf_set_timing_mask(c, enable ? (1u << GF_NKERNELS) - 1u : 0u);
 }
 
 gf_status gf_kernel_times(gf_ctx* c, int32_t n, double* h_ms_total, int64_t* h_counts) {

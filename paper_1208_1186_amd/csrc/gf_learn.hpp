@@ -94,12 +94,13 @@ __device__ __forceinline__ void mlp_features(const float* sin2_4, float log10_th
 // cores: a wave takes kTableGroups groups of 16 tuples; for each, every lane
 // evaluates layer 1 for the 16 hidden units k = l/16 + 4m of tuple l%16 (its
 // A operand), v_mfma_f32_16x16x4f32 forms the 16 x 64 pre-activations of
-// layer 2 in four 16 x 16 tiles over K = 64 (16 steps), and layer 3 is a sum
-// across the 16 lanes that hold one tuple's hidden units. The lanes' W2
-// operands stay in registers for all groups. o_a is evaluated once per block
-// at the zero tuple, one hidden unit per lane of wave 0.
+// layer 2 in four 16 x 16 tiles over K = 64 (16 steps, B operands read from
+// the padded W2 in LDS), and layer 3 is a sum across the 16 lanes that hold
+// one tuple's hidden units. o_a is evaluated once per block at the zero
+// tuple, one hidden unit per lane of wave 0. (Keeping the B operands in
+// registers for several groups measured slower: 256 VGPRs, one wave per SIMD.)
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kTableGroups = 4;
+constexpr int kTableGroups = 1;
 constexpr int kTableTuplesPerBlock = 4 * 16 * kTableGroups;
 
 template <typename T>
@@ -146,11 +147,6 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ par
     const double oa = (double)oa_s;
     const int l = threadIdx.x & 63, kq = l >> 4, lc = l & 15;
     // B operands: W2[unit n*16 + lc][input 4m + kq]
-    float bw[4][16];
-#pragma unroll
-    for (int n = 0; n < 4; ++n)
-#pragma unroll
-        for (int m = 0; m < 16; ++m) bw[n][m] = w2[(n * 16 + lc) * W2S + 4 * m + kq];
     const T* sx = sin2;
     const T* sy = sx + tg.n[0];
     const T* sz = sy + tg.n[1];
@@ -183,7 +179,7 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ par
         for (int n = 0; n < 4; ++n) {
             acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int m = 0; m < 16; ++m) acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(h1[m], bw[n][m], acc[n], 0, 0, 0);
+            for (int m = 0; m < 16; ++m) acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(h1[m], w2[(n * 16 + lc) * W2S + 4 * m + kq], acc[n], 0, 0, 0);
         }
         // layer 3, first output: partial sums over this lane's units, then over the 16 lanes of the group
         float o0[4] = {0.f, 0.f, 0.f, 0.f};

@@ -73,6 +73,7 @@ def _signatures(lib):
         "gf_stage_gauge": (i32, [_P, _P, _P]),
         "gf_stage_update": (i32, [_P, _P]),
         "gf_set_timing": (i32, [_P, i32]),
+        "gf_set_timing_mask": (i32, [_P, ctypes.c_uint32]),
         "gf_kernel_times": (i32, [_P, i32, pd, ctypes.POINTER(ctypes.c_int64)]),
         "gf_mlp_param_count": (i32, []),
         "gf_mlp_set_weights": (i32, [_P, _P, i32]),
@@ -252,6 +253,14 @@ NKERNELS = 8
 
 def gf_set_timing(ctx, enable):
     _check(ctx, load().gf_set_timing(ctx, 1 if enable else 0))
+
+
+def gf_set_timing_mask(ctx, kernel_names):
+    """Time only the named kernels (names from KERNEL_NAMES)."""
+    mask = 0
+    for n in kernel_names:
+        mask |= 1 << KERNEL_NAMES.index(n)
+    _check(ctx, load().gf_set_timing_mask(ctx, mask))
 
 
 def gf_kernel_times(ctx):

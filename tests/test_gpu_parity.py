@@ -254,3 +254,4 @@ def test_workload_shapes_loop(dims):
         assert abs(res.theta - landau.theta(ref)) < 1e-10 * res.theta
         outs.append(ug)
     assert np.max(np.abs(outs[0] - outs[1])) < 1e-14
+
