@@ -95,11 +95,15 @@ def copy_ceiling(torch, dev, mib=1024, reps=10):
     return round(gbps, 1)
 
 
+TILINGS = {}  # precision -> (planes per (x, y) block, columns per (z, t) block) chosen by the library
+
+
 def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events, only=None):
     """Time `steps` FA iterations after `warmup`; with_events brackets the kernels named in `only`
     (all kernels if None) with HIP events on the context's stream."""
     links = u_dev.clone()
     fx = gf.GaugeFixer(links, precision, check_every=max(steps, warmup, 1))
+    TILINGS[precision] = gf.gf_fft_tiling(fx.ctx)
     if warmup:
         fx.iterate(warmup)
     torch.cuda.synchronize()
@@ -420,6 +424,8 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kern,
         "event_ms_per_step": round(events_ms, 5),
+        "fft_tiling_autotuned": {p: {"xy_planes_per_block": g, "zt_columns_per_block": b}
+                                 for p, (g, b) in TILINGS.items()},
         **extras,
     }
     print(json.dumps(out), flush=True)

@@ -148,6 +148,15 @@ gf_status gf_init_batch(gf_ctx** ctx, int32_t n, const gf_params* params, double
  */
 gf_status gf_fix_until_batch(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf_result* results);
 
+/*
+ * FFT tiling in use (for GF_MIXED: of the active phase): planes per block of
+ * the (x, y) passes and x columns per block of the (z, t) pass. gf_init picks
+ * them by timing the compile-time alternatives for the lattice shape and
+ * precision, once per process (GF_FLAG_GENERIC_FFT: the runtime-shaped
+ * kernels' defaults).
+ */
+gf_status gf_fft_tiling(gf_ctx* ctx, int32_t* xy_planes, int32_t* zt_columns);
+
 /* theta and F of the current links, in double precision. */
 gf_status gf_quality(gf_ctx* ctx, double* theta, double* F);
 

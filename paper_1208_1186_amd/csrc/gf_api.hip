@@ -18,6 +18,8 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/gf.h"
@@ -101,6 +103,23 @@ struct Layout {
     size_t child_off[2];
 };
 
+// Launch shape of the (x, y) passes for G planes per block, and of the (z, t)
+// pass for bx columns per block.
+void set_xy_tile(Layout& L, int G) {
+    const size_t csz = L.fp32 ? 8 : 16;
+    L.G = G;
+    L.rs = L.n[0] + 1;
+    L.thrA = std::min(1024, std::max(64, round64((G * L.n[0] * L.n[1] + kEPT - 1) / kEPT)));
+    L.ldsA = (size_t)(L.n[0] + L.n[1]) * csz + (size_t)G * L.n[1] * L.rs * csz;
+}
+void set_zt_tile(Layout& L, int bx) {
+    const size_t csz = L.fp32 ? 8 : 16;
+    L.bx = bx;
+    L.tsp = L.n[2] * bx + 1;
+    L.thrB = std::min(1024, std::max(64, round64((bx * L.n[2] * L.n[3] + kEPT - 1) / kEPT)));
+    L.ldsB = (size_t)(L.n[2] + L.n[3]) * csz + (size_t)L.n[3] * L.tsp * csz;
+}
+
 gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     if (!p) {
         err = "params is NULL";
@@ -152,14 +171,11 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2], nt = L.n[3];
     // (x, y) pass: G planes per block, enough work per block, never straddling a field.
     const int nzt = nz * nt;
-    // (measured at 32x32: two planes per block beat one and four)
+    // (the default; gf_init times the compile-time alternatives of the shape and keeps the fastest)
     const int want = nx * ny >= 1024 ? 2048 : 512;
-    L.G = 1;
-    while (L.G * 2 <= nzt && nzt % (L.G * 2) == 0 && L.G * nx * ny < want) L.G *= 2;
-    L.rs = nx + 1;
-    const int EA = L.G * nx * ny;
-    L.thrA = std::min(1024, std::max(64, round64((EA + kEPT - 1) / kEPT)));
-    L.ldsA = (size_t)(nx + ny) * csz + (size_t)L.G * ny * L.rs * csz;
+    int G = 1;
+    while (G * 2 <= nzt && nzt % (G * 2) == 0 && G * nx * ny < want) G *= 2;
+    set_xy_tile(L, G);
     // (z, t) pass: bx consecutive x columns, up to 128 contiguous bytes per row.
     L.bx = 0;
     for (int b : {16, 8, 4, 2, 1}) {
@@ -175,10 +191,7 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
         err = "z-t plane too large for one block";
         return GF_ENOTSUP;
     }
-    L.tsp = nz * L.bx + 1;
-    const int EB = L.bx * nz * nt;
-    L.thrB = std::min(1024, std::max(64, round64((EB + kEPT - 1) / kEPT)));
-    L.ldsB = (size_t)(nz + nt) * csz + (size_t)nt * L.tsp * csz;
+    set_zt_tile(L, L.bx);
     // inverse (x, y) + gauge pass: the four fields of one (z, t) plane per block.
     const int EC = 4 * nx * ny;
     L.eptC = EC <= kEPT * 1024 ? kEPT : 16;
@@ -388,11 +401,17 @@ const cx<T>* twp(gf_ctx* c, int d) {
 
 // Shapes with compile-time FFT kernels: (Nx, Ny, G) for the (x, y) passes,
 // (Nz, Nt, bx) for the (z, t) pass at each precision, (Nx, Ny) for the gauge pass.
-#define GF_XY_CASES(X) X(8, 8, 8) X(12, 12, 4) X(16, 16, 2) X(24, 24, 1) X(32, 32, 2) X(48, 48, 1)
-#define GF_ZT_CASES_F64(X) \
-    X(8, 8, 8) X(12, 12, 4) X(16, 16, 8) X(24, 8, 8) X(32, 4, 8) X(48, 8, 8) X(32, 32, 4) X(32, 64, 2)
-#define GF_ZT_CASES_F32(X) \
-    X(8, 8, 8) X(12, 12, 4) X(16, 16, 16) X(24, 8, 8) X(32, 4, 16) X(48, 8, 16) X(32, 32, 8) X(32, 64, 4)
+// Several entries per shape are the alternatives the autotuner times.
+#define GF_XY_CASES(X)                                                                                         \
+    X(8, 8, 8) X(8, 8, 16) X(8, 8, 32) X(12, 12, 4) X(12, 12, 8) X(12, 12, 16) X(16, 16, 2) X(16, 16, 4)       \
+    X(16, 16, 8) X(24, 24, 1) X(24, 24, 2) X(24, 24, 4) X(32, 32, 1) X(32, 32, 2) X(32, 32, 4) X(48, 48, 1)    \
+    X(48, 48, 2)
+#define GF_ZT_CASES_F64(X)                                                                                     \
+    X(8, 8, 4) X(8, 8, 8) X(12, 12, 4) X(16, 16, 4) X(16, 16, 8) X(16, 16, 16) X(24, 8, 8) X(32, 4, 8)         \
+    X(32, 4, 16) X(48, 8, 8) X(48, 8, 16) X(32, 32, 2) X(32, 32, 4) X(32, 64, 2)
+#define GF_ZT_CASES_F32(X)                                                                                     \
+    X(8, 8, 8) X(12, 12, 4) X(16, 16, 8) X(16, 16, 16) X(24, 8, 8) X(32, 4, 16) X(32, 4, 32) X(48, 8, 8)       \
+    X(48, 8, 16) X(32, 32, 4) X(32, 32, 8) X(32, 64, 4)
 #define GF_GAUGE_CASES(X) X(8, 8) X(12, 12) X(16, 16) X(24, 24) X(32, 32) X(48, 48)
 
 bool generic_fft(const gf_ctx* c) { return (c->p.flags & GF_FLAG_GENERIC_FFT) != 0; }
@@ -702,6 +721,120 @@ void stage_spectral(gf_ctx* c, bool gauge) {
         launch_xy<T, true>(c, c->Q, c->Q, 1, false);
 }
 
+// ------------------------------------------------------------- autotuning
+// The compile-time FFT kernels come in several tilings per plane shape ((x, y):
+// planes per block; (z, t): x columns per block). On the first context of a
+// shape and precision in a process, each alternative is timed on the
+// context's own buffers (two launches to warm up, then ten) and the fastest
+// is kept for every later context of that shape and precision. The tilings
+// compute bitwise the same transform.
+struct TuneKey {
+    int n[4];
+    bool fp32;
+    bool operator<(const TuneKey& o) const {
+        for (int i = 0; i < 4; ++i)
+            if (n[i] != o.n[i]) return n[i] < o.n[i];
+        return fp32 < o.fp32;
+    }
+};
+std::map<TuneKey, std::pair<int, int>> g_tuned;  // (G, bx)
+std::mutex g_tuned_mu;
+
+std::vector<int> xy_candidates(const Layout& L) {
+    std::vector<int> v;
+    const int nzt = L.n[2] * L.n[3];
+#define GF_X(A, B, GG) \
+    if (L.n[0] == A && L.n[1] == B && GG <= nzt && nzt % GG == 0) v.push_back(GG);
+    GF_XY_CASES(GF_X)
+#undef GF_X
+    return v;
+}
+
+std::vector<int> zt_candidates(const Layout& L) {
+    std::vector<int> v;
+#define GF_X(A, B, BB) \
+    if (L.n[2] == A && L.n[3] == B && L.n[0] % BB == 0) v.push_back(BB);
+    if (L.fp32) {
+        GF_ZT_CASES_F32(GF_X)
+    } else {
+        GF_ZT_CASES_F64(GF_X)
+    }
+#undef GF_X
+    return v;
+}
+
+constexpr int kTuneReps = 10;
+
+template <typename T>
+double time_pass(gf_ctx* c, bool xy) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return 1e30;
+    auto run = [&]() {
+        if (xy)
+            launch_xy<T, false>(c, c->D, c->Q, 1, false);
+        else
+            launch_zt<T>(c, c->Q, 1);
+    };
+    run();
+    run();
+    (void)hipEventRecord(a, c->st);
+    for (int i = 0; i < kTuneReps; ++i) run();
+    (void)hipEventRecord(b, c->st);
+    float ms = 1e30f;
+    if (hipGetLastError() != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+        ms = 1e30f;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+
+gf_status autotune(gf_ctx* c) {
+    if (generic_fft(c) || c->cs != 0) return GF_OK;
+    TuneKey key{};
+    for (int i = 0; i < 4; ++i) key.n[i] = c->L.n[i];
+    key.fp32 = c->L.fp32;
+    {
+        std::lock_guard<std::mutex> lock(g_tuned_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            set_xy_tile(c->L, it->second.first);
+            set_zt_tile(c->L, it->second.second);
+            return GF_OK;
+        }
+    }
+    int bestG = c->L.G, bestB = c->L.bx;
+    const std::vector<int> xs = xy_candidates(c->L), zs = zt_candidates(c->L);
+    if (xs.size() > 1) {
+        double best = 1e30;
+        for (int G : xs) {
+            set_xy_tile(c->L, G);
+            const double t = c->L.fp32 ? time_pass<float>(c, true) : time_pass<double>(c, true);
+            if (t < best) {
+                best = t;
+                bestG = G;
+            }
+        }
+    }
+    set_xy_tile(c->L, bestG);
+    if (zs.size() > 1) {
+        double best = 1e30;
+        for (int B : zs) {
+            set_zt_tile(c->L, B);
+            const double t = c->L.fp32 ? time_pass<float>(c, false) : time_pass<double>(c, false);
+            if (t < best) {
+                best = t;
+                bestB = B;
+            }
+        }
+    }
+    set_zt_tile(c->L, bestB);
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lock(g_tuned_mu);
+    g_tuned[key] = {bestG, bestB};
+    return check_hip(c, hipStreamSynchronize(c->st), "autotune sync");
+}
+
 constexpr int kMaxRejects = 3;  // consecutive rejected learned steps before the network is switched off
 
 gf_status set_guard(gf_ctx* c, int on) {
@@ -852,6 +985,7 @@ gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_l
         s = launched(c, "identity launch");
     }
     if (s == GF_OK && measure) s = launch_measure(c);
+    if (s == GF_OK) s = autotune(c);
     if (s == GF_OK) s = read_head(c);
     if (s == GF_OK) {
         // hipMemcpyAsync from pageable memory may return before the copy is done: keep `host` alive until here.
@@ -1111,6 +1245,8 @@ gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned 
             if (!d) return fail(c, GF_EINVAL, "out of host memory");
             g.drv[ph] = d;
             carve(d, g.q[ph], g.L[ph], nullptr, ws + g.off[ph], st);
+            set_xy_tile(d->L, g.view[ph][0]->L.G);  // the tiling tuned for this shape and precision
+            set_zt_tile(d->L, g.view[ph][0]->L.bx);
             d->cs = g.cs[ph];
             d->act_dev = g.d_act;
         }
@@ -1471,6 +1607,15 @@ gf_status gf_get_links(gf_ctx* c, void* d_out) {
     gf_status s = unpack_links(c, reinterpret_cast<double*>(d_out));
     if (s != GF_OK) return s;
     return check_hip(c, hipStreamSynchronize(c->st), "sync");
+}
+
+gf_status gf_fft_tiling(gf_ctx* c, int32_t* xy_planes, int32_t* zt_columns) {
+    if (!c || !xy_planes || !zt_columns) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    const gf_ctx* a = active(c);
+    *xy_planes = a->L.G;
+    *zt_columns = a->L.bx;
+    return GF_OK;
 }
 
 size_t gf_state_bytes(const gf_ctx* c) {

@@ -64,6 +64,7 @@ def _signatures(lib):
         "gf_state_bytes": (sz, [_P]),
         "gf_get_state": (i32, [_P, _P, sz]),
         "gf_set_state": (i32, [_P, _P, sz]),
+        "gf_fft_tiling": (i32, [_P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "gf_quality": (i32, [_P, pd, pd]),
         "gf_get_links": (i32, [_P, _P]),
         "gf_get_gauge": (i32, [_P, _P]),
@@ -206,6 +207,12 @@ def gf_get_state(ctx, d_out, nbytes):
 
 def gf_set_state(ctx, d_in, nbytes):
     _check(ctx, load().gf_set_state(ctx, _P(d_in), nbytes))
+
+
+def gf_fft_tiling(ctx):
+    g, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, load().gf_fft_tiling(ctx, ctypes.byref(g), ctypes.byref(b)))
+    return g.value, b.value
 
 
 def gf_quality(ctx):
