@@ -226,23 +226,13 @@ def batch_workload(gf, torch, synth, dev, n=64, tol=1e-15):
     return out
 
 
-def learned_workload(gf, torch, synth, n_train=64, n_iter=120, epochs=60):
+def learned_workload(gf, torch, synth):
     """Train the spectral-preconditioner network on 16^4 plain-FA trajectories (on the GPU, with the
     library's kernels), then compare iterations and wall time to theta < 1e-15 against plain FA."""
     from paper_1208_1186_amd import learn
-    import numpy as np
-    log(f"learned preconditioner: recording {n_train} 16^4 trajectories")
-    t0 = time.perf_counter()
-    dims_tr = (16, 16, 16, 16)
-    X, TG, ns = learn.collect(dims_tr, range(100, 100 + n_train), n_iter)
-    t_rec = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    params, hist = learn.train(X, TG, learn.n_tuples(dims_tr), ns, epochs=epochs, batch=32, lr=1e-3)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    out = {"train": {"lattice": list(dims_tr), "trajectories": n_train, "samples": int(ns),
-                     "record_s": round(t_rec, 2), "train_s": round(t_train, 2), "epochs": epochs,
-                     "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}, "eval": []}
+    log("learned preconditioner: recording 64 16^4 trajectories and training")
+    params, info = learn.train_default()
+    out = {"train": info, "eval": []}
     tot = {"plain_iters": 0, "learned_iters": 0, "plain_s": 0.0, "learned_s": 0.0}
     for dims, seeds, eps in [((32, 32, 32, 32), range(10000, 10004), synth.EPS_P059),
                              ((48, 48, 48, 8), range(20000, 20004), synth.EPS_P060)]:

@@ -103,6 +103,23 @@ def train(X, TG, T, n_samples, epochs=20, batch=16, lr=2e-3, seed=0, params=None
     return p, hist
 
 
+def train_default(dims=(16, 16, 16, 16), n_train=64, n_iter=120, epochs=60, batch=32, lr=1e-3, seed=0,
+                  first_seed=100, log=None):
+    """The training recipe used for the learned workload: record n_train plain-FA trajectories of
+    seeded dims lattices (seeds first_seed..), then Adam over whole samples. Returns (params, info)."""
+    t0 = time.perf_counter()
+    X, TG, ns = collect(dims, range(first_seed, first_seed + n_train), n_iter, log=log)
+    t_rec = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    params, hist = train(X, TG, n_tuples(dims), ns, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
+    import torch
+    torch.cuda.synchronize()
+    info = {"lattice": list(dims), "trajectories": n_train, "samples": int(ns), "record_s": round(t_rec, 2),
+            "train_s": round(time.perf_counter() - t0, 2), "epochs": epochs,
+            "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}
+    return params, info
+
+
 def solve(u, precision="fp64_18", params=None, tol=1e-15, max_iter=20000, device="cuda:0", check_every=10):
     """Fix the gauge of u with or without the network; returns (result, wall seconds, final links)."""
     import torch

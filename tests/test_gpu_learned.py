@@ -204,3 +204,22 @@ def test_fallback_rescues_corrupted_weights():
     assert res.status == gf.GF_OK and res.theta < 1e-15
     assert res.fallbacks >= 1
     assert landau.theta(links.cpu().numpy()) < 1e-15
+
+
+def test_trained_network_gains_over_plain_fa():
+    """Train the network on the GPU (library kernels) on recorded 16^4 trajectories, then solve held-out
+    16^4 configurations with and without it: fewer iterations in total, theta < 1e-15 by the oracle."""
+    dims = (16, 16, 16, 16)
+    params, info = learn.train_default(dims)  # 64 trajectories, the learned workload's recipe
+    assert info["loss_first_last"][1] < info["loss_first_last"][0]
+    plain, learned = 0, 0
+    for seed in (800, 801, 802):
+        u = synth.make_config(dims, seed)
+        r0, _, _ = learn.solve(u)
+        r1, _, links = learn.solve(u, params=params)
+        assert r0.status == gf.GF_OK and r1.status == gf.GF_OK
+        assert landau.theta(links.cpu().numpy()) < 1e-15
+        plain += r0.iters
+        learned += r1.iters
+    print(f"plain {plain} learned {learned} iterations", flush=True)
+    assert learned < plain

@@ -92,3 +92,22 @@ def test_gauge_not_kept_without_flag():
     with pytest.raises(gf.GfError) as e:
         fx.get_gauge()
     assert e.value.status == gf.GF_ESTATE
+
+
+def test_mixed_48x48x48x8_full_size():
+    """The mixed-precision workload at its full size (48^3 x 8, plaquette ~0.60), in the launch
+    configuration bench.py times: invariants checked by the oracle against the input and against the
+    plain FP64-18 solve on the GPU."""
+    print("mixed 48x48x48x8 full size", flush=True)
+    dims = (48, 48, 48, 8)
+    u = synth.make_config(dims, 0, synth.EPS_P060)
+    lm = to_dev(u)
+    rm = gf.GaugeFixer(lm, "mixed", check_every=10, switch_theta=1e-8).fix_until(1e-15, 100000)
+    l64 = to_dev(u)
+    r64 = gf.GaugeFixer(l64, "fp64_18", check_every=10).fix_until(1e-15, 100000)
+    assert rm.status == gf.GF_OK and r64.status == gf.GF_OK and rm.phase == 1
+    out = lm.cpu().numpy()
+    assert landau.theta(out) < 1e-15
+    assert abs(observables.plaquette(out) - observables.plaquette(u)) < 1e-12
+    assert abs(rm.F - r64.F) < 1e-12  # same local maximum as the double-precision solve
+    assert abs(landau.functional(out) - rm.F) < 1e-13
