@@ -243,9 +243,11 @@ gf_status gf_kernel_times(gf_ctx* ctx, int32_t n, double* h_ms_total, int64_t* h
  *   x = (p^2_mu/4 - 1/2 for mu = 0..3, log10(theta_k)/8 + 1, k/64),
  * o_a being read at the zero tuple. Parameters, gf_mlp_param_count() floats:
  * W1 (64x6, row-major), b1 (64), W2 (64x64), b2 (64), W3 (2x64), b3 (2).
- * A learned step that increases theta or lowers F (beyond 1e-14) is undone
- * and replaced by a plain Fourier-accelerated step; after 3 consecutive
- * rejections the network is switched off (gf_result.fallbacks counts them).
+ * A learned step that increases theta, lowers F (beyond 1e-14) or gives a
+ * theta that is not finite is stopped on the device, undone and replaced by a
+ * plain Fourier-accelerated step; after its r-th such rejection the network
+ * pauses for 2^r plain steps, and after 6 it stays off (gf_result.fallbacks
+ * counts the rejections).
  */
 int32_t gf_mlp_param_count(void);
 

@@ -292,7 +292,8 @@ struct gf_ctx {
     void* mtab;          // multiplier per tuple for the current iteration
     bool net_on = false;       // gf_mlp_set_weights called and not disabled
     bool net_this = false;     // the iteration being queued uses the table
-    int rejects = 0;           // consecutive rejected learned steps
+    int rejects = 0;           // rejected learned steps since gf_mlp_set_weights
+    long long net_pause = 0;   // plain updates still to take before the network is tried again
     int fallbacks = 0;         // rejected learned steps in total
     // spectrum recording
     void* spec[4];  // spectra of the plain iterates (0, 1) and of the probe steps (2, 3)
@@ -835,7 +836,9 @@ gf_status autotune(gf_ctx* c) {
     return check_hip(c, hipStreamSynchronize(c->st), "autotune sync");
 }
 
-constexpr int kMaxRejects = 3;  // consecutive rejected learned steps before the network is switched off
+// After its r-th rejected step the network pauses for 2^r plain updates; after
+// kMaxRejects rejections it stays off.
+constexpr int kMaxRejects = 6;
 
 gf_status set_guard(gf_ctx* c, int on) {
     hipLaunchKernelGGL(k_set_guard, dim3(1), dim3(64), 0, c->st, c->ctl, on);
@@ -855,12 +858,10 @@ gf_status learned_chunk(gf_ctx* c, int64_t n) {
     if (s == GF_OK) s = loop_finalize(c);
     if (s == GF_OK) s = read_head(c);
     if (s != GF_OK) return s;
-    if (!c->h_head->rejected) {
-        c->rejects = 0;
-        return GF_OK;
-    }
+    if (!c->h_head->rejected) return GF_OK;
     ++c->fallbacks;
     if (++c->rejects >= kMaxRejects) c->net_on = false;
+    c->net_pause = 1ll << c->rejects;
     const long long k0 = c->h_head->iters - 1;
     hipLaunchKernelGGL(k_rollback, dim3(1), dim3(64), 0, c->st, c->ctl, k0);
     c->k_host = k0;
@@ -882,11 +883,15 @@ gf_status run_loop(gf_ctx* c, double tol, int64_t max_iter, gf_result* r, bool u
     const long long start = c->h_head->iters;
     while (!c->h_head->done && c->h_head->iters - start < max_iter) {
         const int64_t left = max_iter - (c->h_head->iters - start);
-        const int64_t k = std::min<int64_t>(left, c->p.check_every);
-        if (c->net_on) {
+        int64_t k = std::min<int64_t>(left, c->p.check_every);
+        if (c->net_on && c->net_pause == 0) {
             s = learned_chunk(c, k);
             if (s != GF_OK) return s;
             continue;
+        }
+        if (c->net_on) {  // paused after a rejection: plain updates, counted down
+            k = std::min<int64_t>(k, c->net_pause);
+            c->net_pause -= k;
         }
         for (int64_t i = 0; i < k && s == GF_OK; ++i) s = one_iteration(c, c->k_host + i);
         if (s == GF_OK) s = loop_finalize(c);
@@ -1095,6 +1100,7 @@ struct StateHeader {
     uint32_t flags;
     int64_t k_host[3];  // this context, float child, double child
     int32_t phase, net_on, rejects, fallbacks;
+    int64_t net_pause;
 };
 static_assert(sizeof(StateHeader) <= kStateHead, "state header too large");
 
@@ -1110,6 +1116,7 @@ StateHeader state_header(const gf_ctx* c) {
     h.phase = c->phase;
     h.net_on = c->net_on ? 1 : 0;
     h.rejects = c->rejects;
+    h.net_pause = c->net_pause;
     h.fallbacks = c->fallbacks;
     return h;
 }
@@ -1121,6 +1128,7 @@ void restore_header(gf_ctx* c, const StateHeader& h) {
     c->phase = h.phase;
     c->net_on = h.net_on != 0;
     c->rejects = h.rejects;
+    c->net_pause = h.net_pause;
     c->fallbacks = h.fallbacks;
 }
 
@@ -1834,6 +1842,7 @@ gf_status gf_mlp_set_weights(gf_ctx* c, const float* d_params, int32_t enable) {
     GF_TRY_HIP(c, hipStreamSynchronize(c->st));
     c->net_on = enable != 0;
     c->rejects = 0;
+    c->net_pause = 0;
     return GF_OK;
 }
 

@@ -100,6 +100,13 @@ __device__ __forceinline__ void mlp_features(const float* sin2_4, float log10_th
 // tuple, one hidden unit per lane of wave 0. (Keeping the B operands in
 // registers for several groups measured slower: 256 VGPRs, one wave per SIMD.)
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// tanh(x) = 1 - 2 / (exp(2x) + 1) with the hardware exponential and
+// reciprocal: absolute error about 1e-7, saturating correctly at both ends
+// (inference only; the training kernels use tanhf).
+__device__ __forceinline__ float tanh_fast(float x) {
+    return 1.0f - 2.0f * __frcp_rn(__expf(2.0f * x) + 1.0f);
+}
 constexpr int kTableGroups = 1;
 constexpr int kTableTuplesPerBlock = 4 * 16 * kTableGroups;
 
@@ -110,14 +117,41 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ par
     if (!force && ctl->done) return;
     constexpr int W2S = kMlpH + 1;  // padded row stride of W2 in LDS
     __shared__ float w1[kMlpH * kMlpIn], b1[kMlpH], w2[kMlpH * W2S], b2[kMlpH], w3[2 * kMlpH], h1z[kMlpH];
+    __shared__ float c1[kMlpH];  // b1 + the theta and k terms of layer 1, shared by every tuple
     __shared__ float oa_s;
-    for (int i = threadIdx.x; i < kMlpH * kMlpIn; i += 256) w1[i] = params[kOffW1 + i];
-    for (int i = threadIdx.x; i < kMlpH * kMlpH; i += 256) w2[(i / kMlpH) * W2S + i % kMlpH] = params[kOffW2 + i];
-    for (int i = threadIdx.x; i < kMlpH; i += 256) {
-        b1[i] = params[kOffB1 + i];
-        b2[i] = params[kOffB2 + i];
-        w3[i] = params[kOffW3 + i];
-        w3[kMlpH + i] = params[kOffW3 + kMlpH + i];
+    {
+        // every load first, then the LDS stores: one memory round trip for the whole network
+        constexpr int N2 = kMlpH * kMlpH / 256, N1 = (kMlpH * kMlpIn + 255) / 256;
+        float r2[N2], r1[N1], rb1 = 0.f, rb2 = 0.f, rw30 = 0.f, rw31 = 0.f;
+#pragma unroll
+        for (int q = 0; q < N2; ++q) r2[q] = params[kOffW2 + q * 256 + threadIdx.x];
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+            const int i = q * 256 + threadIdx.x;
+            r1[q] = i < kMlpH * kMlpIn ? params[kOffW1 + i] : 0.f;
+        }
+        if (threadIdx.x < kMlpH) {
+            rb1 = params[kOffB1 + threadIdx.x];
+            rb2 = params[kOffB2 + threadIdx.x];
+            rw30 = params[kOffW3 + threadIdx.x];
+            rw31 = params[kOffW3 + kMlpH + threadIdx.x];
+        }
+#pragma unroll
+        for (int q = 0; q < N2; ++q) {
+            const int i = q * 256 + threadIdx.x;
+            w2[(i / kMlpH) * W2S + i % kMlpH] = r2[q];
+        }
+#pragma unroll
+        for (int q = 0; q < N1; ++q) {
+            const int i = q * 256 + threadIdx.x;
+            if (i < kMlpH * kMlpIn) w1[i] = r1[q];
+        }
+        if (threadIdx.x < kMlpH) {
+            b1[threadIdx.x] = rb1;
+            b2[threadIdx.x] = rb2;
+            w3[threadIdx.x] = rw30;
+            w3[kMlpH + threadIdx.x] = rw31;
+        }
     }
     __syncthreads();
     const float lt = (float)log10(fmax(ctl->theta, 1e-300));
@@ -128,17 +162,25 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ par
         float zx[kMlpIn];
         const float zs[4] = {0.f, 0.f, 0.f, 0.f};
         mlp_features(zs, lt, kk, zx);
-        float a = b1[j];
+        const float cj = fmaf(w1[j * kMlpIn + 5], zx[5], fmaf(w1[j * kMlpIn + 4], zx[4], b1[j]));
+        c1[j] = cj;
+        float a = cj;
 #pragma unroll
-        for (int i = 0; i < kMlpIn; ++i) a = fmaf(w1[j * kMlpIn + i], zx[i], a);
-        h1z[j] = tanhf(a);
+        for (int i = 0; i < 4; ++i) a = fmaf(w1[j * kMlpIn + i], zx[i], a);
+        h1z[j] = tanh_fast(a);
     }
     __syncthreads();
     if (threadIdx.x < kMlpH) {  // layers 2 and 3 of the zero tuple, second output
         const int j = threadIdx.x;
-        float a = b2[j];
-        for (int i = 0; i < kMlpH; ++i) a = fmaf(w2[j * W2S + i], h1z[i], a);
-        float p = w3[kMlpH + j] * tanhf(a);
+        float a0 = b2[j], a1 = 0.f, a2 = 0.f, a3 = 0.f;
+#pragma unroll
+        for (int i = 0; i < kMlpH; i += 4) {
+            a0 = fmaf(w2[j * W2S + i], h1z[i], a0);
+            a1 = fmaf(w2[j * W2S + i + 1], h1z[i + 1], a1);
+            a2 = fmaf(w2[j * W2S + i + 2], h1z[i + 2], a2);
+            a3 = fmaf(w2[j * W2S + i + 3], h1z[i + 3], a3);
+        }
+        float p = w3[kMlpH + j] * tanh_fast((a0 + a1) + (a2 + a3));
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) p += __shfl_xor(p, o, 64);
         if (j == 0) oa_s = p + b31;
@@ -168,10 +210,10 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ par
 #pragma unroll
         for (int m = 0; m < 16; ++m) {
             const int j = kq + 4 * m;
-            float a = b1[j];
+            float a = c1[j];
 #pragma unroll
-            for (int i = 0; i < kMlpIn; ++i) a = fmaf(w1[j * kMlpIn + i], x[i], a);
-            h1[m] = tanhf(a);
+            for (int i = 0; i < 4; ++i) a = fmaf(w1[j * kMlpIn + i], x[i], a);
+            h1[m] = tanh_fast(a);
         }
         // layer 2: acc[n] holds rows 4*kq + q (tuples t0 + 4*kq + q), unit n*16 + lc
         f32x4 acc[4];
@@ -187,7 +229,7 @@ __global__ void __launch_bounds__(256) k_mlp_table(const float* __restrict__ par
         for (int n = 0; n < 4; ++n) {
             const int j = n * 16 + lc;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) o0[q] = fmaf(w3[j], tanhf(acc[n][q] + b2[j]), o0[q]);
+            for (int q = 0; q < 4; ++q) o0[q] = fmaf(w3[j], tanh_fast(acc[n][q] + b2[j]), o0[q]);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q)
