@@ -369,6 +369,16 @@ def main():
             extras[f"{p2}_it_per_s"] = round(args.steps / d2, 1)
             extras[f"{p2}_model_GBps"] = round((8 * L2 + 64) * S2 * vol * args.steps / d2 / 1e9, 1)
             log(f"{p2}: {args.steps / d2:.1f} it/s")
+        # FP32-12 on 32^3 x 64: 403 MB of links, beyond the 256 MB last-level cache that the 32^4 FP32-12
+        # working set (201 MB of links) fits in
+        dims_c = (32, 32, 32, 64)
+        u_c = torch.from_numpy(synth.make_config(dims_c, 0, synth.EPS_P059)).to(dev)
+        d3, _, _, _ = timed_rate(gf, torch, u_c, "fp32_12", args.steps, args.warmup, with_events=False)
+        vol_c = 32 * 32 * 32 * 64
+        extras["fp32_12_32x32x32x64_it_per_s"] = round(args.steps / d3, 1)
+        extras["fp32_12_32x32x32x64_model_GBps"] = round((8 * 12 + 64) * 4 * vol_c * args.steps / d3 / 1e9, 1)
+        log(f"fp32_12 32x32x32x64: {args.steps / d3:.1f} it/s")
+        del u_c
         for p2 in ["fp64_18", "fp64_12"]:
             tt, rr = time_to_theta(gf, torch, u_dev, p2)
             extras[f"{p2}_time_to_theta_1e-15_s"] = round(tt, 4)
