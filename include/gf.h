@@ -157,6 +157,14 @@ gf_status gf_fix_until_batch(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf
  */
 gf_status gf_fft_tiling(gf_ctx* ctx, int32_t* xy_planes, int32_t* zt_columns);
 
+/*
+ * Mean plaquette of the current links, (1/(18V)) sum_x sum_{mu<nu} Re Tr[
+ * U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag], summed in double precision
+ * in a fixed order. Gauge invariant: gauge fixing must leave it unchanged
+ * (the check of a result without the input's gauge).
+ */
+gf_status gf_plaquette(gf_ctx* ctx, double* plaquette);
+
 /* theta and F of the current links, in double precision. */
 gf_status gf_quality(gf_ctx* ctx, double* theta, double* F);
 

@@ -1084,6 +1084,14 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
 }
 
 
+template <typename T, int NE>
+void launch_plaquette_t(gf_ctx* c) {
+    hipLaunchKernelGGL((k_plaquette<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
+                       links_of<T, NE>(c, cur(c)), c->geom, c->part);
+    hipLaunchKernelGGL(k_plaquette_sum, dim3(1), dim3(256), 0, c->st, c->part, c->L.nblk,
+                       1.0 / (18.0 * (double)c->L.vol), c->ctl);
+}
+
 // ------------------------------------------------------------- checkpoints
 // A saved state is this header followed by a copy of the whole workspace
 // (control block, history, tables, fields, both link buffers, accumulated
@@ -1615,6 +1623,20 @@ gf_status gf_get_links(gf_ctx* c, void* d_out) {
     gf_status s = unpack_links(c, reinterpret_cast<double*>(d_out));
     if (s != GF_OK) return s;
     return check_hip(c, hipStreamSynchronize(c->st), "sync");
+}
+
+gf_status gf_plaquette(gf_ctx* c, double* plaquette) {
+    if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    if (!plaquette) return fail(c, GF_EINVAL, "plaquette is NULL");
+    gf_ctx* a = active(c);
+    GF_DISPATCH(a, launch_plaquette_t, a);
+    gf_status s = launched(a, "plaquette launch");
+    if (s == GF_OK)
+        s = check_hip(a, hipMemcpyAsync(plaquette, &a->ctl->plaquette, sizeof(double), hipMemcpyDeviceToHost, a->st),
+                      "plaquette readback");
+    if (s == GF_OK) s = check_hip(a, hipStreamSynchronize(a->st), "sync");
+    return s == GF_OK ? GF_OK : fail(c, s, a->err);
 }
 
 gf_status gf_fft_tiling(gf_ctx* c, int32_t* xy_planes, int32_t* zt_columns) {

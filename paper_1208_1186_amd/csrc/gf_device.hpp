@@ -284,6 +284,7 @@ struct Ctl {
     int guard;        // stop (rejected = 1) when an update raises theta, lowers F or is not finite
     int rejected;     // the last update was stopped by the guard
     int reserved;
+    double plaquette; // mean plaquette of the links, when gf_plaquette last measured it
     double hist_theta[kHist];
     double hist_F[kHist];
 };

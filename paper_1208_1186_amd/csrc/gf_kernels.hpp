@@ -215,6 +215,50 @@ __global__ void __launch_bounds__(256) k_finalize(const double2* __restrict__ pa
     reduce_partials(part, n, inv3v, inv12v, ctl, mode);
 }
 
+// Plaquette (gauge invariant, for checks): per site the six (mu < nu) loops
+// Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] = Re sum_ij A_ij conj(B_ij)
+// with A = U_mu(x) U_nu(x+mu), B = U_nu(x) U_mu(x+nu); one FP64 partial per block.
+template <typename T, int NE>
+__global__ void __launch_bounds__(kSiteThreads) k_plaquette(Links<T, NE> L, Geom g, double2* __restrict__ part) {
+    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
+    double sum = 0.0, none = 0.0;
+    if (s < g.vol) {
+        int c[4];
+        site_coords(g, s, c);
+#pragma unroll 1
+        for (int mu = 0; mu < 4; ++mu) {
+            const su3<T> um = L.load(mu, s);
+#pragma unroll 1
+            for (int nu = mu + 1; nu < 4; ++nu) {
+                const su3<T> a = mul(um, L.load(nu, site_fwd(g, s, c, mu)));
+                const su3<T> b = mul(L.load(nu, s), L.load(mu, site_fwd(g, s, c, nu)));
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const cx<T> x = a.e[k / 3][k % 3], y = b.e[k / 3][k % 3];
+                    sum += (double)x.re * y.re + (double)x.im * y.im;
+                }
+            }
+        }
+    }
+    block_sum2<kSiteThreads>(sum, none);
+    if (threadIdx.x == 0) part[blockIdx.x] = make_double2(sum, 0.0);
+}
+
+// Fixed-order sum of n block partials (.x) times scale into ctl->plaquette (one block of 256).
+__global__ void __launch_bounds__(256) k_plaquette_sum(const double2* __restrict__ part, int n, double scale,
+                                                       Ctl* ctl) {
+    __shared__ double r[256];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) a += part[i].x;
+    r[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) r[threadIdx.x] += r[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl->plaquette = r[0] * scale;
+}
+
 // Copy the leading words of n control blocks (cs bytes apart) into a dense array.
 __global__ void __launch_bounds__(64) k_gather_heads(const unsigned char* __restrict__ ctl0, size_t cs, int words,
                                                      unsigned long long* __restrict__ out) {

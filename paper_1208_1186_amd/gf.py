@@ -65,6 +65,7 @@ def _signatures(lib):
         "gf_get_state": (i32, [_P, _P, sz]),
         "gf_set_state": (i32, [_P, _P, sz]),
         "gf_fft_tiling": (i32, [_P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "gf_plaquette": (i32, [_P, pd]),
         "gf_quality": (i32, [_P, pd, pd]),
         "gf_get_links": (i32, [_P, _P]),
         "gf_get_gauge": (i32, [_P, _P]),
@@ -213,6 +214,12 @@ def gf_fft_tiling(ctx):
     g, b = ctypes.c_int32(), ctypes.c_int32()
     _check(ctx, load().gf_fft_tiling(ctx, ctypes.byref(g), ctypes.byref(b)))
     return g.value, b.value
+
+
+def gf_plaquette(ctx):
+    p = ctypes.c_double()
+    _check(ctx, load().gf_plaquette(ctx, ctypes.byref(p)))
+    return p.value
 
 
 def gf_quality(ctx):
@@ -403,6 +410,9 @@ class GaugeFixer:
 
     def quality(self):
         return gf_quality(self.ctx)
+
+    def plaquette(self):
+        return gf_plaquette(self.ctx)
 
     def history(self, n):
         return gf_history(self.ctx, n)

@@ -255,3 +255,17 @@ def test_workload_shapes_loop(dims):
         outs.append(ug)
     assert np.max(np.abs(outs[0] - outs[1])) < 1e-14
 
+
+
+@pytest.mark.parametrize("dims,precision", [((8, 8, 8, 8), "fp64_18"), ((12, 8, 6, 4), "fp64_12"),
+                                            ((6, 4, 8, 4), "fp32_12"), ((16, 16, 16, 16), "mixed")])
+def test_plaquette_matches_oracle_and_is_invariant(dims, precision):
+    print(f"plaquette {dims} {precision}", flush=True)
+    u = synth.make_config(dims, 41)
+    links = to_dev(u)
+    fx = gf.GaugeFixer(links, precision)
+    want = observables.plaquette(u)
+    tol = 1e-6 if precision.startswith("fp32") or precision == "mixed" else 1e-13
+    assert fx.plaquette() == pytest.approx(want, abs=tol)
+    fx.fix_until(1e-15 if precision != "fp32_12" else 1e-11, 10000)
+    assert fx.plaquette() == pytest.approx(want, abs=1e-12 if precision != "fp32_12" else 1e-6)
