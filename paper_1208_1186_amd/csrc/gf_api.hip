@@ -313,6 +313,7 @@ struct gf_ctx {
     BatchState* batch = nullptr;  // set on a context made by gf_init_batch
     FftPlan plan[4];
     Ctl* h_head;  // pinned host copy of the control block's leading scalars
+    bool own_head = true;  // h_head was allocated here (not a slot of a batch group's array)
     std::string err;
     // Optional per-kernel HIP-event timing (gf_set_timing / gf_kernel_times).
     bool timing = false;
@@ -955,27 +956,47 @@ void carve(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsi
     for (int d = 1; d < 4; ++d) c->geom.stride[d] = c->geom.stride[d - 1] * L.n[d - 1];
 }
 
+// Host data uploaded at set-up: the tables and the initial control-block head. A batch group shares
+// one copy among its configurations and keeps it until its stream has been synchronised.
+struct HostInit {
+    std::vector<unsigned char> tables;
+    std::vector<unsigned char> head;
+};
+
+void build_host_init(gf_ctx* c, HostInit& h) {
+    if (c->L.fp32)
+        fill_tables<float>(c, h.tables);
+    else
+        fill_tables<double>(c, h.tables);
+    h.head.assign(kHeadBytes, 0);
+    const double no_tol = -1.0;
+    std::memcpy(h.head.data() + offsetof(Ctl, tol), &no_tol, sizeof(double));
+}
+
+// Set a plain context up in ws: tables, control block, links packed from the canonical d_links, the
+// accumulated transform set to 1, and (if measure) theta and F of the input. With shared (a batch
+// group's configurations) the host data come from there, h_head is the given slot and nothing is
+// read back or waited for: the caller synchronises the stream before `shared` goes away.
 gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsigned char* ws,
-                     hipStream_t st, bool measure) {
+                     hipStream_t st, bool measure, HostInit* shared = nullptr, Ctl* head_slot = nullptr) {
     carve(c, p, L, d_links, ws, st);
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_head), kHeadBytes) != hipSuccess) {
+    if (head_slot) {
+        c->h_head = head_slot;
+        c->own_head = false;
+    } else if (hipHostMalloc(reinterpret_cast<void**>(&c->h_head), kHeadBytes) != hipSuccess) {
         c->h_head = nullptr;
         return fail(c, GF_EDEVICE, "hipHostMalloc of the control readback buffer failed");
     }
     std::memset(c->h_head, 0, kHeadBytes);
     raise_lds_limits();
-    std::vector<unsigned char> host;
-    if (L.fp32)
-        fill_tables<float>(c, host);
-    else
-        fill_tables<double>(c, host);
-    Ctl head{};
-    head.tol = -1.0;
+    HostInit own;
+    HostInit& h = shared ? *shared : own;
+    if (h.tables.empty()) build_host_init(c, h);
     gf_status s;
-    if ((s = check_hip(c, hipMemcpyAsync(c->sin2, host.data(), host.size(), hipMemcpyHostToDevice, c->st),
+    if ((s = check_hip(c, hipMemcpyAsync(c->sin2, h.tables.data(), h.tables.size(), hipMemcpyHostToDevice, c->st),
                        "table upload")) != GF_OK)
         return s;
-    if ((s = check_hip(c, hipMemcpyAsync(c->ctl, &head, kHeadBytes, hipMemcpyHostToDevice, c->st),
+    if ((s = check_hip(c, hipMemcpyAsync(c->ctl, h.head.data(), kHeadBytes, hipMemcpyHostToDevice, c->st),
                        "control upload")) != GF_OK)
         return s;
     GF_DISPATCH(c, launch_pack_t, c, c->links_user);
@@ -991,9 +1012,10 @@ gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_l
     }
     if (s == GF_OK && measure) s = launch_measure(c);
     if (s == GF_OK) s = autotune(c);
+    if (shared) return s;
     if (s == GF_OK) s = read_head(c);
     if (s == GF_OK) {
-        // hipMemcpyAsync from pageable memory may return before the copy is done: keep `host` alive until here.
+        // hipMemcpyAsync from pageable memory may return before the copy is done: keep `own` alive until here.
         s = check_hip(c, hipStreamSynchronize(c->st), "sync");
     }
     return s;
@@ -1007,7 +1029,7 @@ void free_ctx(gf_ctx* c) {
     if (c->batch) free_batch(c->batch);
     if (c->h_head) {
         (void)hipStreamSynchronize(c->st);
-        (void)hipHostFree(c->h_head);
+        if (c->own_head) (void)hipHostFree(c->h_head);
     }
     for (auto& e : c->ev) (void)hipEventDestroy(e);
     delete c;
@@ -1161,6 +1183,20 @@ struct BatchGroup {
     unsigned char* d_heads = nullptr;
     int* h_act = nullptr;              // pinned
     unsigned char* h_heads = nullptr;  // pinned
+    std::vector<unsigned char> h_views[2];  // the configurations' control-block heads (host)
+    hipStream_t st = nullptr;          // the group's own stream: groups run side by side
+    hipEvent_t ev = nullptr;           // end of the group's last queued read-back
+    // progress of gf_fix_until_batch
+    enum Stage { kStart, kRun, kEnd, kDone } stage = kStart;
+    int ph = 0;
+    long long k = 0;   // updates every active configuration of the phase has applied
+    int64_t left = 0;  // updates the group may still apply
+    int64_t n_it = 0;  // updates in the chunk being read back
+    bool waiting = false;
+    std::vector<int> act;
+    std::vector<double> last;
+    std::vector<long long> it0;
+    std::vector<char> stalled;
 };
 
 struct BatchState {
@@ -1178,6 +1214,11 @@ void free_batch(BatchState* b) {
         }
         if (g.h_act) (void)hipHostFree(g.h_act);
         if (g.h_heads) (void)hipHostFree(g.h_heads);
+        if (g.ev) (void)hipEventDestroy(g.ev);
+        if (g.st) {
+            (void)hipStreamSynchronize(g.st);
+            (void)hipStreamDestroy(g.st);
+        }
     }
     delete b;
 }
@@ -1239,9 +1280,27 @@ gf_status plan_batch(int32_t n, const gf_params* params, BatchState& b, std::str
     return GF_OK;
 }
 
-gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned char* ws, hipStream_t st) {
+gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned char* ws, hipStream_t caller) {
+    hipEvent_t ready = nullptr;  // the caller's links are written on its stream
+    GF_TRY_HIP(c, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    gf_status rs = check_hip(c, hipEventRecord(ready, caller), "event record");
     for (auto& g : b.g) {
+        if (rs != GF_OK) break;
+        rs = check_hip(c, hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking), "stream create");
+        if (rs == GF_OK) rs = check_hip(c, hipEventCreateWithFlags(&g.ev, hipEventDisableTiming), "event create");
+        if (rs == GF_OK) rs = check_hip(c, hipStreamWaitEvent(g.st, ready, 0), "stream wait");
+    }
+    (void)hipEventDestroy(ready);
+    if (rs != GF_OK) return rs;
+    for (auto& g : b.g) {
+        const hipStream_t st = g.st;
         const int ng = (int)g.idx.size();
+        HostInit hinit[2];
+        struct Drain {  // the uploads from hinit have finished before it goes away, on every return path
+            hipStream_t st;
+            ~Drain() { (void)hipStreamSynchronize(st); }
+        } drain{st};
+        for (int ph = 0; ph < g.nphase; ++ph) g.h_views[ph].assign((size_t)ng * kHeadBytes, 0);
         g.d_act = reinterpret_cast<int*>(ws + g.off_act);
         g.d_heads = ws + g.off_heads;
         if (hipHostMalloc(reinterpret_cast<void**>(&g.h_act), ng * sizeof(int)) != hipSuccess ||
@@ -1253,8 +1312,9 @@ gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned 
                 if (!v) return fail(c, GF_EINVAL, "out of host memory");
                 g.view[ph].push_back(v);
                 // a GF_MIXED double slab keeps the input links in its buffer 0 until the hand-over
-                const gf_status s = init_plain(v, g.q[ph], g.L[ph], d_links[g.idx[i]], ws + g.off[ph] + i * g.cs[ph],
-                                               st, ph == 0);
+                const gf_status s =
+                    init_plain(v, g.q[ph], g.L[ph], d_links[g.idx[i]], ws + g.off[ph] + i * g.cs[ph], st, ph == 0,
+                               &hinit[ph], reinterpret_cast<Ctl*>(g.h_views[ph].data() + (size_t)i * kHeadBytes));
                 if (s != GF_OK) return fail(c, s, v->err);
             }
             gf_ctx* d = new (std::nothrow) gf_ctx();
@@ -1266,22 +1326,33 @@ gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned 
             d->cs = g.cs[ph];
             d->act_dev = g.d_act;
         }
+        GF_TRY_HIP(c, hipStreamSynchronize(st));  // reports a failed upload (drain repeats it harmlessly)
     }
     return GF_OK;
 }
 
-// Read the control blocks of every configuration of phase ph into their views.
-gf_status gather_heads(gf_ctx* c, BatchGroup& g, int ph) {
+// Queue the read-back of every control block of phase ph (one gather kernel and one copy), and
+// mark its end with the group's event.
+gf_status enqueue_gather(gf_ctx* c, BatchGroup& g) {
     const int ng = (int)g.idx.size();
-    hipLaunchKernelGGL(k_gather_heads, dim3(ng), dim3(64), 0, c->st,
-                       reinterpret_cast<const unsigned char*>(g.view[ph][0]->ctl), g.cs[ph], (int)(kHeadBytes / 8),
-                       reinterpret_cast<unsigned long long*>(g.d_heads));
+    hipLaunchKernelGGL(k_gather_heads, dim3(ng), dim3(64), 0, g.st,
+                       reinterpret_cast<const unsigned char*>(g.view[g.ph][0]->ctl), g.cs[g.ph],
+                       (int)(kHeadBytes / 8), reinterpret_cast<unsigned long long*>(g.d_heads));
     gf_status s = launched(c, "gather launch");
     if (s != GF_OK) return s;
-    GF_TRY_HIP(c, hipMemcpyAsync(g.h_heads, g.d_heads, ng * kHeadBytes, hipMemcpyDeviceToHost, c->st));
-    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    GF_TRY_HIP(c, hipMemcpyAsync(g.h_heads, g.d_heads, ng * kHeadBytes, hipMemcpyDeviceToHost, g.st));
+    GF_TRY_HIP(c, hipEventRecord(g.ev, g.st));
+    g.waiting = true;
+    return GF_OK;
+}
+
+// Wait for the read-back and copy the control blocks into the views.
+gf_status finish_gather(gf_ctx* c, BatchGroup& g) {
+    GF_TRY_HIP(c, hipEventSynchronize(g.ev));
+    g.waiting = false;
+    const int ng = (int)g.idx.size();
     for (int i = 0; i < ng; ++i) {
-        gf_ctx* v = g.view[ph][i];
+        gf_ctx* v = g.view[g.ph][i];
         std::memcpy(v->h_head, g.h_heads + (size_t)i * kHeadBytes, kHeadBytes);
         v->k_host = v->h_head->iters;
     }
@@ -1307,82 +1378,149 @@ gf_status finish_config(gf_ctx* c, gf_ctx* v, int phase, long long iters_before,
     return GF_OK;
 }
 
-gf_status run_group(gf_ctx* c, BatchGroup& g, double tol, int64_t max_iter, std::vector<BatchOutcome>& out) {
+double phase_tol(const gf_ctx* c, const BatchGroup& g, double tol) {
+    return (g.nphase == 2 && g.ph == 0) ? std::max(c->p.switch_theta, tol) : tol;
+}
+
+// Queue the group's next piece of work on its stream (ending in a read-back when the host must look
+// at the control blocks before going on).
+gf_status advance_group(gf_ctx* c, BatchGroup& g, double tol, std::vector<BatchOutcome>& out) {
     const int ng = (int)g.idx.size();
     const bool mixed = g.nphase == 2;
-    int64_t left = max_iter;
-    std::vector<long long> it0(ng, 0);  // float-phase updates of each configuration
-    std::vector<char> stalled(ng, 0);
     gf_status s = GF_OK;
-    for (int ph = 0; ph < g.nphase; ++ph) {
-        const double tp = (mixed && ph == 0) ? std::max(c->p.switch_theta, tol) : tol;
-        gf_ctx* drv = g.drv[ph];
-        for (int i = 0; i < ng && s == GF_OK; ++i)
-            if (!out[g.idx[i]].finished) s = set_tol(g.view[ph][i], tp);
-        if (s == GF_OK) s = gather_heads(c, g, ph);
-        if (s != GF_OK) return s;
-        std::vector<int> act;
-        std::vector<double> last(ng, 0.0);
-        for (int i = 0; i < ng; ++i) {
-            const Ctl* h = g.view[ph][i]->h_head;
-            last[i] = h->theta;
-            if (!out[g.idx[i]].finished && !h->done) act.push_back(i);
-        }
-        long long k = 0;  // every active configuration of the phase has applied k updates
-        while (!act.empty() && left > 0) {
-            std::copy(act.begin(), act.end(), g.h_act);
-            GF_TRY_HIP(c, hipMemcpyAsync(g.d_act, g.h_act, act.size() * sizeof(int), hipMemcpyHostToDevice, c->st));
-            drv->nact = (int)act.size();
-            const int64_t n_it = std::min<int64_t>(left, c->p.check_every);
-            for (int64_t j = 0; j < n_it && s == GF_OK; ++j) s = one_iteration(drv, k + j);
+    switch (g.stage) {
+        case BatchGroup::kStart:  // arm the stopping test of the phase, then read every control block
+            for (int i = 0; i < ng && s == GF_OK; ++i)
+                if (!out[g.idx[i]].finished) s = set_tol(g.view[g.ph][i], phase_tol(c, g, tol));
+            if (s == GF_OK) s = enqueue_gather(c, g);
+            return s;
+        case BatchGroup::kRun: {  // one chunk of updates over the active configurations
+            gf_ctx* drv = g.drv[g.ph];
+            std::copy(g.act.begin(), g.act.end(), g.h_act);
+            GF_TRY_HIP(c, hipMemcpyAsync(g.d_act, g.h_act, g.act.size() * sizeof(int), hipMemcpyHostToDevice, g.st));
+            drv->nact = (int)g.act.size();
+            g.n_it = std::min<int64_t>(g.left, c->p.check_every);
+            for (int64_t j = 0; j < g.n_it && s == GF_OK; ++j) s = one_iteration(drv, g.k + j);
             if (s == GF_OK) s = loop_finalize(drv);
-            if (s == GF_OK) s = gather_heads(c, g, ph);
-            if (s != GF_OK) return fail(c, s, drv->err);
-            k += n_it;
-            left -= n_it;
-            std::vector<int> next;
-            for (int i : act) {
-                const Ctl* h = g.view[ph][i]->h_head;
-                if (h->done || h->numeric) continue;
-                if (h->iters != k) return fail(c, GF_EDEVICE, "batch configurations fell out of step");
-                if (mixed && ph == 0) {
-                    const double th = h->theta;
-                    stalled[i] = th < kStallTheta && th > kStallRatio * last[i];
-                    last[i] = th;
-                    if (stalled[i]) continue;
-                }
-                next.push_back(i);
-            }
-            act.swap(next);
+            if (s == GF_OK) s = enqueue_gather(c, g);
+            return s == GF_OK ? GF_OK : fail(c, s, drv->err);
         }
-        for (int i = 0; i < ng; ++i) {
-            BatchOutcome& o = out[g.idx[i]];
-            if (o.finished) continue;
-            gf_ctx* v = g.view[ph][i];
-            const Ctl* h = v->h_head;
-            if (mixed && ph == 0) {
-                it0[i] = h->iters;
-                const bool reached = h->theta < tp;
-                if (h->numeric || (tol > 0.0 && h->theta < tol) || (!reached && !stalled[i])) {
-                    // converged in float, not finite, or out of iterations before the hand-over
-                    s = finish_config(c, v, 0, 0, o, h->theta < tol);
+        case BatchGroup::kEnd: {  // hand-over to double precision, or the results of the phase
+            const double tp = phase_tol(c, g, tol);
+            for (int i = 0; i < ng; ++i) {
+                BatchOutcome& o = out[g.idx[i]];
+                if (o.finished) continue;
+                gf_ctx* v = g.view[g.ph][i];
+                const Ctl* h = v->h_head;
+                if (mixed && g.ph == 0) {
+                    g.it0[i] = h->iters;
+                    const bool reached = h->theta < tp;
+                    if (h->numeric || (tol > 0.0 && h->theta < tol) || (!reached && !g.stalled[i])) {
+                        // converged in float, not finite, or out of iterations before the hand-over
+                        s = finish_config(c, v, 0, 0, o, h->theta < tol);
+                        if (s != GF_OK) return s;
+                        continue;
+                    }
+                    gf_ctx* w = g.view[1][i];
+                    hipLaunchKernelGGL(k_apply_accumulated<9>, dim3(w->L.nblk), dim3(kSiteThreads), 0, w->st,
+                                       links_of<double, 9>(w, 0), reinterpret_cast<const cx<float>*>(v->Acc),
+                                       v->L.ps, reinterpret_cast<cx<double>*>(w->Acc), w->L.ps, w->geom);
+                    s = launched(w, "hand-over launch");
+                    if (s == GF_OK) s = launch_measure(w);
+                    if (s != GF_OK) return fail(c, s, w->err);
+                } else {
+                    s = finish_config(c, v, mixed ? 1 : (v->L.fp32 ? 0 : 1), mixed ? g.it0[i] : 0, o, h->done != 0);
                     if (s != GF_OK) return s;
-                    continue;
                 }
-                gf_ctx* w = g.view[1][i];
-                hipLaunchKernelGGL(k_apply_accumulated<9>, dim3(w->L.nblk), dim3(kSiteThreads), 0, w->st,
-                                   links_of<double, 9>(w, 0), reinterpret_cast<const cx<float>*>(v->Acc), v->L.ps,
-                                   reinterpret_cast<cx<double>*>(w->Acc), w->L.ps, w->geom);
-                s = launched(w, "hand-over launch");
-                if (s == GF_OK) s = launch_measure(w);
-                if (s != GF_OK) return fail(c, s, w->err);
-            } else {
-                s = finish_config(c, v, mixed ? 1 : (v->L.fp32 ? 0 : 1), mixed ? it0[i] : 0, o, h->done != 0);
-                if (s != GF_OK) return s;
             }
+            if (mixed && g.ph == 0) {
+                g.ph = 1;
+                g.stage = BatchGroup::kStart;
+            } else {
+                g.stage = BatchGroup::kDone;
+            }
+            return GF_OK;
         }
+        case BatchGroup::kDone:
+            return GF_OK;
     }
     return GF_OK;
+}
+
+// Take in the read-back that advance_group queued.
+gf_status absorb_group(gf_ctx* c, BatchGroup& g, std::vector<BatchOutcome>& out) {
+    gf_status s = finish_gather(c, g);
+    if (s != GF_OK) return s;
+    const int ng = (int)g.idx.size();
+    if (g.stage == BatchGroup::kStart) {
+        g.act.clear();
+        g.last.assign(ng, 0.0);
+        for (int i = 0; i < ng; ++i) {
+            const Ctl* h = g.view[g.ph][i]->h_head;
+            g.last[i] = h->theta;
+            if (!out[g.idx[i]].finished && !h->done) g.act.push_back(i);
+        }
+        g.k = 0;  // every configuration of a phase starts from its own count 0
+        g.stage = (g.act.empty() || g.left <= 0) ? BatchGroup::kEnd : BatchGroup::kRun;
+        return GF_OK;
+    }
+    // a chunk of updates
+    g.k += g.n_it;
+    g.left -= g.n_it;
+    std::vector<int> next;
+    for (int i : g.act) {
+        const Ctl* h = g.view[g.ph][i]->h_head;
+        if (h->done || h->numeric) continue;
+        if (h->iters != g.k) return fail(c, GF_EDEVICE, "batch configurations fell out of step");
+        if (g.nphase == 2 && g.ph == 0) {
+            const double th = h->theta;
+            g.stalled[i] = th < kStallTheta && th > kStallRatio * g.last[i];
+            g.last[i] = th;
+            if (g.stalled[i]) continue;
+        }
+        next.push_back(i);
+    }
+    g.act.swap(next);
+    if (g.act.empty() || g.left <= 0) g.stage = BatchGroup::kEnd;
+    return GF_OK;
+}
+
+// Every group to completion, side by side: queue each group's next piece of work on its stream,
+// then take in the read-backs in turn.
+gf_status run_batch(gf_ctx* c, BatchState& b, double tol, int64_t max_iter, std::vector<BatchOutcome>& out) {
+    hipEvent_t ready = nullptr;  // the caller's stream is ordered before the groups' work
+    GF_TRY_HIP(c, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    gf_status s = check_hip(c, hipEventRecord(ready, c->st), "event record");
+    for (auto& g : b.g) {
+        const int ng = (int)g.idx.size();
+        g.stage = BatchGroup::kStart;
+        g.ph = 0;
+        g.k = 0;
+        g.left = max_iter;
+        g.waiting = false;
+        g.it0.assign(ng, 0);
+        g.stalled.assign(ng, 0);
+        if (s == GF_OK) s = check_hip(c, hipStreamWaitEvent(g.st, ready, 0), "stream wait");
+    }
+    (void)hipEventDestroy(ready);
+    bool busy = true;
+    while (s == GF_OK && busy) {
+        busy = false;
+        for (auto& g : b.g) {
+            // phase ends queue work without a read-back: go on with the group until it waits or is done
+            while (s == GF_OK && !g.waiting && g.stage != BatchGroup::kDone) s = advance_group(c, g, tol, out);
+            busy = busy || g.stage != BatchGroup::kDone;
+        }
+        for (auto& g : b.g)
+            if (s == GF_OK && g.waiting) s = absorb_group(c, g, out);
+    }
+    // the caller's stream waits for every group (the results are in the caller's link buffers)
+    for (auto& g : b.g) {
+        if (s != GF_OK) break;
+        s = check_hip(c, hipEventRecord(g.ev, g.st), "event record");
+        if (s == GF_OK) s = check_hip(c, hipStreamWaitEvent(c->st, g.ev, 0), "stream wait");
+    }
+    return s;
 }
 }  // namespace
 
@@ -1581,11 +1719,9 @@ gf_status gf_fix_until_batch(gf_ctx* c, double tol, int64_t max_iter, gf_result*
         const auto t0 = std::chrono::steady_clock::now();
         BatchState& b = *c->batch;
         std::vector<BatchOutcome> out(b.n);
-        for (auto& g : b.g) {
-            gf_status s = run_group(c, g, tol, max_iter, out);
-            if (s != GF_OK) return s;
-        }
-        gf_status s = check_hip(c, hipStreamSynchronize(c->st), "sync");
+        gf_status s = run_batch(c, b, tol, max_iter, out);
+        if (s != GF_OK) return s;
+        s = check_hip(c, hipStreamSynchronize(c->st), "sync");
         if (s != GF_OK) return s;
         const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         gf_status worst = GF_OK;

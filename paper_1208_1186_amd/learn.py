@@ -44,8 +44,9 @@ def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=
     import torch
     T = n_tuples(dims)
     xs, ts = [], []
-    for seed in seeds:
-        u = synth.make_config(dims, seed, eps)
+    seeds = list(seeds)
+    configs = synth.make_configs([dims] * len(seeds), seeds, eps)  # host worker processes
+    for seed, u in zip(seeds, configs):
         links = torch.from_numpy(u).to(device)
         fx = gf.GaugeFixer(links, precision, alpha=alpha, flags=gf.FLAG_RECORD_SPECTRA)
         rec, theta = fx.record(n_iter, probe_scale)
@@ -103,7 +104,7 @@ def train(X, TG, T, n_samples, epochs=20, batch=16, lr=2e-3, seed=0, params=None
     return p, hist
 
 
-def train_default(dims=(16, 16, 16, 16), n_train=64, n_iter=120, epochs=60, batch=32, lr=1e-3, seed=0,
+def train_default(dims=(16, 16, 16, 16), n_train=64, n_iter=60, epochs=60, batch=32, lr=1e-3, seed=0,
                   first_seed=100, log=None):
     """The training recipe used for the learned workload: record n_train plain-FA trajectories of
     seeded dims lattices (seeds first_seed..), then Adam over whole samples. Returns (params, info)."""
