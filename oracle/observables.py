@@ -61,3 +61,45 @@ def singlet_correlator(u, r, axis_mu=0):
     w = wilson_lines(u)
     wr = np.roll(w, -r, axis=2 - axis_mu)
     return complex(np.mean(trace(wr @ dag(w))) / 3.0)
+
+
+def singlet_table(u):
+    """C(r) = (1/(3 V_s)) sum_x Tr[W(x + r) W(x)^dagger] for every spatial separation r (Eq. 1 before the
+    ensemble average), by the definition: one periodic shift of the Wilson lines per r.
+
+    Returns a complex array of shape (Nz, Ny, Nx); entry [rz, ry, rx] is r = (rx, ry, rz). C(-r) is the
+    complex conjugate of C(r), so any average over r and -r is real.
+    """
+    w = wilson_lines(u)
+    nz, ny, nx = w.shape[:3]
+    out = np.empty((nz, ny, nx), dtype=np.complex128)
+    for rz in range(nz):
+        for ry in range(ny):
+            for rx in range(nx):
+                wr = np.roll(w, (-rz, -ry, -rx), axis=(0, 1, 2))  # wr[x] = W(x + r)
+                out[rz, ry, rx] = np.mean(trace(wr @ dag(w))) / 3.0
+    return out
+
+
+def distance_sq(spatial_dims):
+    """r^2 = sum_i min(r_i, N_i - r_i)^2 of every separation, shape (Nz, Ny, Nx) for spatial_dims (Nx, Ny, Nz)."""
+    nx, ny, nz = spatial_dims
+    out = np.empty((nz, ny, nx), dtype=np.int64)
+    for rz in range(nz):
+        for ry in range(ny):
+            for rx in range(nx):
+                out[rz, ry, rx] = min(rx, nx - rx) ** 2 + min(ry, ny - ry) ** 2 + min(rz, nz - rz) ** 2
+    return out
+
+
+def shell_average(table, spatial_dims):
+    """Average of Re C(r) over each shell of equal r^2 (the periodic minimum-image distance).
+
+    Returns (r2, count, mean): the distinct r^2 in increasing order, the number of separations in each
+    shell and the mean of Re C over the shell.
+    """
+    d2 = distance_sq(spatial_dims)
+    r2 = sorted(set(int(v) for v in d2.ravel()))
+    count = np.array([int(np.sum(d2 == v)) for v in r2], dtype=np.int64)
+    mean = np.array([float(np.mean(table.real[d2 == v])) for v in r2])
+    return np.array(r2, dtype=np.int64), count, mean

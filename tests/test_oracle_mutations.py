@@ -119,3 +119,91 @@ def test_pins_catch_mutation(label, monkeypatch):
         except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError):
             failed += 1
     assert failed >= 1, f"no pin caught: {label}"
+
+
+# ------------------------------------------------------------ Wilson lines and the singlet correlator
+from oracle import observables  # noqa: E402
+import test_oracle_correlator as cpins  # noqa: E402
+
+_ORIG_LINES = observables.wilson_lines
+
+
+def _lines_reversed(u):
+    nt = u.shape[0]
+    w = u[nt - 1, ..., 3, :, :].copy()
+    for t in range(nt - 2, -1, -1):
+        w = w @ u[t, ..., 3, :, :]
+    return w
+
+
+def _table_wrong_direction(u):
+    w = _ORIG_LINES(u)
+    nz, ny, nx = w.shape[:3]
+    out = np.empty((nz, ny, nx), dtype=np.complex128)
+    for rz in range(nz):
+        for ry in range(ny):
+            for rx in range(nx):
+                wr = np.roll(w, (rz, ry, rx), axis=(0, 1, 2))
+                out[rz, ry, rx] = np.mean(su3.trace(wr @ su3.dag(w))) / 3.0
+    return out
+
+
+def _table_swapped_axes(u):
+    w = _ORIG_LINES(u)
+    nz, ny, nx = w.shape[:3]
+    out = np.empty((nz, ny, nx), dtype=np.complex128)
+    for rz in range(nz):
+        for ry in range(ny):
+            for rx in range(nx):
+                wr = np.roll(w, (-rx % nz, -ry, -rz % nx), axis=(0, 1, 2))
+                out[rz, ry, rx] = np.mean(su3.trace(wr @ su3.dag(w))) / 3.0
+    return out
+
+
+def _table_no_third(u):
+    return _ORIG_TABLE(u) * 3.0
+
+
+def _distance_no_min_image(spatial_dims):
+    nx, ny, nz = spatial_dims
+    rz, ry, rx = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return (rx * rx + ry * ry + rz * rz).astype(np.int64)
+
+
+_ORIG_TABLE = observables.singlet_table
+
+CORR_MUTATIONS = {
+    "lines multiplied in decreasing t": ("wilson_lines", _lines_reversed),
+    "separation taken as x - r": ("singlet_table", _table_wrong_direction),
+    "separation axes x and z swapped": ("singlet_table", _table_swapped_axes),
+    "correlator without the 1/3": ("singlet_table", _table_no_third),
+    "distance without the minimum image": ("distance_sq", _distance_no_min_image),
+}
+
+CORR_PINS = [
+    lambda: cpins.test_plane_wave_closed_form(),
+    lambda: cpins.test_zero_separation_and_sum_rule(),
+    lambda: cpins.test_wilson_line_order_is_gauge_covariant(),
+    lambda: cpins.test_correlator_symmetries(),
+    lambda: cpins.test_shell_counts(),
+    lambda: cpins.test_plane_wave_shell_average(),
+]
+
+
+def test_unmutated_correlator_oracle_passes_every_pin():
+    for pin in CORR_PINS:
+        pin()
+
+
+@pytest.mark.parametrize("label", sorted(CORR_MUTATIONS))
+def test_correlator_pins_catch_mutation(label, monkeypatch):
+    name, fn = CORR_MUTATIONS[label]
+    monkeypatch.setattr(observables, name, fn)
+    failed = 0
+    for pin in CORR_PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError):
+            failed += 1
+    assert failed >= 1, f"no pin caught: {label}"
