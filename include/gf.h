@@ -332,6 +332,60 @@ const char* gf_last_error(const gf_ctx* ctx);
 /* Free the host context (the caller frees its own device buffers). */
 void gf_destroy(gf_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Temporal Wilson lines and the colour-singlet correlator (paper, Section 1,
+ * Eq. (1)): the singlet free energy comes from (1/3) < Tr W(r) W(0)^dag >,
+ * which is not gauge invariant and is taken on the Landau-gauge-fixed field.
+ * For one configuration:
+ *     W(x) = U_t(x, 0) U_t(x, 1) ... U_t(x, Nt-1)          (x spatial)
+ *     C(r) = 1/(3 Vs) sum_x Re Tr[W(x + r) W(x)^dag]       (every r, periodic)
+ * with Vs = Nx Ny Nz; the ensemble average over configurations is the
+ * caller's. The imaginary part is odd in r and is dropped (it cancels in any
+ * average over r and -r). Shells group the separations by the minimum-image
+ * r^2 = sum_i min(r_i, N_i - r_i)^2, in increasing r^2; a shell's value is
+ * the mean of C over its members, summed in a fixed order. The sum over x
+ * runs as a cyclic correlation by 3D FFT of the nine matrix elements.
+ * Double precision throughout. dims as in gf_params (each extent even,
+ * 2^a 3^b, <= 64).
+ * ---------------------------------------------------------------------- */
+typedef struct gf_wilson gf_wilson;
+
+/* Device workspace bytes for these dims (0 if invalid). */
+size_t gf_wilson_workspace_bytes(const int32_t dims[4]);
+
+/*
+ * Create a handle over the caller's workspace (>= gf_wilson_workspace_bytes,
+ * 256-byte aligned, owned by the caller and kept for the handle's life).
+ * Uploads the twiddle and shell tables on stream (a hipStream_t, NULL = the
+ * default stream) and synchronises it. GF_EINVAL / GF_ENOTSUP: nothing is
+ * created (gf_wilson_last_error(NULL) gives the reason).
+ */
+gf_status gf_wilson_create(gf_wilson** out, const int32_t dims[4], void* d_workspace,
+                           size_t workspace_bytes, void* stream);
+
+/* Number of shells (-1 for a NULL handle). */
+int32_t gf_wilson_shell_count(const gf_wilson* w);
+
+/* Host copies of each shell's r^2 and member count (either pointer may be NULL). */
+gf_status gf_wilson_shells(const gf_wilson* w, int32_t* h_r2, int32_t* h_count);
+
+/*
+ * Queue the correlator of canonical links d_links (complex double
+ * [s][mu][row][col], the layout gf_init takes and returns) on the handle's
+ * stream; nothing is synchronised. Outputs (device, caller-owned; each may be
+ * NULL): d_lines, W as complex double [xs][row][col] with xs = x + Nx(y + Ny z);
+ * d_corr, C(r) as double [rz][ry][rx]; d_shell, gf_wilson_shell_count doubles.
+ * Calls on one handle must not overlap (they share its workspace).
+ */
+gf_status gf_wilson_correlator(gf_wilson* w, const double* d_links, double* d_lines, double* d_corr,
+                               double* d_shell);
+
+/* Message of the last error on this handle (or of the last failed create if w is NULL). */
+const char* gf_wilson_last_error(const gf_wilson* w);
+
+/* Free the handle (synchronises its stream first). */
+void gf_wilson_destroy(gf_wilson* w);
+
 #ifdef __cplusplus
 }
 #endif

@@ -76,9 +76,15 @@ def singlet_table(u):
     for rz in range(nz):
         for ry in range(ny):
             for rx in range(nx):
-                wr = np.roll(w, (-rz, -ry, -rx), axis=(0, 1, 2))  # wr[x] = W(x + r)
-                out[rz, ry, rx] = np.mean(trace(wr @ dag(w))) / 3.0
+                out[rz, ry, rx] = singlet_at(w, (rx, ry, rz))
     return out
+
+
+def singlet_at(w, r):
+    """C(r) for one separation r = (rx, ry, rz), from Wilson lines w of shape (Nz, Ny, Nx, 3, 3)."""
+    rx, ry, rz = r
+    wr = np.roll(w, (-rz, -ry, -rx), axis=(0, 1, 2))  # wr[x] = W(x + r)
+    return complex(np.mean(trace(wr @ dag(w))) / 3.0)
 
 
 def distance_sq(spatial_dims):

@@ -87,6 +87,13 @@ def _signatures(lib):
         "gf_mlp_loss_grad": (i32, [_P, _P, _P, _P, i32, i64, _P, _P, sz, _P, pd]),
         "gf_mlp_adam": (i32, [_P, _P, _P, _P, i64, ctypes.c_float, _P]),
         "gf_mlp_train_step": (i32, [_P, _P, _P, i64, ctypes.c_float, _P, _P, _P, i32, i64, _P, _P, sz, _P, pd]),
+        "gf_wilson_workspace_bytes": (sz, [ctypes.POINTER(i32)]),
+        "gf_wilson_create": (i32, [ctypes.POINTER(_P), ctypes.POINTER(i32), _P, sz, _P]),
+        "gf_wilson_shell_count": (i32, [_P]),
+        "gf_wilson_shells": (i32, [_P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "gf_wilson_correlator": (i32, [_P, _P, _P, _P, _P]),
+        "gf_wilson_last_error": (ctypes.c_char_p, [_P]),
+        "gf_wilson_destroy": (None, [_P]),
         "gf_last_error": (ctypes.c_char_p, [_P]),
         "gf_destroy": (None, [_P]),
     }
@@ -506,6 +513,91 @@ class BatchFixer:
         if getattr(self, "ctx", None):
             gf_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ Wilson lines and the singlet correlator
+
+def _dims4(dims):
+    return (ctypes.c_int32 * 4)(*[int(d) for d in dims])
+
+
+def gf_wilson_workspace_bytes(dims):
+    return load().gf_wilson_workspace_bytes(_dims4(dims))
+
+
+def gf_wilson_last_error(w):
+    msg = load().gf_wilson_last_error(w)
+    return msg.decode() if msg else ""
+
+
+def gf_wilson_create(dims, d_workspace, workspace_bytes, stream=0):
+    w = _P()
+    st = load().gf_wilson_create(ctypes.byref(w), _dims4(dims), _P(d_workspace), workspace_bytes, _P(stream))
+    if st != GF_OK:
+        raise GfError(st, gf_wilson_last_error(None))
+    return w
+
+
+def gf_wilson_shells(w):
+    lib = load()
+    n = lib.gf_wilson_shell_count(w)
+    r2 = (ctypes.c_int32 * n)()
+    cnt = (ctypes.c_int32 * n)()
+    st = lib.gf_wilson_shells(w, r2, cnt)
+    if st != GF_OK:
+        raise GfError(st, gf_wilson_last_error(w))
+    return list(r2), list(cnt)
+
+
+def gf_wilson_correlator(w, d_links, d_lines=0, d_corr=0, d_shell=0):
+    st = load().gf_wilson_correlator(w, _P(d_links), _P(d_lines or None), _P(d_corr or None), _P(d_shell or None))
+    if st != GF_OK:
+        raise GfError(st, gf_wilson_last_error(w))
+
+
+class WilsonCorrelator:
+    """Temporal Wilson lines and the singlet correlator of complex128 CUDA links (Nt, Nz, Ny, Nx, 4, 3, 3)."""
+
+    def __init__(self, dims, device="cuda:0", stream=None):
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        nbytes = gf_wilson_workspace_bytes(self.dims)
+        if nbytes == 0:
+            w = _P()
+            st = load().gf_wilson_create(ctypes.byref(w), _dims4(self.dims), None, 0, None)
+            raise GfError(st, gf_wilson_last_error(None))
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self.w = gf_wilson_create(self.dims, base + (-base) % 256, nbytes, self.stream.cuda_stream)
+        self.r2, self.count = gf_wilson_shells(self.w)
+
+    def __call__(self, links, lines=None, corr=None, shell=None):
+        """Queue the correlator; returns (lines, corr, shell) tensors (allocated when not given)."""
+        import torch
+        nx, ny, nz, nt = self.dims
+        if tuple(links.shape) != (nt, nz, ny, nx, 4, 3, 3) or links.dtype != torch.complex128 \
+                or not links.is_contiguous():
+            raise ValueError("links must be a contiguous complex128 tensor of shape (Nt, Nz, Ny, Nx, 4, 3, 3)")
+        dev = links.device
+        if corr is None:
+            corr = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev)
+        if shell is None:
+            shell = torch.empty(len(self.r2), dtype=torch.float64, device=dev)
+        gf_wilson_correlator(self.w, links.data_ptr(), lines.data_ptr() if lines is not None else 0,
+                             corr.data_ptr(), shell.data_ptr())
+        return lines, corr, shell
+
+    def close(self):
+        if getattr(self, "w", None):
+            load().gf_wilson_destroy(self.w)
+            self.w = None
 
     def __del__(self):
         try:

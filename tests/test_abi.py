@@ -125,3 +125,37 @@ def test_state_calls_reject_null_context(lib):
     assert lib.gf_state_bytes(None) == 0
     assert lib.gf_get_state(None, gf._P(256), 1 << 20) == gf.GF_EINVAL
     assert lib.gf_set_state(None, gf._P(256), 1 << 20) == gf.GF_EINVAL
+
+
+@pytest.mark.parametrize("dims,status", [
+    ((8, 8, 8, 5), gf.GF_ENOTSUP),
+    ((10, 8, 8, 8), gf.GF_ENOTSUP),
+    ((8, 128, 8, 8), gf.GF_ENOTSUP),
+    ((8, 8, 1, 8), gf.GF_EINVAL),
+])
+def test_wilson_bad_dims_rejected_before_device(lib, dims, status):
+    d = gf._dims4(dims)
+    assert lib.gf_wilson_workspace_bytes(d) == 0
+    w = gf._P()
+    st = lib.gf_wilson_create(ctypes.byref(w), d, ctypes.c_void_p(256), 1 << 40, None)
+    assert st == status and not w.value
+    assert lib.gf_wilson_last_error(None)
+
+
+def test_wilson_workspace_and_null_handle(lib):
+    small = lib.gf_wilson_workspace_bytes(gf._dims4((8, 8, 8, 8)))
+    big = lib.gf_wilson_workspace_bytes(gf._dims4((16, 16, 16, 8)))
+    # nine planes of Wilson-line elements, the spectrum and the table dominate: 9*16 + 16 + 8 = 168 B per spatial site
+    assert small >= 168 * 512 and big >= 168 * 4096 and big > small
+    # Nt does not change the spatial workspace
+    assert lib.gf_wilson_workspace_bytes(gf._dims4((8, 8, 8, 32))) == small
+    w = gf._P()
+    assert lib.gf_wilson_create(ctypes.byref(w), gf._dims4((8, 8, 8, 8)), None, small, None) == gf.GF_EINVAL
+    assert lib.gf_wilson_create(ctypes.byref(w), gf._dims4((8, 8, 8, 8)), ctypes.c_void_p(256), small - 1,
+                                None) == gf.GF_EINVAL
+    assert lib.gf_wilson_create(ctypes.byref(w), gf._dims4((8, 8, 8, 8)), ctypes.c_void_p(257), small,
+                                None) == gf.GF_EINVAL
+    assert lib.gf_wilson_shell_count(None) == -1
+    assert lib.gf_wilson_shells(None, None, None) == gf.GF_EINVAL
+    assert lib.gf_wilson_correlator(None, None, None, None, None) == gf.GF_EINVAL
+    lib.gf_wilson_destroy(None)
