@@ -260,6 +260,53 @@ def learned_workload(gf, torch, synth):
     return out
 
 
+def wilson_bytes(dims):
+    """Algorithmic HBM bytes of one correlator call: the temporal links read once (144 B per site), the nine
+    Wilson-line planes written, transformed in (x, y) (read + write) and read by the z pass, the spectrum
+    written and transformed back, the table written and read by the shell pass with its member list."""
+    nx, ny, nz, nt = dims
+    vs = nx * ny * nz
+    lines = 144 * vs * nt + 9 * 16 * vs
+    return {"wilson_lines": lines, "total": lines + 2 * 9 * 16 * vs + 9 * 16 * vs + 16 * vs + 16 * vs + 8 * vs
+            + 8 * vs + 4 * vs}
+
+
+def wilson_workload(gf, torch, synth, dev, reps=50):
+    """Singlet correlator of temporal Wilson lines (Eq. 1) on Landau-gauge-fixed 32^4 and 48^3x8 fields."""
+    out = {}
+    for dims, eps in [((32, 32, 32, 32), synth.EPS_P059), ((48, 48, 48, 8), synth.EPS_P060)]:
+        nx, ny, nz, nt = dims
+        links = torch.from_numpy(synth.make_config(dims, 0, eps)).to(dev)
+        fx = gf.GaugeFixer(links, "fp64_18", check_every=10)
+        r = fx.fix_until(1e-15, 100000)
+        fx.close()
+        wc = gf.WilsonCorrelator(dims)
+        corr = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev)
+        shell = torch.empty(len(wc.r2), dtype=torch.float64, device=dev)
+        for _ in range(5):
+            wc(links, corr=corr, shell=shell)
+        stream = torch.cuda.current_stream(dev)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            wc(links, corr=corr, shell=shell)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        by = wilson_bytes(dims)
+        sh = shell.cpu().tolist()
+        key = f"{nx}x{ny}x{nz}x{nt}"
+        out[key] = {"fix_iters": int(r.iters), "fix_theta": r.theta, "us_per_correlator": round(us, 2),
+                    "correlators_per_s": round(1e6 / us, 1), "bytes_per_call": by["total"],
+                    "call_GBps": round(by["total"] / us / 1e3, 1), "shells": len(sh),
+                    "C_r2_0_1_2_3": [round(v, 6) for v in sh[:4]]}
+        log(f"wilson correlator {key}: {us:.1f} us per call ({by['total'] / us / 1e3:.0f} GB/s algorithmic)")
+        wc.close()
+        del links
+    return out
+
+
 def cpu_baseline(u, budget_s=12.0):
     """The FP64 NumPy oracle's FA iterations on the same input, on the host cores."""
     from oracle import landau
@@ -291,6 +338,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="skip the 48^3x8 mixed-precision workload")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice uneven batch workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner workload")
+    ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-line correlator workload")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -397,6 +445,8 @@ def main():
         extras["batch_64_uneven"] = batch_workload(gf, torch, synth, dev)
     if not args.no_extras and not args.no_learned:
         extras["learned_preconditioner"] = learned_workload(gf, torch, synth)
+    if not args.no_extras and not args.no_wilson:
+        extras["wilson_singlet_correlator"] = wilson_workload(gf, torch, synth, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

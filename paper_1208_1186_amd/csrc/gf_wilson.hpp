@@ -16,7 +16,7 @@
 //                    temporal link is read once)
 //   k_wcorr_xy_fwd   forward (x, y) transform of one z plane of one element
 //   k_wcorr_z        per column chunk: forward z transforms of the nine
-//                    elements, S accumulated in registers, inverse z transform of S
+//                    elements together, S summed over them, inverse z transform of S
 //   k_wcorr_xy_inv   inverse (x, y) transform of S, Re * 1/(3 Vs^2) -> C(r)
 //   k_wcorr_shells   one wave per shell: members summed in a fixed order
 #pragma once
@@ -132,9 +132,9 @@ __global__ void __launch_bounds__(1024) k_wcorr_xy_fwd(cx<double>* __restrict__ 
     }
 }
 
-// Block b takes the bx consecutive in-plane positions q0 = b*bx .. q0+bx-1 for every z. For each of the
-// nine elements: forward z transform, then |.|^2 added to S (each thread keeps the same elements of
-// the chunk in registers). Then the inverse z transform of S, written to Sg.
+// Block b takes the bx consecutive in-plane positions q0 = b*bx .. q0+bx-1 for every z and all nine
+// elements at once (LDS element (f, b, z) at f*bx*nz + z*bx + b): forward z transforms of the 9*bx
+// columns, S = sum_f |.|^2 in a fixed order, then the inverse z transform of S, written to Sg.
 template <int EPT>
 __global__ void __launch_bounds__(1024) k_wcorr_z(const cx<double>* __restrict__ W, size_t wps, int plane, int nz,
                                                   int bx, FftPlan pz, const cx<double>* __restrict__ twgz,
@@ -142,38 +142,29 @@ __global__ void __launch_bounds__(1024) k_wcorr_z(const cx<double>* __restrict__
     extern __shared__ __align__(16) unsigned char smem[];
     cx<double>* twz = reinterpret_cast<cx<double>*>(smem);
     cx<double>* buf = twz + nz;
+    const int E = bx * nz;
+    cx<double>* sb = buf + 9 * E;
     const int nthr = blockDim.x;
     for (int i = threadIdx.x; i < nz; i += nthr) twz[i] = twgz[i];
     const int q0 = blockIdx.x * bx;
-    const int E = bx * nz;
-    double s[EPT];
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) s[k] = 0.0;
-    for (int f = 0; f < 9; ++f) {
-        const cx<double>* g = W + (size_t)f * wps + q0;
-        for (int e = threadIdx.x; e < E; e += nthr) {  // element (b, z) at z*bx + b
-            const int z = e / bx, b = e - z * bx;
-            buf[e] = g[(size_t)z * plane + b];
-        }
-        __syncthreads();
-        fft_rows<EPT, double, false>(buf, twz, pz, bx, bx, bx, 1, 0);
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-            const int e = threadIdx.x + k * nthr;
-            if (e < E) s[k] += norm2(buf[e]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-        const int e = threadIdx.x + k * nthr;
-        if (e < E) buf[e] = {s[k], 0.0};
+    for (int e = threadIdx.x; e < 9 * E; e += nthr) {
+        const int f = e / E, r = e - f * E;
+        const int z = r / bx, b = r - z * bx;
+        buf[e] = W[(size_t)f * wps + (size_t)z * plane + q0 + b];
     }
     __syncthreads();
-    fft_rows<EPT, double, true>(buf, twz, pz, bx, bx, bx, 1, 0);
+    fft_rows<EPT, double, false>(buf, twz, pz, bx, 9 * bx, bx, 1, E);
+    for (int e = threadIdx.x; e < E; e += nthr) {
+        double s = 0.0;
+#pragma unroll
+        for (int f = 0; f < 9; ++f) s += norm2(buf[f * E + e]);
+        sb[e] = {s, 0.0};
+    }
+    __syncthreads();
+    fft_rows<EPT, double, true>(sb, twz, pz, bx, bx, bx, 1, 0);
     for (int e = threadIdx.x; e < E; e += nthr) {
         const int z = e / bx, b = e - z * bx;
-        Sg[(size_t)z * plane + q0 + b] = buf[e];
+        Sg[(size_t)z * plane + q0 + b] = sb[e];
     }
 }
 

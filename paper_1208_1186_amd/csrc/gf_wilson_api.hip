@@ -43,7 +43,7 @@ struct gf_wilson {
 
 namespace {
 
-constexpr int kWEpt = 8;  // FFT elements per thread per stage
+constexpr int kWEpt = 4;  // FFT elements per thread per stage (small blocks of short work: more waves)
 constexpr int kWMaxExtent = 64;
 constexpr size_t kWAlign = 256;
 
@@ -226,7 +226,14 @@ gf_status gf_wilson_create(gf_wilson** out, const int32_t* dims, void* d_workspa
     w->off = reinterpret_cast<int*>(ws + L.off_off);
     w->members = reinterpret_cast<int*>(ws + L.off_mem);
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2], nt = L.n[3];
-    w->chunks = nt % 8 == 0 ? 8 : (nt % 4 == 0 ? 4 : 2);
+    // t chunks per site: as many as divide Nt while each chunk keeps two links or more (one in flight
+    // while the other is multiplied), at most 8
+    w->chunks = 2;
+    for (int c : {8, 4})
+        if (nt % c == 0 && nt / c >= 2) {
+            w->chunks = c;
+            break;
+        }
     w->px = w_plan(nx);
     w->py = w_plan(ny);
     w->pz = w_plan(nz);
@@ -234,9 +241,10 @@ gf_status gf_wilson_create(gf_wilson** out, const int32_t* dims, void* d_workspa
     w->thr_xy = std::min(1024, std::max(64, wround64((nx * ny + kWEpt - 1) / kWEpt)));
     w->lds_xy = (size_t)(nx + ny + (size_t)w->rs * ny) * sizeof(cx<double>);
     const int plane = nx * ny;
-    w->bx = plane % 16 == 0 ? 16 : (plane % 8 == 0 ? 8 : 4);
-    w->thr_z = std::min(1024, std::max(64, wround64((w->bx * nz + kWEpt - 1) / kWEpt)));
-    w->lds_z = (size_t)(nz + (size_t)w->bx * nz) * sizeof(cx<double>);
+    w->bx = 4;  // 64-byte runs per z row; the plane (both extents even) always divides
+    (void)plane;
+    w->thr_z = std::min(1024, std::max(64, wround64((9 * w->bx * nz + kWEpt - 1) / kWEpt)));
+    w->lds_z = (size_t)(nz + (size_t)10 * w->bx * nz) * sizeof(cx<double>);
     // host tables: twiddles, shells (ordered by r^2, members by site index)
     const long double pi = 3.14159265358979323846264338327950288L;
     std::vector<cx<double>> tw[3];

@@ -39,11 +39,11 @@ def _run(dims, u, lines=True):
 
 
 @pytest.mark.parametrize("dims,seed", [
-    ((4, 4, 6, 4), 1),     # Nt = 4: four chunks of one link
-    ((8, 8, 8, 8), 2),     # eight chunks of one link
+    ((4, 4, 6, 4), 1),     # Nt = 4: two t chunks of two links
+    ((8, 8, 8, 8), 2),     # four chunks of two links
     ((6, 4, 12, 6), 3),    # Nt = 6: two chunks of three; radix-3 z transform
-    ((12, 8, 6, 4), 4),    # radix 3 along x, in-plane chunks of 16
-    ((6, 6, 4, 2), 5),     # Nt = 2; plane of 36 (chunks of 4)
+    ((12, 8, 6, 4), 4),    # radix 3 along x
+    ((6, 6, 4, 2), 5),     # Nt = 2: two chunks of one link; plane of 36
     ((8, 12, 6, 16), 6),   # Nt = 16: eight chunks of two links
 ])
 def test_matches_oracle_elementwise(dims, seed):
