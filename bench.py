@@ -326,6 +326,28 @@ def cpu_baseline(u, budget_s=12.0):
     return n / dt, n, dt, workers
 
 
+def cpu_baseline_wilson(u, nsep=64):
+    """The oracle's correlator on the same 32^4 input: its Wilson lines, then nsep separations by the
+    definition (one periodic shift each); the full table's time is Vs times the per-separation time."""
+    import numpy as np
+    from oracle import observables
+    t0 = time.perf_counter()
+    w = observables.wilson_lines(u)
+    t_lines = time.perf_counter() - t0
+    nz, ny, nx = w.shape[:3]
+    rng = np.random.default_rng(0)
+    t0 = time.perf_counter()
+    for _ in range(nsep):
+        observables.singlet_at(w, (int(rng.integers(nx)), int(rng.integers(ny)), int(rng.integers(nz))))
+    t_sep = (time.perf_counter() - t0) / nsep
+    vs = nx * ny * nz
+    total = t_lines + vs * t_sep
+    return {"value": round(1.0 / total, 8), "unit": "correlators/s", "cores": 1, "kind": "oracle",
+            "sample": f"Wilson lines of {nx}x{ny}x{nz}x{u.shape[0]} ({t_lines:.2f}s) + {nsep} separations by the "
+                      f"definition ({t_sep * 1e3:.1f} ms each), full table extrapolated to {vs} separations: "
+                      f"{total:.0f}s"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -456,6 +478,9 @@ def main():
                "sample": f"first {cn} FA iterations of {nx}x{ny}x{nz}x{nt} seed 0 (FP64 NumPy, scipy.fft "
                          f"workers={workers}), {cdt:.1f}s"}
         log(f"oracle: {crate:.3f} it/s over {cn} iterations")
+        if not args.no_extras and not args.no_wilson:
+            extras["wilson_cpu_baseline"] = cpu_baseline_wilson(u)
+            log(f"oracle correlator: {extras['wilson_cpu_baseline']['sample']}")
 
     out = {
         "metric": METRIC,
