@@ -145,6 +145,11 @@ def staple_sum(u, mu):
     return a
 
 
+def overrelax_element(v):
+    """The over-relaxation multiplier V^2 of a pair with projection V."""
+    return v @ v
+
+
 def cm_update(ulink, staple, beta, draw_pair, overrelax):
     """One Cabibbo-Marinari update of links ulink (..., 3, 3) with staple sums (..., 3, 3).
     draw_pair(p) returns the draw(call) function of pair p. Returns the new links and how many pairs
@@ -158,7 +163,7 @@ def cm_update(ulink, staple, beta, draw_pair, overrelax):
         ks = np.where(live, k, 1.0)
         v = su2_from_quaternion(r / ks[..., None])
         if overrelax:
-            s = v @ v
+            s = overrelax_element(v)
         else:
             draw = draw_pair(p)
             x0, ok = kp_sample(2.0 * beta * ks / 3.0, draw)
@@ -189,13 +194,14 @@ def _link_index(dims, mu):
     return s * np.uint64(4) + np.uint64(mu)
 
 
-def update(u, beta, seed, sweep, n_or=0):
-    """One heatbath sweep (random numbers of sweep `sweep`), then n_or over-relaxation sweeps, then every
-    link reunitarised. Returns (new links, number of rejected pair updates)."""
+def update(u, beta, seed, sweep, n_or=0, heatbath=True, reunit=True):
+    """One heatbath sweep (random numbers of sweep `sweep`; skipped if not heatbath), then n_or
+    over-relaxation sweeps, then (if reunit) every link reunitarised. Returns (new links, number of
+    rejected pair updates)."""
     dims = (u.shape[3], u.shape[2], u.shape[1], u.shape[0])
     u = u.copy()
     rejected = 0
-    for rep in range(1 + n_or):
+    for rep in range(0 if heatbath else 1, 1 + n_or):
         overrelax = rep > 0
         for mu in range(4):
             lid = _link_index(dims, mu)
@@ -214,7 +220,7 @@ def update(u, beta, seed, sweep, n_or=0):
                 um = u[..., mu, :, :]
                 um[mask] = new
                 u[..., mu, :, :] = um
-    return reunitarize(u), rejected
+    return (reunitarize(u) if reunit else u), rejected
 
 
 def multihit(u, beta, seed, tag, n_hits):

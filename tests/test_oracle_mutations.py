@@ -207,3 +207,75 @@ def test_correlator_pins_catch_mutation(label, monkeypatch):
         except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError):
             failed += 1
     assert failed >= 1, f"no pin caught: {label}"
+
+
+# ------------------------------------------------------------ Monte Carlo generator
+from oracle import mc  # noqa: E402
+import test_oracle_mc as mpins  # noqa: E402
+
+_ORIG_KP = mc.kp_sample
+
+
+def _kp_half_alpha(alpha, draw):
+    return _ORIG_KP(np.asarray(alpha) / 2.0, draw)
+
+
+def _kp_no_gaussian_term(alpha, draw):
+    alpha = np.asarray(alpha, dtype=np.float64)
+    x0 = np.ones_like(alpha)
+    done = np.zeros(alpha.shape, dtype=bool)
+    for j in range(1, mc.MAX_ATTEMPTS + 1):
+        u1, u2 = draw(2 * j - 1)
+        u3, u4 = draw(2 * j)
+        delta = -np.log(u1) / alpha
+        ok = (~done) & (u4 * u4 <= 1.0 - 0.5 * delta)
+        x0 = np.where(ok, 1.0 - delta, x0)
+        done |= ok
+    return x0, done
+
+
+def _or_first_power(v):
+    return v
+
+
+def _staple_up_only(u, mu):
+    a = np.zeros(u.shape[:4] + (3, 3), dtype=np.complex128)
+    um = u[..., mu, :, :]
+    for nu in range(4):
+        if nu != mu:
+            un = u[..., nu, :, :]
+            a += landau.shift(un, mu, 1) @ su3.dag(landau.shift(um, nu, 1)) @ su3.dag(un)
+    return 2.0 * a
+
+
+MC_MUTATIONS = {
+    "heatbath exponent beta k/3 instead of 2 beta k/3": ("kp_sample", _kp_half_alpha),
+    "Kennedy-Pendleton without the Gaussian term": ("kp_sample", _kp_no_gaussian_term),
+    "over-relaxation by V instead of V^2": ("overrelax_element", _or_first_power),
+    "staple without the backward plaquettes": ("staple_sum", _staple_up_only),
+}
+
+# cheap pins first: a mutation needs to fail only one
+MC_PINS = [
+    lambda: mpins.test_staples_count_each_plaquette_four_times(),
+    lambda: mpins.test_overrelaxation_keeps_the_action(),
+    lambda: [mpins.test_kennedy_pendleton_moments(a) for a in (0.8, 3.0, 12.0)],
+    lambda: mpins.test_heatbath_distribution_weak_coupling(),
+    lambda: mpins.test_heatbath_distribution_strong_coupling(),
+    lambda: mpins.test_weak_coupling_plaquette(),
+]
+
+
+@pytest.mark.parametrize("label", sorted(MC_MUTATIONS))
+def test_mc_pins_catch_mutation(label, monkeypatch):
+    name, fn = MC_MUTATIONS[label]
+    monkeypatch.setattr(mc, name, fn)
+    caught = False
+    for pin in MC_PINS:
+        try:
+            with np.errstate(all="ignore"):
+                pin()
+        except (AssertionError, FloatingPointError, ValueError, ZeroDivisionError):
+            caught = True
+            break
+    assert caught, f"no pin caught: {label}"
