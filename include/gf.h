@@ -386,6 +386,65 @@ const char* gf_wilson_last_error(const gf_wilson* w);
 /* Free the handle (synchronises its stream first). */
 void gf_wilson_destroy(gf_wilson* w);
 
+/* ------------------------------------------------------------------------
+ * Monte Carlo input generator. The paper gauge-fixes thermalised SU(3)
+ * configurations (Section 3: 32^4 at beta = 5.8, 6.0, 6.2) and applies
+ * multi-hit to the temporal links before fixing (Section 1), without
+ * stating either algorithm; these are the standard ones:
+ *   Wilson action S = beta sum_p (1 - (1/3) Re Tr U_p); the link U_mu(x) has
+ *   local weight exp((beta/3) Re Tr(U A)), A the sum of its six staples.
+ *   Heatbath: Cabibbo-Marinari over the SU(2) subgroups of rows (0,1), (0,2),
+ *   (1,2), each drawn by Kennedy-Pendleton. Over-relaxation: the SU(2)
+ *   reflection that keeps Re Tr(U A). A sweep updates the 4 directions, even
+ *   sites then odd, and reunitarises every link at the end.
+ *   Multi-hit: with all other links fixed, the average of n successive
+ *   heatbath updates of each temporal link (not reunitarised).
+ * Random numbers are Philox4x32-10 (Salmon et al., SC11) keyed by the seed,
+ * with counters (link index 4s + mu, sweep or tag, hit/pair/draw, purpose),
+ * so results depend only on (seed, sweep/tag) and not on the launch shape.
+ * Links are canonical (see gf_init), updated in place. Every extent even and
+ * in [2, 256]; at most 2^32 links. Double precision throughout.
+ * ---------------------------------------------------------------------- */
+typedef struct gf_mc gf_mc;
+
+/* Device workspace bytes for these dims (0 if invalid). */
+size_t gf_mc_workspace_bytes(const int32_t dims[4]);
+
+/*
+ * Create a generator handle: beta > 0 and finite, any 64-bit seed, workspace
+ * >= gf_mc_workspace_bytes and 256-byte aligned (caller-owned, kept for the
+ * handle's life), stream a hipStream_t (NULL = default). Queues nothing.
+ * GF_EINVAL / GF_ENOTSUP: nothing created (gf_mc_last_error(NULL)).
+ */
+gf_status gf_mc_create(gf_mc** out, const int32_t dims[4], double beta, uint64_t seed, void* d_workspace,
+                       size_t workspace_bytes, void* stream);
+
+/*
+ * One heatbath sweep with the random numbers of `sweep` (< 2^32), then
+ * n_overrelax (0..64) over-relaxation sweeps, then every link reunitarised,
+ * in place on d_links. If h_rejected is not NULL the stream is synchronised
+ * and it receives the number of SU(2) pair updates that kept their old value
+ * because 64 Kennedy-Pendleton attempts were all rejected (0 in practice at
+ * beta >~ 1). Otherwise nothing is synchronised.
+ */
+gf_status gf_mc_update(gf_mc* m, double* d_links, uint64_t sweep, int32_t n_overrelax, int64_t* h_rejected);
+
+/*
+ * Multi-hit average of every temporal link with the random numbers of `tag`
+ * (< 2^32) and n_hits (1..4095) hits: d_out is complex double [s][row][col]
+ * (V x 9, caller-owned); d_links is only read. Queued, not synchronised.
+ */
+gf_status gf_mc_multihit(gf_mc* m, const double* d_links, uint64_t tag, int32_t n_hits, double* d_out);
+
+/* Mean plaquette (1/(18V)) sum Re Tr U_p of canonical links, fixed-order FP64 sum; synchronises. */
+gf_status gf_mc_plaquette(gf_mc* m, const double* d_links, double* h_plaquette);
+
+/* Message of the last error on this handle (or of the last failed create if m is NULL). */
+const char* gf_mc_last_error(const gf_mc* m);
+
+/* Free the handle (synchronises its stream first). */
+void gf_mc_destroy(gf_mc* m);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgf.so")
-SOURCES = ["gf_api.hip", "gf_wilson_api.hip"]
-HEADERS = ["gf_device.hpp", "gf_fft.hpp", "gf_fft_ct.hpp", "gf_kernels.hpp", "gf_learn.hpp", "gf_wilson.hpp"]
+SOURCES = ["gf_api.hip", "gf_wilson_api.hip", "gf_mc_api.hip"]
+HEADERS = ["gf_device.hpp", "gf_fft.hpp", "gf_fft_ct.hpp", "gf_kernels.hpp", "gf_learn.hpp", "gf_wilson.hpp", "gf_mc.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -94,6 +94,13 @@ def _signatures(lib):
         "gf_wilson_correlator": (i32, [_P, _P, _P, _P, _P]),
         "gf_wilson_last_error": (ctypes.c_char_p, [_P]),
         "gf_wilson_destroy": (None, [_P]),
+        "gf_mc_workspace_bytes": (sz, [ctypes.POINTER(i32)]),
+        "gf_mc_create": (i32, [ctypes.POINTER(_P), ctypes.POINTER(i32), dbl, ctypes.c_uint64, _P, sz, _P]),
+        "gf_mc_update": (i32, [_P, _P, ctypes.c_uint64, i32, ctypes.POINTER(i64)]),
+        "gf_mc_multihit": (i32, [_P, _P, ctypes.c_uint64, i32, _P]),
+        "gf_mc_plaquette": (i32, [_P, _P, pd]),
+        "gf_mc_last_error": (ctypes.c_char_p, [_P]),
+        "gf_mc_destroy": (None, [_P]),
         "gf_last_error": (ctypes.c_char_p, [_P]),
         "gf_destroy": (None, [_P]),
     }
@@ -598,6 +605,68 @@ class WilsonCorrelator:
         if getattr(self, "w", None):
             load().gf_wilson_destroy(self.w)
             self.w = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------ Monte Carlo input generator
+
+def gf_mc_last_error(m):
+    msg = load().gf_mc_last_error(m)
+    return msg.decode() if msg else ""
+
+
+class MonteCarlo:
+    """SU(3) Wilson-action heatbath / over-relaxation / multi-hit on complex128 CUDA links
+    (Nt, Nz, Ny, Nx, 4, 3, 3), updated in place."""
+
+    def __init__(self, dims, beta, seed, device="cuda:0", stream=None):
+        import torch
+        self.dims = tuple(int(d) for d in dims)
+        lib = load()
+        nbytes = lib.gf_mc_workspace_bytes(_dims4(self.dims))
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        self.workspace = torch.empty(max(nbytes, 1) + 256, dtype=torch.uint8, device=device)
+        base = self.workspace.data_ptr()
+        m = _P()
+        st = lib.gf_mc_create(ctypes.byref(m), _dims4(self.dims), float(beta), int(seed) & ((1 << 64) - 1),
+                              _P(base + (-base) % 256 if nbytes else None), nbytes, _P(self.stream.cuda_stream))
+        if st != GF_OK:
+            raise GfError(st, gf_mc_last_error(None))
+        self.m = m
+
+    def _check(self, st):
+        if st != GF_OK:
+            raise GfError(st, gf_mc_last_error(self.m))
+
+    def update(self, links, sweep, n_overrelax=0, count_rejected=False):
+        """One heatbath sweep + n_overrelax over-relaxation sweeps; returns the rejected-pair count if asked."""
+        rej = ctypes.c_int64(0)
+        self._check(load().gf_mc_update(self.m, _P(links.data_ptr()), int(sweep), int(n_overrelax),
+                                        ctypes.byref(rej) if count_rejected else None))
+        return rej.value if count_rejected else None
+
+    def multihit(self, links, tag, n_hits, out=None):
+        import torch
+        if out is None:
+            nx, ny, nz, nt = self.dims
+            out = torch.empty((nt, nz, ny, nx, 3, 3), dtype=torch.complex128, device=links.device)
+        self._check(load().gf_mc_multihit(self.m, _P(links.data_ptr()), int(tag), int(n_hits), _P(out.data_ptr())))
+        return out
+
+    def plaquette(self, links):
+        v = ctypes.c_double(0.0)
+        self._check(load().gf_mc_plaquette(self.m, _P(links.data_ptr()), ctypes.byref(v)))
+        return v.value
+
+    def close(self):
+        if getattr(self, "m", None):
+            load().gf_mc_destroy(self.m)
+            self.m = None
 
     def __del__(self):
         try:

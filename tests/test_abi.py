@@ -159,3 +159,48 @@ def test_wilson_workspace_and_null_handle(lib):
     assert lib.gf_wilson_shells(None, None, None) == gf.GF_EINVAL
     assert lib.gf_wilson_correlator(None, None, None, None, None) == gf.GF_EINVAL
     lib.gf_wilson_destroy(None)
+
+
+@pytest.mark.parametrize("dims,beta,status", [
+    ((8, 8, 8, 5), 6.0, gf.GF_EINVAL),     # odd extent: no even/odd split
+    ((8, 8, 0, 8), 6.0, gf.GF_EINVAL),
+    ((512, 8, 8, 8), 6.0, gf.GF_ENOTSUP),
+    ((8, 8, 8, 8), 0.0, gf.GF_EINVAL),
+    ((8, 8, 8, 8), float("nan"), gf.GF_EINVAL),
+])
+def test_mc_bad_parameters_rejected_before_device(lib, dims, beta, status):
+    m = gf._P()
+    nb = lib.gf_mc_workspace_bytes(gf._dims4(dims))
+    st = lib.gf_mc_create(ctypes.byref(m), gf._dims4(dims), beta, 1, ctypes.c_void_p(256), 1 << 40, None)
+    assert st == status and not m.value
+    assert lib.gf_mc_last_error(None)
+    if beta == 6.0:
+        assert nb == 0  # the shape alone is invalid
+
+
+def test_mc_null_handle_and_workspace(lib):
+    nb = lib.gf_mc_workspace_bytes(gf._dims4((8, 8, 8, 8)))
+    assert nb > 0
+    m = gf._P()
+    assert lib.gf_mc_create(ctypes.byref(m), gf._dims4((8, 8, 8, 8)), 6.0, 1, None, nb, None) == gf.GF_EINVAL
+    assert lib.gf_mc_create(ctypes.byref(m), gf._dims4((8, 8, 8, 8)), 6.0, 1, ctypes.c_void_p(256), nb - 1,
+                            None) == gf.GF_EINVAL
+    assert lib.gf_mc_update(None, None, 0, 0, None) == gf.GF_EINVAL
+    assert lib.gf_mc_multihit(None, None, 0, 1, None) == gf.GF_EINVAL
+    assert lib.gf_mc_plaquette(None, None, None) == gf.GF_EINVAL
+    lib.gf_mc_destroy(None)
+
+
+def test_binding_argument_counts_match_header(lib):
+    """Every ctypes signature in the binding takes as many arguments as the header declares."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", open(gf.HEADER).read(), flags=re.S)
+    seen = 0
+    for m in re.finditer(r"\b(gf_[a-z_]+)\s*\(([^;]*?)\)\s*;", text):
+        name, args = m.group(1), m.group(2).strip()
+        n = 0 if args in ("", "void") else args.count(",") + 1
+        fn = getattr(lib, name)
+        assert fn.argtypes is not None, name
+        assert len(fn.argtypes) == n, (name, len(fn.argtypes), n)
+        seen += 1
+    assert seen == len(gf.header_functions())
