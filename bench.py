@@ -307,6 +307,62 @@ def wilson_workload(gf, torch, synth, dev, reps=50):
     return out
 
 
+def pipeline_workload(gf, torch, dev, dims=(32, 32, 32, 32), beta=6.0, n_therm=100, n_or=4, n_hits=8):
+    """The paper's pipeline on a thermalised field: heatbath + over-relaxation from a cold start at
+    beta = 6.0, Landau gauge fixing to theta < 1e-15, multi-hit temporal links, singlet correlator."""
+    import numpy as np
+    nx, ny, nz, nt = dims
+    links = torch.zeros((nt, nz, ny, nx, 4, 3, 3), dtype=torch.complex128, device=dev)
+    links[..., 0, 0] = 1
+    links[..., 1, 1] = 1
+    links[..., 2, 2] = 1
+    m = gf.MonteCarlo(dims, beta, 2012)
+    log(f"pipeline: thermalising {nx}x{ny}x{nz}x{nt} at beta {beta}: {n_therm} x (heatbath + {n_or} OR)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rej = 0
+    for sweep in range(n_therm):
+        r = m.update(links, sweep, n_or, count_rejected=(sweep == n_therm - 1))
+        rej += r or 0
+    torch.cuda.synchronize()
+    t_therm = time.perf_counter() - t0
+    plaq = m.plaquette(links)
+    out = {"lattice": list(dims), "beta": beta, "sweeps": n_therm, "overrelax_per_sweep": n_or,
+           "sweep_ms": round(t_therm / n_therm * 1e3, 3), "plaquette": round(plaq, 6),
+           "rejected_pairs_last_sweep": int(rej)}
+    log(f"pipeline: {t_therm / n_therm * 1e3:.2f} ms per sweep, plaquette {plaq:.5f}")
+    for prec in ["fp64_18", "mixed"]:
+        lk = links.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fx = gf.GaugeFixer(lk, prec, check_every=10)
+        r = fx.fix_until(1e-15, 100000)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fx.close()
+        out[f"fix_{prec}"] = {"iters": int(r.iters), "theta": r.theta, "F": r.F, "s": round(dt, 4)}
+        log(f"pipeline: {prec} fix {r.iters} iterations, {dt:.3f}s, F {r.F:.6f}")
+        if prec == "fp64_18":
+            fixed = lk
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ubar = m.multihit(fixed, 0, n_hits)
+    torch.cuda.synchronize()
+    t_mh = time.perf_counter() - t0
+    wc = gf.WilsonCorrelator(dims)
+    _, corr, shell = wc(ubar)
+    _, corr0, shell0 = wc(fixed)
+    torch.cuda.synchronize()
+    sh, sh0 = shell.cpu().numpy(), shell0.cpu().numpy()
+    out["multihit"] = {"hits": n_hits, "ms": round(t_mh * 1e3, 3)}
+    out["singlet_C_r2_0_to_4"] = {"multihit": [float(f"{v:.4e}") for v in sh[:5]],
+                                  "plain": [float(f"{v:.4e}") for v in sh0[:5]], "r2": wc.r2[:5]}
+    wc.close()
+    m.close()
+    del links, fixed, ubar
+    return out
+
+
 def cpu_baseline(u, budget_s=12.0):
     """The FP64 NumPy oracle's FA iterations on the same input, on the host cores."""
     from oracle import landau
@@ -361,6 +417,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-lattice uneven batch workload")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner workload")
     ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-line correlator workload")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="skip the thermalise / fix / multi-hit / correlator pipeline at beta 6.0")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -469,6 +527,8 @@ def main():
         extras["learned_preconditioner"] = learned_workload(gf, torch, synth)
     if not args.no_extras and not args.no_wilson:
         extras["wilson_singlet_correlator"] = wilson_workload(gf, torch, synth, dev)
+    if not args.no_extras and not args.no_pipeline:
+        extras["thermalised_pipeline"] = pipeline_workload(gf, torch, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

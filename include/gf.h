@@ -60,7 +60,9 @@ typedef enum {
     GF_FP64_12 = 1,   /* double, rows 1-2, row 3 rebuilt on every read */
     GF_FP32_12 = 2,   /* float, rows 1-2 (re-orthonormalised on write) */
     GF_FP32_18 = 3,   /* float, full matrix */
-    GF_MIXED = 4      /* FP32-12 until theta < switch_theta, then FP64-18 */
+    GF_MIXED = 4      /* FP32-12 until theta < switch_theta, then FP64-18; the hand-over comes
+                         earlier if the float descent stalls: no new minimum of theta for 200
+                         updates while theta < 1e-6, or for 2000 at any theta */
 } gf_precision;
 
 enum {
@@ -379,6 +381,14 @@ gf_status gf_wilson_shells(const gf_wilson* w, int32_t* h_r2, int32_t* h_count);
  */
 gf_status gf_wilson_correlator(gf_wilson* w, const double* d_links, double* d_lines, double* d_corr,
                                double* d_shell);
+
+/*
+ * The same from a field of temporal links alone, complex double [s][row][col]
+ * (V x 9), e.g. the multi-hit averages of gf_mc_multihit (which need not be
+ * unitary): W(x) is the ordered product of these matrices along t.
+ */
+gf_status gf_wilson_correlator_temporal(gf_wilson* w, const double* d_temporal, double* d_lines, double* d_corr,
+                                        double* d_shell);
 
 /* Message of the last error on this handle (or of the last failed create if w is NULL). */
 const char* gf_wilson_last_error(const gf_wilson* w);

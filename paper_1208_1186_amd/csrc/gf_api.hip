@@ -1040,8 +1040,29 @@ gf_ctx* active(gf_ctx* c) { return c->L.mixed ? c->child[c->phase] : c; }
 // GF_MIXED: float iterations (accumulating G) until theta < max(switch_theta,
 // tol) or the float descent stalls, then U64 = G U0 G(x+mu)^dag in double and
 // double iterations. tol < 0 means "apply max_iter updates" (gf_iterate).
-constexpr double kStallTheta = 1e-5;   // below this, a batch that does not cut theta by 5% has stalled
-constexpr double kStallRatio = 0.95;
+// The float descent has stalled (its rounding floor is above the switch point) when theta has gone
+// kStallIters updates without a new minimum while below kStallTheta, or kStallItersAny at any theta.
+// theta is not monotone under steepest descent (F is): on thermalised fields it climbs back by two or
+// three decades for some hundred updates before falling again, so a shorter window, or the drop over
+// one check interval, hands over to double precision long before float has done its share.
+constexpr double kStallTheta = 1e-6;
+constexpr long long kStallIters = 200;
+constexpr long long kStallItersAny = 2000;
+
+struct StallTracker {
+    double best = INFINITY;
+    long long since = 0;  // updates since the last new minimum
+    // theta after n more updates; true once the descent has stalled
+    bool step(double theta, long long n) {
+        if (theta < best) {
+            best = theta;
+            since = 0;
+        } else {
+            since += n;
+        }
+        return (theta < kStallTheta && since >= kStallIters) || since >= kStallItersAny;
+    }
+};
 
 gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1051,7 +1072,8 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     gf_status s = GF_OK;
     if (c->phase == 0) {
         const double sw = std::max(c->p.switch_theta, tol);
-        double last = a->h_head->theta;
+        StallTracker tracker;
+        tracker.best = a->h_head->theta;
         bool stalled = false;
         while (left > 0 && !stalled) {
             const long long before = a->h_head->iters;
@@ -1059,9 +1081,7 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
             if (s != GF_OK) return fail(c, s, a->err);
             left -= a->h_head->iters - before;
             if (a->h_head->done) break;
-            const double th = a->h_head->theta;
-            stalled = th < kStallTheta && th > kStallRatio * last;
-            last = th;
+            stalled = tracker.step(a->h_head->theta, a->h_head->iters - before);
         }
         if (a->h_head->numeric) return fail(c, GF_ENUMERIC, "theta is not finite");
         const bool reached = a->h_head->theta < sw;
@@ -1194,9 +1214,9 @@ struct BatchGroup {
     int64_t n_it = 0;  // updates in the chunk being read back
     bool waiting = false;
     std::vector<int> act;
-    std::vector<double> last;
     std::vector<long long> it0;
     std::vector<char> stalled;
+    std::vector<StallTracker> tracker;  // float phase of GF_MIXED, as in the single-lattice path
 };
 
 struct BatchState {
@@ -1454,10 +1474,10 @@ gf_status absorb_group(gf_ctx* c, BatchGroup& g, std::vector<BatchOutcome>& out)
     const int ng = (int)g.idx.size();
     if (g.stage == BatchGroup::kStart) {
         g.act.clear();
-        g.last.assign(ng, 0.0);
+        g.tracker.assign(ng, StallTracker{});
         for (int i = 0; i < ng; ++i) {
             const Ctl* h = g.view[g.ph][i]->h_head;
-            g.last[i] = h->theta;
+            g.tracker[i].best = h->theta;
             if (!out[g.idx[i]].finished && !h->done) g.act.push_back(i);
         }
         g.k = 0;  // every configuration of a phase starts from its own count 0
@@ -1473,9 +1493,7 @@ gf_status absorb_group(gf_ctx* c, BatchGroup& g, std::vector<BatchOutcome>& out)
         if (h->done || h->numeric) continue;
         if (h->iters != g.k) return fail(c, GF_EDEVICE, "batch configurations fell out of step");
         if (g.nphase == 2 && g.ph == 0) {
-            const double th = h->theta;
-            g.stalled[i] = th < kStallTheta && th > kStallRatio * g.last[i];
-            g.last[i] = th;
+            g.stalled[i] = g.tracker[i].step(h->theta, g.n_it);
             if (g.stalled[i]) continue;
         }
         next.push_back(i);

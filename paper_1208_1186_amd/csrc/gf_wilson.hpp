@@ -27,8 +27,11 @@ namespace gf {
 
 constexpr int kWlSites = 64;  // spatial sites per k_wilson_lines block (one per lane)
 
+// The temporal link of a site: at site*36 + 27 in canonical links ([site][mu][row][col], mu = 3), or
+// at site*9 in a field of temporal links alone ([site][row][col]).
+template <int STRIDE>
 __device__ __forceinline__ su3<double> load_temporal(const double2* __restrict__ canon, size_t site) {
-    const double2* p = canon + (site * 4 + 3) * 9;  // canonical [site][mu][row][col], mu = 3
+    const double2* p = canon + site * STRIDE + (STRIDE == 36 ? 27 : 0);
     su3<double> m;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -40,8 +43,9 @@ __device__ __forceinline__ su3<double> load_temporal(const double2* __restrict__
     return m;
 }
 
-// C chunks of nt / C consecutive t per spatial site; wave w of the block takes chunk w.
-template <int C>
+// C chunks of nt / C consecutive t per spatial site; wave w of the block takes chunk w. STRIDE: 36
+// for canonical links, 9 for a temporal-link field.
+template <int C, int STRIDE>
 __global__ void __launch_bounds__(64 * C) k_wilson_lines(const double2* __restrict__ canon, int vs, int nt,
                                                          cx<double>* __restrict__ W, size_t wps,
                                                          double2* __restrict__ lines) {
@@ -52,12 +56,12 @@ __global__ void __launch_bounds__(64 * C) k_wilson_lines(const double2* __restri
     const int len = nt / C, t0 = w * len;
     su3<double> acc;
     if (live) {
-        acc = load_temporal(canon, (size_t)xs + (size_t)vs * t0);
+        acc = load_temporal<STRIDE>(canon, (size_t)xs + (size_t)vs * t0);
         su3<double> nxt;
-        if (len > 1) nxt = load_temporal(canon, (size_t)xs + (size_t)vs * (t0 + 1));
+        if (len > 1) nxt = load_temporal<STRIDE>(canon, (size_t)xs + (size_t)vs * (t0 + 1));
         for (int t = t0 + 1; t < t0 + len; ++t) {
             const su3<double> cur = nxt;
-            if (t + 1 < t0 + len) nxt = load_temporal(canon, (size_t)xs + (size_t)vs * (t + 1));  // in flight
+            if (t + 1 < t0 + len) nxt = load_temporal<STRIDE>(canon, (size_t)xs + (size_t)vs * (t + 1));  // in flight
             acc = mul(acc, cur);
         }
     }

@@ -170,12 +170,25 @@ void raise_wilson_lds() {
     done = true;
 }
 
-template <int C>
+template <int C, int STRIDE>
 void launch_lines(gf_wilson* w, const double* links, double* lines) {
-    hipLaunchKernelGGL(k_wilson_lines<C>, dim3((w->vs + kWlSites - 1) / kWlSites), dim3(64 * C), 0, w->st,
+    hipLaunchKernelGGL((k_wilson_lines<C, STRIDE>), dim3((w->vs + kWlSites - 1) / kWlSites), dim3(64 * C), 0, w->st,
                        reinterpret_cast<const double2*>(links), w->vs, w->n[3], w->W, w->wps,
                        reinterpret_cast<double2*>(lines));
 }
+
+template <int STRIDE>
+void launch_lines_c(gf_wilson* w, const double* links, double* lines) {
+    if (w->chunks == 8)
+        launch_lines<8, STRIDE>(w, links, lines);
+    else if (w->chunks == 4)
+        launch_lines<4, STRIDE>(w, links, lines);
+    else
+        launch_lines<2, STRIDE>(w, links, lines);
+}
+
+gf_status correlator(gf_wilson* w, const double* d_links, bool temporal_only, double* d_lines, double* d_corr,
+                     double* d_shell);
 
 }  // namespace
 
@@ -311,14 +324,28 @@ gf_status gf_wilson_correlator(gf_wilson* w, const double* d_links, double* d_li
                                double* d_shell) {
     if (!w) return GF_EINVAL;
     if (!d_links) return wfail(w, GF_EINVAL, "d_links is NULL");
+    return correlator(w, d_links, false, d_lines, d_corr, d_shell);
+}
+
+gf_status gf_wilson_correlator_temporal(gf_wilson* w, const double* d_temporal, double* d_lines, double* d_corr,
+                                        double* d_shell) {
+    if (!w) return GF_EINVAL;
+    if (!d_temporal) return wfail(w, GF_EINVAL, "d_temporal is NULL");
+    return correlator(w, d_temporal, true, d_lines, d_corr, d_shell);
+}
+
+}  // extern "C"
+
+namespace {
+
+gf_status correlator(gf_wilson* w, const double* d_links, bool temporal_only, double* d_lines, double* d_corr,
+                     double* d_shell) {
     const int nx = w->n[0], ny = w->n[1], nz = w->n[2];
     double* corr = d_corr ? d_corr : w->corr;
-    if (w->chunks == 8)
-        launch_lines<8>(w, d_links, d_lines);
-    else if (w->chunks == 4)
-        launch_lines<4>(w, d_links, d_lines);
+    if (temporal_only)
+        launch_lines_c<9>(w, d_links, d_lines);
     else
-        launch_lines<2>(w, d_links, d_lines);
+        launch_lines_c<36>(w, d_links, d_lines);
     gf_status s = wcheck(w, hipGetLastError(), "wilson lines launch");
     if (s != GF_OK) return s;
     hipLaunchKernelGGL(k_wcorr_xy_fwd<kWEpt>, dim3(nz, 9), dim3(w->thr_xy), w->lds_xy, w->st, w->W, w->wps, nx, ny,
@@ -338,6 +365,10 @@ gf_status gf_wilson_correlator(gf_wilson* w, const double* d_links, double* d_li
     }
     return GF_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 const char* gf_wilson_last_error(const gf_wilson* w) { return w ? w->err.c_str() : g_wilson_error.c_str(); }
 

@@ -92,6 +92,7 @@ def _signatures(lib):
         "gf_wilson_shell_count": (i32, [_P]),
         "gf_wilson_shells": (i32, [_P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "gf_wilson_correlator": (i32, [_P, _P, _P, _P, _P]),
+        "gf_wilson_correlator_temporal": (i32, [_P, _P, _P, _P, _P]),
         "gf_wilson_last_error": (ctypes.c_char_p, [_P]),
         "gf_wilson_destroy": (None, [_P]),
         "gf_mc_workspace_bytes": (sz, [ctypes.POINTER(i32)]),
@@ -586,19 +587,25 @@ class WilsonCorrelator:
         self.r2, self.count = gf_wilson_shells(self.w)
 
     def __call__(self, links, lines=None, corr=None, shell=None):
-        """Queue the correlator; returns (lines, corr, shell) tensors (allocated when not given)."""
+        """Queue the correlator; returns (lines, corr, shell) tensors (allocated when not given). links are
+        canonical (Nt, Nz, Ny, Nx, 4, 3, 3) or temporal links alone (Nt, Nz, Ny, Nx, 3, 3)."""
         import torch
         nx, ny, nz, nt = self.dims
-        if tuple(links.shape) != (nt, nz, ny, nx, 4, 3, 3) or links.dtype != torch.complex128 \
+        temporal = tuple(links.shape) == (nt, nz, ny, nx, 3, 3)
+        if (not temporal and tuple(links.shape) != (nt, nz, ny, nx, 4, 3, 3)) or links.dtype != torch.complex128 \
                 or not links.is_contiguous():
-            raise ValueError("links must be a contiguous complex128 tensor of shape (Nt, Nz, Ny, Nx, 4, 3, 3)")
+            raise ValueError("links must be a contiguous complex128 tensor of shape (Nt, Nz, Ny, Nx, 4, 3, 3) "
+                             "or (Nt, Nz, Ny, Nx, 3, 3)")
         dev = links.device
         if corr is None:
             corr = torch.empty((nz, ny, nx), dtype=torch.float64, device=dev)
         if shell is None:
             shell = torch.empty(len(self.r2), dtype=torch.float64, device=dev)
-        gf_wilson_correlator(self.w, links.data_ptr(), lines.data_ptr() if lines is not None else 0,
-                             corr.data_ptr(), shell.data_ptr())
+        fn = load().gf_wilson_correlator_temporal if temporal else load().gf_wilson_correlator
+        st = fn(self.w, _P(links.data_ptr()), _P(lines.data_ptr() if lines is not None else None),
+                _P(corr.data_ptr()), _P(shell.data_ptr()))
+        if st != GF_OK:
+            raise GfError(st, gf_wilson_last_error(self.w))
         return lines, corr, shell
 
     def close(self):

@@ -138,3 +138,29 @@ def test_full_size_on_gauge_fixed_field(dims, eps):
     wr2, wcount, _ = observables.shell_average(np.zeros((nz, ny, nx)), dims[:3])
     assert list(wc.r2) == list(wr2) and list(wc.count) == list(wcount)
     wc.close()
+
+
+def test_temporal_field_entry():
+    """The temporal-field entry gives bitwise the canonical entry's results on the links' own temporal
+    matrices, and matches the oracle on non-unitary fields (multi-hit averages)."""
+    from oracle import mc
+    dims = (6, 4, 8, 4)
+    nx, ny, nz, nt = dims
+    u = synth.make_config(dims, 9)
+    links = torch.from_numpy(u).cuda()
+    wc = gf.WilsonCorrelator(dims)
+    _, c1, s1 = wc(links)
+    temporal = links[..., 3, :, :].contiguous()
+    _, c2, s2 = wc(temporal)
+    torch.cuda.synchronize()
+    assert torch.equal(c1, c2) and torch.equal(s1, s2)
+    ubar = mc.multihit(u, 6.0, 5, 0, 4)
+    _, c3, s3 = wc(torch.from_numpy(ubar).cuda())
+    torch.cuda.synchronize()
+    v = u.copy()
+    v[..., 3, :, :] = ubar
+    tab = observables.singlet_table(v)
+    assert np.max(np.abs(c3.cpu().numpy() - tab.real)) < TOL
+    _, _, wmean = observables.shell_average(tab, dims[:3])
+    assert np.max(np.abs(s3.cpu().numpy() - wmean)) < TOL
+    wc.close()
