@@ -78,17 +78,26 @@ def counted_traffic(prec, dims):
                            + vals["write_kib_per_dispatch"] * vals["write_scale"]))
 
 
-def copy_ceiling(torch, dev, mib=1024, reps=10):
-    """Device-to-device copy rate (read + write bytes per second) of a plain 1 GiB copy on this GPU."""
+def copy_ceiling(torch, dev, mib=1024, reps=10, gf=None):
+    """Device-to-device copy rate (read + write bytes per second) of a 1 GiB copy on this GPU: torch's copy,
+    or with gf the library's streaming copy kernel (16 B per lane, nontemporal)."""
     a = torch.ones(mib * (1 << 20) // 8, dtype=torch.float64, device=dev)
     b = torch.empty_like(a)
-    b.copy_(a)
+    st = torch.cuda.current_stream(dev)
+
+    def once():
+        if gf is None:
+            b.copy_(a)
+        else:
+            gf.load().gf_stream_copy(gf._P(a.data_ptr()), gf._P(b.data_ptr()), a.numel() * 8, gf._P(st.cuda_stream))
+
+    once()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    e0.record()
+    e0.record(st)
     for _ in range(reps):
-        b.copy_(a)
-    e1.record()
+        once()
+    e1.record(st)
     torch.cuda.synchronize()
     gbps = 2 * a.numel() * 8 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
@@ -307,7 +316,7 @@ def wilson_workload(gf, torch, synth, dev, reps=50):
     return out
 
 
-def pipeline_workload(gf, torch, dev, dims=(32, 32, 32, 32), beta=6.0, n_therm=100, n_or=4, n_hits=8):
+def pipeline_workload(gf, torch, dev, dims=(32, 32, 32, 32), beta=6.0, n_therm=100, n_or=4, n_hits=8, fix=True):
     """The paper's pipeline on a thermalised field: heatbath + over-relaxation from a cold start at
     beta = 6.0, Landau gauge fixing to theta < 1e-15, multi-hit temporal links, singlet correlator."""
     import numpy as np
@@ -320,17 +329,17 @@ def pipeline_workload(gf, torch, dev, dims=(32, 32, 32, 32), beta=6.0, n_therm=1
     log(f"pipeline: thermalising {nx}x{ny}x{nz}x{nt} at beta {beta}: {n_therm} x (heatbath + {n_or} OR)")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rej = 0
-    for sweep in range(n_therm):
-        r = m.update(links, sweep, n_or, count_rejected=(sweep == n_therm - 1))
-        rej += r or 0
+    rej = m.update(links, 0, n_or, count_rejected=True, n_sweeps=n_therm)
     torch.cuda.synchronize()
     t_therm = time.perf_counter() - t0
     plaq = m.plaquette(links)
     out = {"lattice": list(dims), "beta": beta, "sweeps": n_therm, "overrelax_per_sweep": n_or,
            "sweep_ms": round(t_therm / n_therm * 1e3, 3), "plaquette": round(plaq, 6),
-           "rejected_pairs_last_sweep": int(rej)}
+           "rejected_pairs": int(rej)}
     log(f"pipeline: {t_therm / n_therm * 1e3:.2f} ms per sweep, plaquette {plaq:.5f}")
+    if not fix:
+        m.close()
+        return out
     for prec in ["fp64_18", "mixed"]:
         lk = links.clone()
         torch.cuda.synchronize()
@@ -419,6 +428,8 @@ def main():
     ap.add_argument("--no-wilson", action="store_true", help="skip the Wilson-line correlator workload")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="skip the thermalise / fix / multi-hit / correlator pipeline at beta 6.0")
+    ap.add_argument("--pipeline-sweeps", type=int, default=100, help="thermalisation sweeps of the pipeline")
+    ap.add_argument("--pipeline-no-fix", action="store_true", help="pipeline: thermalise only")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run a plain device copy of this many MiB (counter calibration under a profiler)")
     args = ap.parse_args()
@@ -493,7 +504,9 @@ def main():
     extras = {}
     if not args.no_extras:
         extras["copy_ceiling_GBps"] = copy_ceiling(torch, dev)
-        log(f"plain 1 GiB device copy: {extras['copy_ceiling_GBps']} GB/s")
+        extras["stream_copy_GBps"] = copy_ceiling(torch, dev, gf=gf)
+        log(f"1 GiB device copy: torch {extras['copy_ceiling_GBps']} GB/s, streaming kernel "
+            f"{extras['stream_copy_GBps']} GB/s")
         for p2 in ["fp64_12", "fp32_12"]:
             if p2 == prec:
                 continue
@@ -528,7 +541,8 @@ def main():
     if not args.no_extras and not args.no_wilson:
         extras["wilson_singlet_correlator"] = wilson_workload(gf, torch, synth, dev)
     if not args.no_extras and not args.no_pipeline:
-        extras["thermalised_pipeline"] = pipeline_workload(gf, torch, dev)
+        extras["thermalised_pipeline"] = pipeline_workload(gf, torch, dev, n_therm=args.pipeline_sweeps,
+                                                           fix=not args.pipeline_no_fix)
 
     cpu = None
     if not args.no_cpu_baseline:

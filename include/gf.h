@@ -334,6 +334,15 @@ const char* gf_last_error(const gf_ctx* ctx);
 /* Free the host context (the caller frees its own device buffers). */
 void gf_destroy(gf_ctx* ctx);
 
+/*
+ * Measurement aid, not part of the method: a plain streaming copy of `bytes`
+ * (a multiple of 16; both pointers 16-byte aligned, device, caller-owned, not
+ * overlapping) queued on stream, 16 bytes per lane with nontemporal loads and
+ * stores. It gives the device bandwidth on the simplest read-once/write-once
+ * traffic, against which the kernels' bandwidth figures are read.
+ */
+gf_status gf_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * Temporal Wilson lines and the colour-singlet correlator (paper, Section 1,
  * Eq. (1)): the singlet free energy comes from (1/3) < Tr W(r) W(0)^dag >,
@@ -422,22 +431,28 @@ size_t gf_mc_workspace_bytes(const int32_t dims[4]);
 
 /*
  * Create a generator handle: beta > 0 and finite, any 64-bit seed, workspace
- * >= gf_mc_workspace_bytes and 256-byte aligned (caller-owned, kept for the
- * handle's life), stream a hipStream_t (NULL = default). Queues nothing.
+ * >= gf_mc_workspace_bytes (about 576 B per site: the even/odd copy of the
+ * links) and 256-byte aligned (caller-owned, kept for the handle's life),
+ * stream a hipStream_t (NULL = default). Queues nothing.
  * GF_EINVAL / GF_ENOTSUP: nothing created (gf_mc_last_error(NULL)).
  */
 gf_status gf_mc_create(gf_mc** out, const int32_t dims[4], double beta, uint64_t seed, void* d_workspace,
                        size_t workspace_bytes, void* stream);
 
 /*
- * One heatbath sweep with the random numbers of `sweep` (< 2^32), then
- * n_overrelax (0..64) over-relaxation sweeps, then every link reunitarised,
- * in place on d_links. If h_rejected is not NULL the stream is synchronised
- * and it receives the number of SU(2) pair updates that kept their old value
- * because 64 Kennedy-Pendleton attempts were all rejected (0 in practice at
- * beta >~ 1). Otherwise nothing is synchronised.
+ * n_sweeps (>= 1) sweeps in place on d_links; sweep k (k = first_sweep ..
+ * first_sweep + n_sweeps - 1, all < 2^32) is one heatbath sweep with the
+ * random numbers of k, then n_overrelax (0..64) over-relaxation sweeps, then
+ * every link reunitarised. The links are packed into the handle's even/odd
+ * planes once before the first sweep and written back after the last. If
+ * h_rejected is not NULL the stream is synchronised and it receives the
+ * number of SU(2) pair updates that kept their old value because 64
+ * Kennedy-Pendleton attempts were all rejected (the chain then stays where it
+ * was, which keeps the target distribution; 0 in practice at beta >~ 1).
+ * Otherwise nothing is synchronised.
  */
-gf_status gf_mc_update(gf_mc* m, double* d_links, uint64_t sweep, int32_t n_overrelax, int64_t* h_rejected);
+gf_status gf_mc_update(gf_mc* m, double* d_links, uint64_t first_sweep, int32_t n_sweeps, int32_t n_overrelax,
+                       int64_t* h_rejected);
 
 /*
  * Multi-hit average of every temporal link with the random numbers of `tag`

@@ -1542,6 +1542,14 @@ gf_status run_batch(gf_ctx* c, BatchState& b, double tol, int64_t max_iter, std:
 }
 }  // namespace
 
+// A plain streaming copy (16 bytes per lane, nontemporal): the bandwidth the device reaches on the
+// simplest read-once / write-once traffic, against which the kernels' figures are read.
+__global__ void __launch_bounds__(256) k_stream_copy(const cx<double>* __restrict__ a, cx<double>* __restrict__ b,
+                                                     size_t n) {
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) nt_store(b + i, nt_load(a + i));
+}
+
 extern "C" {
 
 size_t gf_workspace_bytes(const gf_params* params) {
@@ -2248,5 +2256,17 @@ gf_status gf_mlp_make_samples(const double* d_records, int32_t n_records, const 
 }
 
 void gf_destroy(gf_ctx* c) { free_ctx(c); }
+
+gf_status gf_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream) {
+    if (!d_src || !d_dst || bytes % 16 || reinterpret_cast<uintptr_t>(d_src) % 16 ||
+        reinterpret_cast<uintptr_t>(d_dst) % 16)
+        return GF_EINVAL;
+    const size_t n = bytes / 16;
+    if (n == 0) return GF_OK;
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       reinterpret_cast<hipStream_t>(stream), static_cast<const cx<double>*>(d_src),
+                       static_cast<cx<double>*>(d_dst), n);
+    return hipGetLastError() == hipSuccess ? GF_OK : GF_EDEVICE;
+}
 
 }  // extern "C"

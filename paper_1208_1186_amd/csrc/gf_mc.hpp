@@ -18,8 +18,13 @@
 // one call gives two doubles in (0, 1] of 53 bits each. Every link's numbers depend only on its
 // counter, so the result does not depend on the launch shape.
 //
-// Links are canonical complex double [site][mu][row][col]; one thread per link. Links of one
-// direction and one parity share no staple, so each (mu, parity) half is one launch.
+// The sweeps run on an even/odd structure-of-arrays copy of the links in the handle's workspace: plane
+// (mu, element, parity) holds that matrix element of U_mu at the sites of that parity, site s at
+// index s >> 1 (x is fastest and Nx is even, so s and s ^ 1 share an index and differ in parity).
+// A wave's 64 lanes take consecutive sites of one parity, so every load and store of a link element
+// is one contiguous 1 KB run. One thread per link; links of one direction and one parity share no
+// staple, so each (mu, parity) half is one launch. The canonical links ([site][mu][row][col]) are
+// packed before the first sweep of a call and unpacked after the last.
 #pragma once
 
 #include "gf_device.hpp"
@@ -88,6 +93,31 @@ __device__ __forceinline__ void mc_store(double2* __restrict__ links, long long 
     double2* p = links + (s * 4 + mu) * 9;
 #pragma unroll
     for (int k = 0; k < 9; ++k) p[k] = {m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im};
+}
+
+// Even/odd planes: P + ((mu*9 + e)*2 + parity) * hp + (s >> 1).
+struct McPlanes {
+    double2* p;
+    size_t hp;  // elements per plane
+};
+
+__device__ __forceinline__ int mc_parity(const int c[4]) { return (c[0] + c[1] + c[2] + c[3]) & 1; }
+
+__device__ __forceinline__ su3<double> eo_load(const McPlanes& P, long long s, int par, int mu) {
+    const double2* q = P.p + (size_t)(mu * 18 + par) * P.hp + (s >> 1);
+    su3<double> m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double2 v = q[(size_t)k * 2 * P.hp];
+        m.e[k / 3][k % 3] = {v.x, v.y};
+    }
+    return m;
+}
+
+__device__ __forceinline__ void eo_store(const McPlanes& P, long long s, int par, int mu, const su3<double>& m) {
+    double2* q = P.p + (size_t)(mu * 18 + par) * P.hp + (s >> 1);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[(size_t)k * 2 * P.hp] = {m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im};
 }
 
 // a * b^dagger
@@ -178,6 +208,39 @@ __device__ __forceinline__ su3<double> mc_staples(const double2* __restrict__ li
     return a;
 }
 
+// Staple sum of U_mu at site coordinates c (parity p) from the even/odd planes; the same products in the
+// same order as mc_staples. Neighbours one step away have parity 1 - p, two steps away parity p.
+__device__ __forceinline__ su3<double> eo_staples(const McPlanes& P, const McGeom& g, const int c[4], int p, int mu) {
+    su3<double> a;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) a.e[i][j] = {0.0, 0.0};
+    const long long s = mc_site(g, c);
+    const long long s_pm = mc_step(g, c, mu, 1);
+    for (int nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        {
+            const su3<double> t = mc_mul_adj(eo_load(P, s_pm, 1 - p, nu), eo_load(P, mc_step(g, c, nu, 1), 1 - p, mu));
+            const su3<double> up = mc_mul_adj(t, eo_load(P, s, p, nu));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) a.e[i][j] = a.e[i][j] + up.e[i][j];
+        }
+        {
+            const long long s_mn = mc_step(g, c, nu, -1);
+            const su3<double> mb = mul(eo_load(P, s_mn, 1 - p, mu), eo_load(P, mc_step2(g, c, mu, 1, nu, -1), p, nu));
+            const su3<double> dn = mc_adj_mul(mb, eo_load(P, s_mn, 1 - p, nu));
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) a.e[i][j] = a.e[i][j] + dn.e[i][j];
+        }
+    }
+    return a;
+}
+
 struct Su2 {
     cx<double> m00, m01, m10, m11;
 };
@@ -256,8 +319,8 @@ __device__ __forceinline__ int mc_cm_update(su3<double>& u, const su3<double>& a
 // given parity, in lexicographic order. Block b adds its count of rejected pair updates to rej[b]
 // (plain stores: the launches of a sweep are ordered on one stream).
 template <bool OR>
-__global__ void __launch_bounds__(kMcThreads) k_mc_update(double2* __restrict__ links, McGeom g, int mu, int parity,
-                                                          double beta, McKey key, unsigned* __restrict__ rej) {
+__global__ void __launch_bounds__(kMcThreads) k_mc_update(McPlanes P, McGeom g, int mu, int parity, double beta,
+                                                          McKey key, unsigned* __restrict__ rej) {
     __shared__ unsigned red[kMcThreads];
     const long long h = (long long)blockIdx.x * kMcThreads + threadIdx.x;
     unsigned rj = 0;
@@ -269,10 +332,10 @@ __global__ void __launch_bounds__(kMcThreads) k_mc_update(double2* __restrict__ 
         c[3] = (int)(row / ((long long)g.n[1] * g.n[2]));
         c[0] = 2 * (int)(h - row * g.half_x) + ((c[1] + c[2] + c[3] + parity) & 1);
         const long long s = mc_site(g, c);
-        const su3<double> a = mc_staples(links, g, c, mu);
-        su3<double> u = mc_load(links, s, mu);
+        const su3<double> a = eo_staples(P, g, c, parity, mu);
+        su3<double> u = eo_load(P, s, parity, mu);
         rj = (unsigned)mc_cm_update<OR>(u, a, beta, key, (unsigned)(s * 4 + mu), 0);
-        mc_store(links, s, mu, u);
+        eo_store(P, s, parity, mu, u);
     }
     if (OR) return;
     red[threadIdx.x] = rj;
@@ -282,6 +345,51 @@ __global__ void __launch_bounds__(kMcThreads) k_mc_update(double2* __restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0 && red[0]) rej[blockIdx.x] += red[0];
+}
+
+// Canonical links <-> even/odd planes, one thread per site.
+__global__ void __launch_bounds__(256) k_mc_pack(const double2* __restrict__ links, McPlanes P, McGeom g) {
+    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (s >= g.vol) return;
+    int c[4];
+    long long r = s;
+    for (int d = 0; d < 4; ++d) {
+        c[d] = (int)(r % g.n[d]);
+        r /= g.n[d];
+    }
+    const int par = mc_parity(c);
+    for (int mu = 0; mu < 4; ++mu) eo_store(P, s, par, mu, mc_load(links, s, mu));
+}
+
+__global__ void __launch_bounds__(256) k_mc_unpack(McPlanes P, McGeom g, double2* __restrict__ links) {
+    const long long s = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (s >= g.vol) return;
+    int c[4];
+    long long r = s;
+    for (int d = 0; d < 4; ++d) {
+        c[d] = (int)(r % g.n[d]);
+        r /= g.n[d];
+    }
+    const int par = mc_parity(c);
+    for (int mu = 0; mu < 4; ++mu) mc_store(links, s, mu, eo_load(P, s, par, mu));
+}
+
+// Every link reunitarised in the planes: thread per (site of one parity index, parity, mu).
+__global__ void __launch_bounds__(256) k_mc_reunit(McPlanes P, long long half) {
+    const long long l = (long long)blockIdx.x * 256 + threadIdx.x;  // l = (mu * 2 + parity) * half + h
+    if (l >= 8 * half) return;
+    const long long h = l % half;
+    const int mp = (int)(l / half), mu = mp >> 1, par = mp & 1;
+    double2* q = P.p + (size_t)(mu * 18 + par) * P.hp + h;
+    su3<double> m;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const double2 v = q[(size_t)k * 2 * P.hp];
+        m.e[k / 3][k % 3] = {v.x, v.y};
+    }
+    reunitarize(m);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) q[(size_t)k * 2 * P.hp] = {m.e[k / 3][k % 3].re, m.e[k / 3][k % 3].im};
 }
 
 __global__ void __launch_bounds__(256) k_mc_zero(unsigned* __restrict__ p, int n) {
@@ -302,14 +410,6 @@ __global__ void __launch_bounds__(256) k_mc_count(const unsigned* __restrict__ p
         __syncthreads();
     }
     if (threadIdx.x == 0) *out = red[0];
-}
-
-__global__ void __launch_bounds__(256) k_mc_reunit(double2* __restrict__ links, long long nlinks) {
-    const long long l = (long long)blockIdx.x * 256 + threadIdx.x;  // link l = 4 s + mu
-    if (l >= nlinks) return;
-    su3<double> m = mc_load(links, l >> 2, (int)(l & 3));
-    reunitarize(m);
-    mc_store(links, l >> 2, (int)(l & 3), m);
 }
 
 // Multi-hit average of every temporal link, out as complex double [site][row][col].

@@ -1,10 +1,12 @@
 // libgf host side of the Monte Carlo input generator (gf_mc_* in include/gf.h).
 //
-// The handle keeps the lattice shape, beta, the seed and a small workspace of
-// the caller's: per-block counters of rejected heatbath pair updates, plaquette
-// partials and two result scalars. A sweep is 8 launches per heatbath or
-// over-relaxation pass (4 directions x 2 parities) and one reunitarisation
-// launch; all on the handle's stream.
+// The handle keeps the lattice shape, beta, the seed and a workspace of the
+// caller's: the even/odd link planes the sweeps run on (72 planes of V/2
+// complex doubles), per-block counters of rejected heatbath pair updates,
+// plaquette partials and two result scalars. A call packs the canonical links
+// into the planes, runs its sweeps (8 launches per heatbath or over-relaxation
+// pass: 4 directions x 2 parities; then one reunitarisation launch) and
+// unpacks; all on the handle's stream.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -18,6 +20,7 @@ using namespace gf;
 
 struct gf_mc {
     McGeom g;
+    McPlanes P;
     double beta;
     unsigned long long seed;
     int nblk_half;  // blocks of one (mu, parity) launch
@@ -42,7 +45,8 @@ size_t mc_align(size_t x) { return (x + kMcAlign - 1) / kMcAlign * kMcAlign; }
 struct McLayout {
     McGeom g;
     int nblk_half, nblk_plaq;
-    size_t off_rej, off_part, off_count, off_plaq, total;
+    size_t hp;
+    size_t off_planes, off_rej, off_part, off_count, off_plaq, total;
 };
 
 gf_status mc_layout(const int32_t* dims, McLayout& L, std::string& err) {
@@ -72,7 +76,10 @@ gf_status mc_layout(const int32_t* dims, McLayout& L, std::string& err) {
     L.g.half_x = L.g.n[0] / 2;
     L.nblk_half = (int)((vol / 2 + kMcThreads - 1) / kMcThreads);
     L.nblk_plaq = (int)((vol + 255) / 256);
+    L.hp = (size_t)(vol / 2 + 255) / 256 * 256;
     size_t o = 0;
+    L.off_planes = o;
+    o = mc_align(o + 72 * L.hp * sizeof(double2));
     L.off_rej = o;
     o = mc_align(o + (size_t)L.nblk_half * sizeof(unsigned));
     L.off_part = o;
@@ -142,6 +149,7 @@ gf_status gf_mc_create(gf_mc** out, const int32_t* dims, double beta, uint64_t s
     m->nblk_half = L.nblk_half;
     m->nblk_plaq = L.nblk_plaq;
     unsigned char* ws = static_cast<unsigned char*>(d_workspace);
+    m->P = {reinterpret_cast<double2*>(ws + L.off_planes), L.hp};
     m->rej = reinterpret_cast<unsigned*>(ws + L.off_rej);
     m->part = reinterpret_cast<double*>(ws + L.off_part);
     m->d_count = reinterpret_cast<unsigned long long*>(ws + L.off_count);
@@ -151,30 +159,41 @@ gf_status gf_mc_create(gf_mc** out, const int32_t* dims, double beta, uint64_t s
     return GF_OK;
 }
 
-gf_status gf_mc_update(gf_mc* m, double* d_links, uint64_t sweep, int32_t n_overrelax, int64_t* h_rejected) {
+gf_status gf_mc_update(gf_mc* m, double* d_links, uint64_t first_sweep, int32_t n_sweeps, int32_t n_overrelax,
+                       int64_t* h_rejected) {
     if (!m) return GF_EINVAL;
     if (!d_links) return mfail(m, GF_EINVAL, "d_links is NULL");
-    if (sweep > 0xFFFFFFFFull) return mfail(m, GF_EINVAL, "sweep must fit in 32 bits");
+    if (n_sweeps < 1) return mfail(m, GF_EINVAL, "n_sweeps must be >= 1");
+    if (first_sweep + (uint64_t)n_sweeps - 1 > 0xFFFFFFFFull) return mfail(m, GF_EINVAL, "sweeps must fit in 32 bits");
     if (n_overrelax < 0 || n_overrelax > 64) return mfail(m, GF_EINVAL, "n_overrelax must be in [0, 64]");
     double2* links = reinterpret_cast<double2*>(d_links);
-    const McKey key = make_key(m, (unsigned)sweep, 0);
+    const unsigned nsite_blk = (unsigned)((m->g.vol + 255) / 256);
     hipLaunchKernelGGL(k_mc_zero, dim3((m->nblk_half + 255) / 256), dim3(256), 0, m->st, m->rej, m->nblk_half);
     gf_status s = mcheck(m, hipGetLastError(), "counter reset launch");
-    for (int rep = 0; rep <= n_overrelax && s == GF_OK; ++rep)
-        for (int mu = 0; mu < 4 && s == GF_OK; ++mu)
-            for (int par = 0; par < 2 && s == GF_OK; ++par) {
-                if (rep == 0)
-                    hipLaunchKernelGGL(k_mc_update<false>, dim3(m->nblk_half), dim3(kMcThreads), 0, m->st, links,
-                                       m->g, mu, par, m->beta, key, m->rej);
-                else
-                    hipLaunchKernelGGL(k_mc_update<true>, dim3(m->nblk_half), dim3(kMcThreads), 0, m->st, links,
-                                       m->g, mu, par, m->beta, key, m->rej);
-                s = mcheck(m, hipGetLastError(), "update launch");
-            }
     if (s != GF_OK) return s;
-    const long long nlinks = m->g.vol * 4;
-    hipLaunchKernelGGL(k_mc_reunit, dim3((unsigned)((nlinks + 255) / 256)), dim3(256), 0, m->st, links, nlinks);
-    if ((s = mcheck(m, hipGetLastError(), "reunitarisation launch")) != GF_OK) return s;
+    hipLaunchKernelGGL(k_mc_pack, dim3(nsite_blk), dim3(256), 0, m->st, links, m->P, m->g);
+    if ((s = mcheck(m, hipGetLastError(), "pack launch")) != GF_OK) return s;
+    const long long half = m->g.vol / 2;
+    for (int32_t k = 0; k < n_sweeps && s == GF_OK; ++k) {
+        const McKey key = make_key(m, (unsigned)(first_sweep + k), 0);
+        for (int rep = 0; rep <= n_overrelax && s == GF_OK; ++rep)
+            for (int mu = 0; mu < 4 && s == GF_OK; ++mu)
+                for (int par = 0; par < 2 && s == GF_OK; ++par) {
+                    if (rep == 0)
+                        hipLaunchKernelGGL(k_mc_update<false>, dim3(m->nblk_half), dim3(kMcThreads), 0, m->st, m->P,
+                                           m->g, mu, par, m->beta, key, m->rej);
+                    else
+                        hipLaunchKernelGGL(k_mc_update<true>, dim3(m->nblk_half), dim3(kMcThreads), 0, m->st, m->P,
+                                           m->g, mu, par, m->beta, key, m->rej);
+                    s = mcheck(m, hipGetLastError(), "update launch");
+                }
+        if (s != GF_OK) return s;
+        hipLaunchKernelGGL(k_mc_reunit, dim3((unsigned)((8 * half + 255) / 256)), dim3(256), 0, m->st, m->P, half);
+        s = mcheck(m, hipGetLastError(), "reunitarisation launch");
+    }
+    if (s != GF_OK) return s;
+    hipLaunchKernelGGL(k_mc_unpack, dim3(nsite_blk), dim3(256), 0, m->st, m->P, m->g, links);
+    if ((s = mcheck(m, hipGetLastError(), "unpack launch")) != GF_OK) return s;
     if (h_rejected) {
         hipLaunchKernelGGL(k_mc_count, dim3(1), dim3(256), 0, m->st, m->rej, m->nblk_half, m->d_count);
         if ((s = mcheck(m, hipGetLastError(), "count launch")) != GF_OK) return s;

@@ -97,11 +97,12 @@ def _signatures(lib):
         "gf_wilson_destroy": (None, [_P]),
         "gf_mc_workspace_bytes": (sz, [ctypes.POINTER(i32)]),
         "gf_mc_create": (i32, [ctypes.POINTER(_P), ctypes.POINTER(i32), dbl, ctypes.c_uint64, _P, sz, _P]),
-        "gf_mc_update": (i32, [_P, _P, ctypes.c_uint64, i32, ctypes.POINTER(i64)]),
+        "gf_mc_update": (i32, [_P, _P, ctypes.c_uint64, i32, i32, ctypes.POINTER(i64)]),
         "gf_mc_multihit": (i32, [_P, _P, ctypes.c_uint64, i32, _P]),
         "gf_mc_plaquette": (i32, [_P, _P, pd]),
         "gf_mc_last_error": (ctypes.c_char_p, [_P]),
         "gf_mc_destroy": (None, [_P]),
+        "gf_stream_copy": (i32, [_P, _P, sz, _P]),
         "gf_last_error": (ctypes.c_char_p, [_P]),
         "gf_destroy": (None, [_P]),
     }
@@ -650,10 +651,11 @@ class MonteCarlo:
         if st != GF_OK:
             raise GfError(st, gf_mc_last_error(self.m))
 
-    def update(self, links, sweep, n_overrelax=0, count_rejected=False):
-        """One heatbath sweep + n_overrelax over-relaxation sweeps; returns the rejected-pair count if asked."""
+    def update(self, links, sweep, n_overrelax=0, count_rejected=False, n_sweeps=1):
+        """Sweeps sweep .. sweep + n_sweeps - 1, each one heatbath + n_overrelax over-relaxation passes;
+        returns the rejected-pair count if asked."""
         rej = ctypes.c_int64(0)
-        self._check(load().gf_mc_update(self.m, _P(links.data_ptr()), int(sweep), int(n_overrelax),
+        self._check(load().gf_mc_update(self.m, _P(links.data_ptr()), int(sweep), int(n_sweeps), int(n_overrelax),
                                         ctypes.byref(rej) if count_rejected else None))
         return rej.value if count_rejected else None
 

@@ -185,7 +185,7 @@ def test_mc_null_handle_and_workspace(lib):
     assert lib.gf_mc_create(ctypes.byref(m), gf._dims4((8, 8, 8, 8)), 6.0, 1, None, nb, None) == gf.GF_EINVAL
     assert lib.gf_mc_create(ctypes.byref(m), gf._dims4((8, 8, 8, 8)), 6.0, 1, ctypes.c_void_p(256), nb - 1,
                             None) == gf.GF_EINVAL
-    assert lib.gf_mc_update(None, None, 0, 0, None) == gf.GF_EINVAL
+    assert lib.gf_mc_update(None, None, 0, 1, 0, None) == gf.GF_EINVAL
     assert lib.gf_mc_multihit(None, None, 0, 1, None) == gf.GF_EINVAL
     assert lib.gf_mc_plaquette(None, None, None) == gf.GF_EINVAL
     lib.gf_mc_destroy(None)

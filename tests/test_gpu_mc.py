@@ -103,3 +103,17 @@ def test_plaquette_limits_at_16x16x16x16(beta, want, tol):
             ps.append(m.plaquette(links))
     assert abs(np.mean(ps) - want) < tol, np.mean(ps)
     m.close()
+
+
+def test_several_sweeps_in_one_call_are_bitwise_single_calls():
+    dims = (8, 4, 6, 4)
+    u = synth.make_config(dims, 8)
+    a = torch.from_numpy(u).cuda()
+    b = torch.from_numpy(u).cuda()
+    m = gf.MonteCarlo(dims, 6.0, 99)
+    ra = m.update(a, 5, 2, count_rejected=True, n_sweeps=3)
+    rb = sum(m.update(b, 5 + k, 2, count_rejected=True) for k in range(3))
+    assert torch.equal(a, b) and ra == rb
+    with pytest.raises(gf.GfError):
+        m.update(a, 0xFFFFFFFF, 0, n_sweeps=2)  # the last sweep index would not fit in 32 bits
+    m.close()
