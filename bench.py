@@ -104,7 +104,7 @@ def copy_ceiling(torch, dev, mib=1024, reps=10, gf=None):
     return round(gbps, 1)
 
 
-TILINGS = {}  # precision -> (planes per (x, y) block, columns per (z, t) block) chosen by the library
+TILINGS = {}  # precision -> ((x, y) planes per block, (z, t) columns per block, loop-kernel z group) chosen by the library
 
 
 def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events, only=None):
@@ -112,7 +112,7 @@ def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events, only=Non
     (all kernels if None) with HIP events on the context's stream."""
     links = u_dev.clone()
     fx = gf.GaugeFixer(links, precision, check_every=max(steps, warmup, 1))
-    TILINGS[precision] = gf.gf_fft_tiling(fx.ctx)
+    TILINGS[precision] = tuple(gf.gf_fft_tiling(fx.ctx)) + (fx.loop_traversal(),)
     if warmup:
         fx.iterate(warmup)
     torch.cuda.synchronize()
@@ -578,8 +578,8 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kern,
         "event_ms_per_step": round(events_ms, 5),
-        "fft_tiling_autotuned": {p: {"xy_planes_per_block": g, "zt_columns_per_block": b}
-                                 for p, (g, b) in TILINGS.items()},
+        "tilings_autotuned": {p: {"xy_planes_per_block": g, "zt_columns_per_block": b, "loop_z_group": z}
+                              for p, (g, b, z) in TILINGS.items()},
         **extras,
     }
     print(json.dumps(out), flush=True)

@@ -160,6 +160,20 @@ gf_status gf_fix_until_batch(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf
 gf_status gf_fft_tiling(gf_ctx* ctx, int32_t* xy_planes, int32_t* zt_columns);
 
 /*
+ * Traversal of the loop kernel (update + divergence + theta/F partials):
+ * blocks of 64 sites sweep the (x, y) planes, taking z in groups of z_group
+ * planes inside the t loop, so that t neighbours are still cached. gf_init
+ * times the groupings that fit the shape (1, and 2, 4, 8 where they divide
+ * Nz) on the first context of a shape and precision in the process and keeps
+ * the fastest. Partials are summed by site block, so every grouping gives
+ * bitwise the same results. gf_set_loop_traversal overrides the choice for
+ * this context (a test and measurement aid); GF_EINVAL if z_group is not one
+ * of the candidates. For GF_MIXED: the active phase.
+ */
+gf_status gf_loop_traversal(gf_ctx* ctx, int32_t* z_group);
+gf_status gf_set_loop_traversal(gf_ctx* ctx, int32_t z_group);
+
+/*
  * Mean plaquette of the current links, (1/(18V)) sum_x sum_{mu<nu} Re Tr[
  * U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag], summed in double precision
  * in a fixed order. Gauge invariant: gauge fixing must leave it unchanged

@@ -80,6 +80,7 @@ struct Layout {
     size_t ps;        // plane stride (elements) of every SoA array
     int nblk;         // blocks of the one-site-per-thread kernels
     int nblk_fused;   // blocks of the loop kernel (kFusedSites sites each)
+    int zb = 1;       // loop-kernel traversal: z planes per group inside the t loop (autotuned)
     bool fp32;
     int ne;           // 9 or 6 complex entries stored per link
     // forward / inverse (x, y) pass over single-field planes
@@ -96,7 +97,7 @@ struct Layout {
     bool record;      // reserve two spectra and the per-tuple record
     int ntuples;      // distinct momentum tuples (N_mu/2 + 1 per axis)
     // workspace offsets
-    size_t off_ctl, off_part, off_sin2, off_tw, off_d, off_q, off_g, off_acc, off_links[2], off_mlp, off_mtab,
+    size_t off_ctl, off_tune, off_part, off_sin2, off_tw, off_d, off_q, off_g, off_acc, off_links[2], off_mlp, off_mtab,
         off_spec[4], off_rec, total;
     // GF_MIXED: a float child (bulk) and a double child (polish) share the workspace
     bool mixed;
@@ -205,6 +206,8 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     size_t o = 0;
     L.off_ctl = o;
     o = align_up(o + sizeof(Ctl), kAlign);
+    L.off_tune = o;  // a scratch control-block head for the autotuner's trial launches of the loop kernel
+    o = align_up(o + offsetof(Ctl, hist_theta), kAlign);
     L.off_part = o;
     o = align_up(o + (size_t)std::max(L.nblk, L.nblk_fused) * sizeof(double2), kAlign);
     L.off_sin2 = o;
@@ -278,6 +281,7 @@ struct gf_ctx {
     double* links_user;
     unsigned char* ws;
     Ctl* ctl;
+    Ctl* tune_ctl;  // head only: the autotuner's trial launches of the loop kernel
     double2* part;
     void* sin2;
     void* tw[4];
@@ -569,7 +573,8 @@ void launch_fused_t(gf_ctx* c, long long k) {
     tstart(c, GF_K_UPDATE_MEASURE);
     hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused, c->nact), dim3(kFusedThreads), 0, c->st,
                        links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
-                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl, reinterpret_cast<cx<T>*>(c->Acc), bt(c));
+                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl, reinterpret_cast<cx<T>*>(c->Acc), bt(c),
+                       L.zb);
     tstop(c);
 }
 
@@ -739,7 +744,10 @@ struct TuneKey {
         return fp32 < o.fp32;
     }
 };
-std::map<TuneKey, std::pair<int, int>> g_tuned;  // (G, bx)
+struct Tuned {
+    int G, bx, zb;  // (x, y) planes per block, (z, t) columns per block, loop-kernel z grouping
+};
+std::map<TuneKey, Tuned> g_tuned;
 std::mutex g_tuned_mu;
 
 std::vector<int> xy_candidates(const Layout& L) {
@@ -791,6 +799,41 @@ double time_pass(gf_ctx* c, bool xy) {
     return ms;
 }
 
+// z groupings the loop kernel can take on this shape (1 always).
+std::vector<int> zb_candidates(const Layout& L) {
+    std::vector<int> v{1};
+    if ((L.n[0] * L.n[1]) % kFusedSites != 0) return v;
+    for (int z : {2, 4, 8})
+        if (L.n[2] % z == 0 && L.n[2] > z) v.push_back(z);
+    return v;
+}
+
+template <typename T, int NE>
+void time_loop_t(gf_ctx* c, double& ms_out) {
+    const Layout& L = c->L;
+    const int a = cur(c);
+    auto run = [&]() {
+        hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused), dim3(kFusedThreads), 0, c->st,
+                           links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
+                           cxp<T>(c->Q), L.ps, c->geom, c->part, c->tune_ctl, static_cast<cx<T>*>(nullptr),
+                           Batch{nullptr, 0}, L.zb);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ms_out = 1e30;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+    run();
+    run();
+    (void)hipEventRecord(e0, c->st);
+    for (int i = 0; i < kTuneReps; ++i) run();
+    (void)hipEventRecord(e1, c->st);
+    float ms = 1e30f;
+    if (hipGetLastError() == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+        ms_out = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
 gf_status autotune(gf_ctx* c) {
     if (generic_fft(c) || c->cs != 0) return GF_OK;
     TuneKey key{};
@@ -800,8 +843,9 @@ gf_status autotune(gf_ctx* c) {
         std::lock_guard<std::mutex> lock(g_tuned_mu);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
-            set_xy_tile(c->L, it->second.first);
-            set_zt_tile(c->L, it->second.second);
+            set_xy_tile(c->L, it->second.G);
+            set_zt_tile(c->L, it->second.bx);
+            c->L.zb = it->second.zb;
             return GF_OK;
         }
     }
@@ -831,9 +875,28 @@ gf_status autotune(gf_ctx* c) {
         }
     }
     set_zt_tile(c->L, bestB);
+    int bestZ = 1;
+    const std::vector<int> zbs = zb_candidates(c->L);
+    if (zbs.size() > 1) {
+        // trial launches: current links -> the other link buffer, divergence -> Q, gauge rows zeroed, a
+        // scratch control-block head; D, the control block and the current links are left as they are
+        double best = 1e30;
+        (void)hipMemsetAsync(c->tune_ctl, 0, offsetof(Ctl, hist_theta), c->st);
+        (void)hipMemsetAsync(c->Gb, 0, 6 * c->L.ps * (c->L.fp32 ? 8 : 16), c->st);
+        for (int z : zbs) {
+            c->L.zb = z;
+            double t = 1e30;
+            GF_DISPATCH(c, time_loop_t, c, t);
+            if (t < best) {
+                best = t;
+                bestZ = z;
+            }
+        }
+    }
+    c->L.zb = bestZ;
     (void)hipGetLastError();
     std::lock_guard<std::mutex> lock(g_tuned_mu);
-    g_tuned[key] = {bestG, bestB};
+    g_tuned[key] = {bestG, bestB, bestZ};
     return check_hip(c, hipStreamSynchronize(c->st), "autotune sync");
 }
 
@@ -928,6 +991,7 @@ void carve(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsi
     c->links_user = d_links;
     c->ws = ws;
     c->ctl = reinterpret_cast<Ctl*>(ws + L.off_ctl);
+    c->tune_ctl = reinterpret_cast<Ctl*>(ws + L.off_tune);
     c->part = reinterpret_cast<double2*>(ws + L.off_part);
     c->sin2 = ws + L.off_sin2;
     for (int d = 0; d < 4; ++d) c->tw[d] = ws + L.off_tw + (size_t)d * kMaxExtent * 16;
@@ -1343,6 +1407,7 @@ gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned 
             carve(d, g.q[ph], g.L[ph], nullptr, ws + g.off[ph], st);
             set_xy_tile(d->L, g.view[ph][0]->L.G);  // the tiling tuned for this shape and precision
             set_zt_tile(d->L, g.view[ph][0]->L.bx);
+            d->L.zb = g.view[ph][0]->L.zb;
             d->cs = g.cs[ph];
             d->act_dev = g.d_act;
         }
@@ -1807,6 +1872,24 @@ gf_status gf_fft_tiling(gf_ctx* c, int32_t* xy_planes, int32_t* zt_columns) {
     const gf_ctx* a = active(c);
     *xy_planes = a->L.G;
     *zt_columns = a->L.bx;
+    return GF_OK;
+}
+
+gf_status gf_loop_traversal(gf_ctx* c, int32_t* z_group) {
+    if (!c || !z_group) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    *z_group = active(c)->L.zb;
+    return GF_OK;
+}
+
+gf_status gf_set_loop_traversal(gf_ctx* c, int32_t z_group) {
+    if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    gf_ctx* a = active(c);
+    const std::vector<int> v = zb_candidates(a->L);
+    if (std::find(v.begin(), v.end(), (int)z_group) == v.end())
+        return fail(c, GF_EINVAL, "z_group must be 1 or a divisor 2, 4, 8 of Nz below Nz (and 64 must divide Nx*Ny)");
+    a->L.zb = z_group;
     return GF_OK;
 }
 

@@ -421,11 +421,17 @@ constexpr int kFusedSites = kFusedThreads / 4;
 
 // With acc_g set (six planes, ps apart) the lane of direction 0 also
 // accumulates the total gauge transform in place: A(x) <- reunitarize(g(x) A(x)).
+// Traversal: the blocks of 64 sites sweep each (x, y) plane; with zb > 1 (zb divides Nz, 64 divides
+// the plane) the planes are visited with z in groups of zb inside the t loop, (z mod zb, t, z / zb), so
+// that a site's t neighbour was read zb planes earlier instead of Nz and is still in the XCD's L2 (the
+// price: one plane in zb reads its z neighbour from farther back). The autotuner picks zb per shape and
+// precision. Block partials are stored by site block, so the choice does not change any result bit.
 template <typename T, int NE>
 __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> Lin, Links<T, NE> Lout,
                                                                   const cx<T>* __restrict__ G, cx<T>* __restrict__ D,
                                                                   size_t ps, Geom g, double2* __restrict__ part,
-                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g, Batch bt) {
+                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g, Batch bt,
+                                                                  int zb) {
     {
         const size_t bo = boff(bt);
         Lin.p = bshift(Lin.p, bo);
@@ -440,7 +446,15 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
     const int mu = lane >> 4;
-    const int64_t s = (int64_t)b * kFusedSites + (threadIdx.x >> 6) * 16 + (lane & 15);
+    int sb = b;  // site block: sites sb*64 .. sb*64 + 63
+    if (zb > 1) {
+        const int bpp = (g.n[0] * g.n[1]) / kFusedSites;
+        const int P = b / bpp, off = b - P * bpp;
+        const int z = P % zb + zb * (P / (zb * g.n[3]));
+        const int t = (P / zb) % g.n[3];
+        sb = (z + g.n[2] * t) * bpp + off;
+    }
+    const int64_t s = (int64_t)sb * kFusedSites + (threadIdx.x >> 6) * 16 + (lane & 15);
     const bool valid = s < g.vol;
     double fsum = 0.0, tsum = 0.0;
     AhAcc<T> acc;
@@ -516,7 +530,7 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
     }
     block_sum2<kFusedThreads>(fsum, tsum);
     if (threadIdx.x == 0) {
-        part[b] = make_double2(fsum, tsum);
+        part[sb] = make_double2(fsum, tsum);
         if (b == 0) ctl->pending = 1;
     }
 }

@@ -66,6 +66,8 @@ def _signatures(lib):
         "gf_set_state": (i32, [_P, _P, sz]),
         "gf_fft_tiling": (i32, [_P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "gf_plaquette": (i32, [_P, pd]),
+        "gf_loop_traversal": (i32, [_P, ctypes.POINTER(i32)]),
+        "gf_set_loop_traversal": (i32, [_P, i32]),
         "gf_quality": (i32, [_P, pd, pd]),
         "gf_get_links": (i32, [_P, _P]),
         "gf_get_gauge": (i32, [_P, _P]),
@@ -429,6 +431,14 @@ class GaugeFixer:
 
     def plaquette(self):
         return gf_plaquette(self.ctx)
+
+    def loop_traversal(self):
+        v = ctypes.c_int32(0)
+        _check(self.ctx, load().gf_loop_traversal(self.ctx, ctypes.byref(v)))
+        return v.value
+
+    def set_loop_traversal(self, z_group):
+        _check(self.ctx, load().gf_set_loop_traversal(self.ctx, int(z_group)))
 
     def history(self, n):
         return gf_history(self.ctx, n)

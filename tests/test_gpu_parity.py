@@ -269,3 +269,28 @@ def test_plaquette_matches_oracle_and_is_invariant(dims, precision):
     assert fx.plaquette() == pytest.approx(want, abs=tol)
     fx.fix_until(1e-15 if precision != "fp32_12" else 1e-11, 10000)
     assert fx.plaquette() == pytest.approx(want, abs=1e-12 if precision != "fp32_12" else 1e-6)
+
+
+@pytest.mark.parametrize("dims,prec", [((8, 8, 16, 4), "fp64_18"), ((8, 8, 8, 6), "fp32_12"), ((16, 8, 12, 4), "fp64_12")])
+def test_loop_traversal_does_not_change_results(dims, prec):
+    """Every z grouping of the loop kernel gives bitwise the same links and theta/F history."""
+    u = synth.make_config(dims, 17)
+    runs = []
+    for zb in (1, 2, 4):
+        if dims[2] % zb or dims[2] == zb:
+            continue
+        links = torch.from_numpy(u).cuda()
+        fx = gf.GaugeFixer(links, prec)
+        fx.set_loop_traversal(zb)
+        assert fx.loop_traversal() == zb
+        fx.iterate(12)
+        runs.append((links.cpu(), fx.history(13)))
+        fx.close()
+    assert len(runs) >= 2
+    for l, (th, f) in runs[1:]:
+        assert torch.equal(l, runs[0][0])
+        assert np.array_equal(th, runs[0][1][0]) and np.array_equal(f, runs[0][1][1])
+    fx = gf.GaugeFixer(torch.from_numpy(u).cuda(), prec)
+    with pytest.raises(gf.GfError):
+        fx.set_loop_traversal(3)
+    fx.close()
