@@ -322,7 +322,21 @@ template <bool OR>
 __global__ void __launch_bounds__(kMcThreads) k_mc_update(McPlanes P, McGeom g, int mu, int parity, double beta,
                                                           McKey key, unsigned* __restrict__ rej) {
     __shared__ unsigned red[kMcThreads];
-    const long long h = (long long)blockIdx.x * kMcThreads + threadIdx.x;
+    // Blocks visit the (x, y) planes with z in pairs inside the t loop, (z mod 2, t, z / 2), so that the t
+    // neighbours were read two planes earlier and are still in the XCD's L2 (3.8 % faster per sweep at
+    // 32^4 than the plain lexicographic order; groups of 4 and 8 were no better). Each link's update
+    // does not depend on the order.
+    long long h = (long long)blockIdx.x * kMcThreads + threadIdx.x;
+    {
+        const long long hpp = (long long)g.half_x * g.n[1];  // half-sites per (x, y) plane
+        if (hpp % kMcThreads == 0 && g.n[2] % 2 == 0 && g.n[2] > 2) {
+            const long long bpp = hpp / kMcThreads;
+            const long long b = blockIdx.x, P = b / bpp, off = b - P * bpp;
+            const long long z = P % 2 + 2 * (P / (2 * g.n[3]));
+            const long long t = (P / 2) % g.n[3];
+            h = ((z + (long long)g.n[2] * t) * bpp + off) * kMcThreads + threadIdx.x;
+        }
+    }
     unsigned rj = 0;
     if (h < g.vol / 2) {
         const long long row = h / g.half_x;
