@@ -66,7 +66,8 @@ typedef enum {
 } gf_precision;
 
 enum {
-    GF_FLAG_EXACT_EXP = 1u << 0,   /* reserved: g = exp((alpha/2) Delta~) instead of first order */
+    GF_FLAG_EXACT_EXP = 1u << 0,   /* g = reunitarize(exp((alpha/2) Delta~)) (closed-form SU(3) exponential,
+                                      Cayley-Hamilton) instead of reunitarize(1 + (alpha/2) Delta~) */
     GF_FLAG_NO_FA = 1u << 1,       /* plain steepest descent: K(p) = 1 instead of p2max/p^2 */
     GF_FLAG_GENERIC_FFT = 1u << 2, /* use the runtime-shaped FFT kernels even where a compile-time one exists */
     GF_FLAG_ACCUMULATE_GAUGE = 1u << 3, /* keep G(x) with U = G U_input G(x+mu)^dag (gf_get_gauge) */
@@ -225,11 +226,12 @@ gf_status gf_history(gf_ctx* ctx, int64_t n, double* h_theta, double* h_F);
  *   gf_stage_filter: d_in (canonical anti-Hermitian traceless field) ->
  *     d_out = (alpha/2) * IFFT[K(p) FFT[d_in]] (canonical matrix field).
  *   gf_stage_gauge: d_in as for gf_stage_filter -> d_out = g(x) =
- *     reunitarize(1 + (alpha/2) Delta~(x)) (canonical matrix field), the
- *     gauge transform the loop applies.
+ *     reunitarize(1 + (alpha/2) Delta~(x)) (canonical matrix field; with
+ *     GF_FLAG_EXACT_EXP of exp((alpha/2) Delta~(x))), the gauge transform the
+ *     loop applies.
  *   gf_stage_update: U_mu(x) -> g U_mu(x) g(x+mu)^dag with
- *     g = reunitarize(1 + d_scaled(x)), d_scaled a canonical field that already
- *     holds (alpha/2) Delta~.
+ *     g = reunitarize(1 + d_scaled(x)) (GF_FLAG_EXACT_EXP: of exp(d_scaled(x))),
+ *     d_scaled a canonical field that already holds (alpha/2) Delta~.
  */
 gf_status gf_stage_divergence(gf_ctx* ctx, void* d_delta);
 gf_status gf_stage_filter(gf_ctx* ctx, const void* d_in, void* d_out);

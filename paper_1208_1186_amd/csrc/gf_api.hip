@@ -388,6 +388,9 @@ void tstop(gf_ctx* c) {
 
 // ---------------------------------------------------------------- launches
 int cur(const gf_ctx* c) { return (int)(c->k_host & 1); }
+
+// g = reunitarize(exp((alpha/2) Delta~)) instead of the first-order 1 + (alpha/2) Delta~.
+int exact_exp(const gf_ctx* c) { return (c->p.flags & GF_FLAG_EXACT_EXP) ? 1 : 0; }
 Batch bt(const gf_ctx* c) { return Batch{c->act_dev, c->cs}; }
 double inv3v(const gf_ctx* c) { return 1.0 / (3.0 * (double)c->L.vol); }
 double inv12v(const gf_ctx* c) { return 1.0 / (12.0 * (double)c->L.vol); }
@@ -469,7 +472,7 @@ bool launch_gauge_ct(gf_ctx* c, int force) {
         hipLaunchKernelGGL((k_fft_xy_gauge_ct<T, A, B>), dim3(L.n[2] * L.n[3], c->nact),                       \
                            dim3(ct_threads(4 * A * B, gauge_ept(A, B))), gauge_ct_lds(A, B, sizeof(cx<T>)),    \
                            c->st, reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps,             \
-                           twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c));                                  \
+                           twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c), exact_exp(c));                    \
         return true;                                                                                           \
     }
     GF_GAUGE_CASES(GF_X)
@@ -533,11 +536,13 @@ void launch_gauge_pass(gf_ctx* c, int force) {
     if (L.eptC == kEPT)
         hipLaunchKernelGGL((k_fft_xy_gauge<T, kEPT>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
                            reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
-                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c));
+                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c),
+                           exact_exp(c));
     else
         hipLaunchKernelGGL((k_fft_xy_gauge<T, 16>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
                            reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
-                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c));
+                           c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c),
+                           exact_exp(c));
     tstop(c);
 }
 
@@ -561,7 +566,7 @@ void launch_update_t(gf_ctx* c) {
     const Layout& L = c->L;
     tstart(c, GF_K_UPDATE);
     hipLaunchKernelGGL((k_update<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c, cur(c)),
-                       reinterpret_cast<const cx<T>*>(c->Q), L.ps, c->geom);
+                       reinterpret_cast<const cx<T>*>(c->Q), L.ps, c->geom, exact_exp(c));
     tstop(c);
 }
 

@@ -161,17 +161,97 @@ __device__ __forceinline__ su3<T> mul_rows(const su3<T>& a, const su3<T>& b) {
     return c;
 }
 
-// g = reunitarize(1 + X), X the anti-Hermitian traceless matrix packed in four
+// exp(X) of an anti-Hermitian traceless 3x3 matrix in closed form (Cayley-Hamilton): with the
+// Hermitian Q = -iX, c0 = det Q, c1 = Tr Q^2 / 2, theta = acos(|c0| / (2 (c1/3)^(3/2))),
+// u = sqrt(c1/3) cos(theta/3), w = sqrt(c1) sin(theta/3), exp(iQ) = f0 + f1 Q + f2 Q^2 with
+// f_j = h_j / (9u^2 - w^2),
+//   h0 = (u^2 - w^2) e^{2iu} + e^{-iu} (8u^2 cos w + 2iu (3u^2 + w^2) xi0(w)),
+//   h1 = 2u e^{2iu} - e^{-iu} (2u cos w - i (3u^2 - w^2) xi0(w)),
+//   h2 = e^{2iu} - e^{-iu} (cos w + 3iu xi0(w)),  xi0(w) = sin(w)/w,
+// and f_j -> (-1)^j conj(f_j) for c0 < 0 (Morningstar and Peardon, Phys. Rev. D 69 (2004) 054501).
+// All terms of h_j are O(c1) or larger relative to the denominator, so small X keeps full precision.
+template <typename T>
+__device__ __forceinline__ su3<T> expm_su3(const su3<T>& X) {
+    su3<T> Q;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) Q.e[i][j] = {X.e[i][j].im, -X.e[i][j].re};
+    T c1 = T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) c1 += norm2(Q.e[i][j]);
+    c1 *= T(0.5);
+    su3<T> r;
+    if (!(c1 > (sizeof(T) == 4 ? T(1e-30) : T(1e-200)))) {  // exp(X) = 1 + X to working precision
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) r.e[i][j] = {X.e[i][j].re + (i == j ? T(1) : T(0)), X.e[i][j].im};
+        return r;
+    }
+    const cx<T> m0 = cmul(Q.e[1][1], Q.e[2][2]) - cmul(Q.e[1][2], Q.e[2][1]);
+    const cx<T> m1 = cmul(Q.e[1][0], Q.e[2][2]) - cmul(Q.e[1][2], Q.e[2][0]);
+    const cx<T> m2 = cmul(Q.e[1][0], Q.e[2][1]) - cmul(Q.e[1][1], Q.e[2][0]);
+    const T c0 = (cmul(Q.e[0][0], m0) - cmul(Q.e[0][1], m1) + cmul(Q.e[0][2], m2)).re;
+    const bool neg = c0 < T(0);
+    const T c0max = T(2) * (c1 / T(3)) * sqrt(c1 / T(3));
+    const T th = acos(fmin(fabs(c0) / c0max, T(1)));
+    const T u = sqrt(c1 / T(3)) * cos(th / T(3));
+    const T w = sqrt(c1) * sin(th / T(3));
+    const T w2 = w * w, u2 = u * u;
+    const T xi0 = fabs(w) < T(0.05) ? T(1) - w2 / T(6) * (T(1) - w2 / T(20) * (T(1) - w2 / T(42))) : sin(w) / w;
+    const cx<T> e2 = {cos(T(2) * u), sin(T(2) * u)};
+    const cx<T> em = {cos(u), -sin(u)};
+    const T cw = cos(w);
+    const cx<T> h0 = cscale(e2, u2 - w2) + cmul(em, cx<T>{T(8) * u2 * cw, T(2) * u * (T(3) * u2 + w2) * xi0});
+    const cx<T> h1 = cscale(e2, T(2) * u) - cmul(em, cx<T>{T(2) * u * cw, -(T(3) * u2 - w2) * xi0});
+    const cx<T> h2 = e2 - cmul(em, cx<T>{cw, T(3) * u * xi0});
+    const T inv = T(1) / (T(9) * u2 - w2);
+    cx<T> f0 = cscale(h0, inv), f1 = cscale(h1, inv), f2 = cscale(h2, inv);
+    if (neg) {
+        f0 = conj(f0);
+        f1 = {-f1.re, f1.im};
+        f2 = conj(f2);
+    }
+    const su3<T> Q2 = mul(Q, Q);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            cx<T> v = cmul(f1, Q.e[i][j]) + cmul(f2, Q2.e[i][j]);
+            if (i == j) v = v + f0;
+            r.e[i][j] = v;
+        }
+    return r;
+}
+
+// g = reunitarize(1 + X), or of exp(X) if exact, X the anti-Hermitian traceless matrix packed in four
 // complex numbers: X01 = z0, X02 = z1, X12 = z2, X00 = i Re z3, X11 = i Im z3.
 template <typename T>
-__device__ __forceinline__ su3<T> g_from_packed(cx<T> z0, cx<T> z1, cx<T> z2, cx<T> z3) {
+__device__ __forceinline__ su3<T> g_from_packed(cx<T> z0, cx<T> z1, cx<T> z2, cx<T> z3, bool exact = false) {
     su3<T> g;
-    g.e[0][0] = {T(1), z3.re};
-    g.e[0][1] = z0;
-    g.e[0][2] = z1;
-    g.e[1][0] = {-z0.re, z0.im};
-    g.e[1][1] = {T(1), z3.im};
-    g.e[1][2] = z2;
+    if (exact) {
+        su3<T> X;
+        X.e[0][0] = {T(0), z3.re};
+        X.e[0][1] = z0;
+        X.e[0][2] = z1;
+        X.e[1][0] = {-z0.re, z0.im};
+        X.e[1][1] = {T(0), z3.im};
+        X.e[1][2] = z2;
+        X.e[2][0] = {-z1.re, z1.im};
+        X.e[2][1] = {-z2.re, z2.im};
+        X.e[2][2] = {T(0), -(z3.re + z3.im)};
+        g = expm_su3(X);
+    } else {
+        g.e[0][0] = {T(1), z3.re};
+        g.e[0][1] = z0;
+        g.e[0][2] = z1;
+        g.e[1][0] = {-z0.re, z0.im};
+        g.e[1][1] = {T(1), z3.im};
+        g.e[1][2] = z2;
+    }
     reunitarize(g);
     return g;
 }

@@ -141,7 +141,7 @@ template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
     k_fft_xy_gauge_ct(const cx<T>* __restrict__ Q, size_t zps, cx<T>* __restrict__ G, size_t gps,
                       const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
-                      int force, Batch bt) {
+                      int force, Batch bt, int exact) {
     constexpr int RS = NX + 1, P = NX * NY, PL = NY * RS, E = 4 * P;
     constexpr int NT = ct_threads(E, gauge_ept(NX, NY));
     {
@@ -176,7 +176,7 @@ __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
         const int r = r0 + threadIdx.x;
         if (P % NT == 0 || r < P) {
             const int li = (r / NX) * RS + r % NX;
-            const su3<T> g = g_from_packed(buf[li], buf[PL + li], buf[2 * PL + li], buf[3 * PL + li]);
+            const su3<T> g = g_from_packed(buf[li], buf[PL + li], buf[2 * PL + li], buf[3 * PL + li], exact != 0);
 #pragma unroll
             for (int k = 0; k < 6; ++k) G[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
         }

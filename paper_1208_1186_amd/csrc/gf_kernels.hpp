@@ -337,8 +337,8 @@ __global__ void __launch_bounds__(kSiteThreads) k_divergence(Links<T, NE> L, cx<
 
 // ------------------------------------------------------- single update
 template <typename T>
-__device__ __forceinline__ su3<T> g_at_packed(const cx<T>* __restrict__ Z, size_t zps, int64_t s) {
-    return g_from_packed(Z[s], Z[zps + s], Z[2 * zps + s], Z[3 * zps + s]);
+__device__ __forceinline__ su3<T> g_at_packed(const cx<T>* __restrict__ Z, size_t zps, int64_t s, bool exact) {
+    return g_from_packed(Z[s], Z[zps + s], Z[2 * zps + s], Z[3 * zps + s], exact);
 }
 
 // U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag in place, g = reunitarize(1 + Z(x)) with
@@ -346,17 +346,17 @@ __device__ __forceinline__ su3<T> g_at_packed(const cx<T>* __restrict__ Z, size_
 // float links are re-orthonormalised on write, double links stored as computed.
 template <typename T, int NE>
 __global__ void __launch_bounds__(kSiteThreads) k_update(Links<T, NE> L, const cx<T>* __restrict__ Z, size_t zps,
-                                                         Geom g) {
+                                                         Geom g, int exact) {
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t s = (int64_t)b * kSiteThreads + threadIdx.x;
     if (s >= g.vol) return;
     int c[4];
     site_coords(g, s, c);
-    const su3<T> g0 = g_at_packed(Z, zps, s);
+    const su3<T> g0 = g_at_packed(Z, zps, s, exact != 0);
     constexpr int NR = NE == 9 ? 3 : 2;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
-        const su3<T> g1 = g_at_packed(Z, zps, site_fwd(g, s, c, mu));
+        const su3<T> g1 = g_at_packed(Z, zps, site_fwd(g, s, c, mu), exact != 0);
         const su3<T> u = L.load(mu, s);
         const su3<T> gu = mul_rows<T, NR>(g0, u);
         su3<T> un = mul_adj<T, NR>(gu, g1);
@@ -712,7 +712,7 @@ __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const c
                                                        cx<T>* __restrict__ G, size_t gps, int nx, int ny, int rs,
                                                        FftPlan px, FftPlan py, const cx<T>* __restrict__ twgx,
                                                        const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
-                                                       int force, Batch bt) {
+                                                       int force, Batch bt, int exact) {
     {
         const size_t bo = boff(bt);
         Q = bshift(Q, bo);
@@ -743,7 +743,7 @@ __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const c
     for (int r = threadIdx.x; r < P; r += nthr) {
         const int row = r / nx, x = r - row * nx;
         const int li = row * rs + x;
-        const su3<T> g = g_from_packed(buf[li], buf[pl + li], buf[2 * pl + li], buf[3 * pl + li]);
+        const su3<T> g = g_from_packed(buf[li], buf[pl + li], buf[2 * pl + li], buf[3 * pl + li], exact != 0);
 #pragma unroll
         for (int k = 0; k < 6; ++k) G[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
     }

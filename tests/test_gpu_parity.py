@@ -294,3 +294,43 @@ def test_loop_traversal_does_not_change_results(dims, prec):
     with pytest.raises(gf.GfError):
         fx.set_loop_traversal(3)
     fx.close()
+
+
+@pytest.mark.parametrize("dims,precision,alpha", [((8, 8, 8, 8), "fp64_18", 0.08), ((12, 6, 4, 8), "fp64_18", 1.5),
+                                                  ((48, 4, 6, 2), "fp64_12", 1.5), ((8, 8, 8, 8), "fp32_12", 1.5),
+                                                  ((6, 4, 8, 2), "fp64_18", 1.5)])
+def test_gauge_stage_exact_exponential(dims, precision, alpha):
+    """GF_FLAG_EXACT_EXP: g = reunitarize(exp((alpha/2) Delta~)) against the oracle's eigen-decomposition
+    exponential; at alpha 1.5 the step is O(1), so the exponential is far from the first-order form."""
+    print(f"exact exp dims={dims} {precision} alpha {alpha}", flush=True)
+    u = synth.make_config(dims, 5)
+    d = landau.divergence(u)
+    dt = landau.fa_filter(d)
+    want = landau.gauge_from_delta(dt, alpha, exact_exp=True)
+    first = landau.gauge_from_delta(dt, alpha)
+    fx, _ = fixer_for(u, precision, alpha=alpha, flags=gf.FLAG_EXACT_EXP)
+    d_dev = to_dev(d)
+    out = torch.empty_like(d_dev)
+    gf.gf_stage_gauge(fx.ctx, d_dev.data_ptr(), out.data_ptr())
+    got = out.cpu().numpy()
+    # float: the filtered field's rounding grows with its size, so the bound of the alpha = 0.08 gauge
+    # test scales with the largest entry of the step X = (alpha/2) Delta~
+    xmax = 0.5 * alpha * np.max(np.abs(dt))
+    tol = 1e-13 if precision.startswith("fp64") else 2e-6 * max(1.0, xmax)
+    assert np.max(np.abs(got - want)) < tol
+    if alpha > 1:
+        assert np.max(np.abs(first - want)) > 1e-2  # the two forms differ at this step size
+
+
+def test_exact_exponential_solve_matches_oracle():
+    """The whole iteration with the exact exponential follows the oracle's trajectory."""
+    dims = (8, 8, 8, 8)
+    u = synth.make_config(dims, 6)
+    fx, links = fixer_for(u, "fp64_18", flags=gf.FLAG_EXACT_EXP)
+    r = fx.fix_until(1e-15, 5000)
+    uo, info = landau.fix(u, 1e-15, 5000, exact_exp=True)
+    assert r.status == gf.GF_OK and r.iters == info["iters"]
+    assert np.max(np.abs(links.cpu().numpy() - uo)) < 1e-10
+    th, f = fx.history(r.iters + 1)
+    wth = np.array([h[0] for h in info["history"]])
+    assert np.max(np.abs(th[:10] - wth[:10]) / wth[:10]) < 1e-11
