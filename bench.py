@@ -372,10 +372,11 @@ def pipeline_workload(gf, torch, dev, dims=(32, 32, 32, 32), beta=6.0, n_therm=1
     return out
 
 
-def cpu_baseline(u, budget_s=12.0):
+def cpu_baseline(u, budget_s=12.0, workers=None, max_iter=8):
     """The FP64 NumPy oracle's FA iterations on the same input, on the host cores."""
     from oracle import landau
-    workers = int(os.environ.get("ORACLE_FFT_WORKERS", str(min(16, os.cpu_count() or 1))))
+    if workers is None:
+        workers = int(os.environ.get("ORACLE_FFT_WORKERS", str(min(16, os.cpu_count() or 1))))
     landau.FFT_WORKERS = workers
     t0 = time.perf_counter()
     n = 0
@@ -385,10 +386,20 @@ def cpu_baseline(u, budget_s=12.0):
         landau.theta(cur)
         landau.functional(cur)
         n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 8:
+        if time.perf_counter() - t0 > budget_s or n >= max_iter:
             break
     dt = time.perf_counter() - t0
     return n / dt, n, dt, workers
+
+
+def cpu_solve_small(synth, dims=(8, 8, 8, 8), workers=1):
+    """The oracle's whole solve to theta < 1e-15 on a small lattice (seed 0): seconds and iterations."""
+    from oracle import landau
+    landau.FFT_WORKERS = workers
+    u = synth.make_config(dims, 0)
+    t0 = time.perf_counter()
+    _, info = landau.fix(u, 1e-15, 100000)
+    return time.perf_counter() - t0, int(info["iters"])
 
 
 def cpu_baseline_wilson(u, nsep=64):
@@ -552,6 +563,16 @@ def main():
                "sample": f"first {cn} FA iterations of {nx}x{ny}x{nz}x{nt} seed 0 (FP64 NumPy, scipy.fft "
                          f"workers={workers}), {cdt:.1f}s"}
         log(f"oracle: {crate:.3f} it/s over {cn} iterations")
+        if not args.no_extras:
+            # numpy's own matrix arithmetic is single-threaded here; only scipy.fft takes the workers
+            r1, n1, d1, _ = cpu_baseline(u, budget_s=8.0, workers=1, max_iter=3)
+            extras["cpu_baseline_1_thread"] = {"value": round(r1, 4), "unit": "FA iterations/s", "cores": 1,
+                                               "kind": "oracle",
+                                               "sample": f"first {n1} FA iterations of {nx}x{ny}x{nz}x{nt} seed 0 "
+                                                         f"(scipy.fft workers=1), {d1:.1f}s"}
+            ts, its = cpu_solve_small(synth, workers=1)
+            extras["cpu_oracle_solve_8x8x8x8"] = {"s_to_theta_1e-15": round(ts, 2), "iters": its, "cores": 1}
+            log(f"oracle 1 thread: {r1:.3f} it/s; 8^4 solve {ts:.2f}s ({its} iterations)")
         if not args.no_extras and not args.no_wilson:
             extras["wilson_cpu_baseline"] = cpu_baseline_wilson(u)
             log(f"oracle correlator: {extras['wilson_cpu_baseline']['sample']}")
