@@ -2218,7 +2218,7 @@ gf_status gf_record_spectra(gf_ctx* c, int64_t n, double probe_scale, double* d_
 // ----------------------------------------------------------- training
 size_t gf_mlp_workspace_bytes(int64_t n_rows, int32_t n_samples) {
     if (n_rows < 1 || n_samples < 1) return 0;
-    const size_t nb = (size_t)((n_rows + kBwdRows - 1) / kBwdRows);
+    const size_t nb = (size_t)((n_rows + kBwdBlockRows - 1) / kBwdBlockRows);
     size_t o = 0;
     o = align_up(o + (size_t)n_rows * kMlpH * sizeof(float), kAlign);   // H1
     o = align_up(o + (size_t)n_rows * kMlpH * sizeof(float), kAlign);   // H2
@@ -2238,7 +2238,7 @@ struct MlpWs {
 MlpWs carve_mlp(void* ws, int64_t n_rows, int32_t n_samples) {
     MlpWs w;
     unsigned char* b = reinterpret_cast<unsigned char*>(ws);
-    w.nb = (int)((n_rows + kBwdRows - 1) / kBwdRows);
+    w.nb = (int)((n_rows + kBwdBlockRows - 1) / kBwdBlockRows);
     size_t o = 0;
     w.h1 = reinterpret_cast<float*>(b + o);
     o = align_up(o + (size_t)n_rows * kMlpH * sizeof(float), kAlign);
@@ -2253,6 +2253,13 @@ MlpWs carve_mlp(void* ws, int64_t n_rows, int32_t n_samples) {
     w.sloss = reinterpret_cast<double*>(b + o);
     (void)n_samples;
     return w;
+}
+void raise_mlp_lds() {
+    static bool done = false;
+    if (done) return;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_mlp_backward), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)kBwdLds);
+    done = true;
 }
 gf_status mlp_status(hipError_t e, const char* what) {
     if (e == hipSuccess) return GF_OK;
@@ -2285,7 +2292,9 @@ gf_status gf_mlp_loss_grad(const float* d_params, const float* d_x, const float*
     hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, st, d_params, d_x, n_rows,
                        w.h1, w.h2, w.o);
     hipLaunchKernelGGL(k_mlp_loss, dim3(n_samples), dim3(256), 0, st, w.o, d_tgt, d_offsets, n_samples, w.dO, w.sloss);
-    hipLaunchKernelGGL(k_mlp_backward, dim3(w.nb), dim3(256), 0, st, d_params, d_x, w.h1, w.h2, w.dO, n_rows, w.gpart);
+    raise_mlp_lds();
+    hipLaunchKernelGGL(k_mlp_backward, dim3(w.nb), dim3(256), kBwdLds, st, d_params, d_x, w.h1, w.h2, w.dO, n_rows,
+                       w.gpart);
     hipLaunchKernelGGL(k_grad_reduce, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, w.gpart, w.nb, d_grad);
     gf_status s = mlp_status(hipGetLastError(), "mlp loss/gradient");
     if (s == GF_OK && h_loss) {

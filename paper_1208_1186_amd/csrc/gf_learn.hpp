@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ p
 #pragma unroll
         for (int i = 0; i < kMlpIn; ++i) a = fmaf(w[kOffW1 + j * kMlpIn + i], x[i], a);
         h1[j] = tanhf(a);
-        H1[row * kMlpH + j] = h1[j];
+        H1[(int64_t)j * n + row] = h1[j];  // column-major: the lanes' consecutive rows store contiguously
     }
     float a0 = w[kOffB3], a1 = w[kOffB3 + 1];
     for (int j = 0; j < kMlpH; ++j) {
@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ p
 #pragma unroll
         for (int i = 0; i < kMlpH; ++i) a = fmaf(w[kOffW2 + j * kMlpH + i], h1[i], a);
         const float h2 = tanhf(a);
-        H2[row * kMlpH + j] = h2;
+        H2[(int64_t)j * n + row] = h2;
         a0 = fmaf(w[kOffW3 + j], h2, a0);
         a1 = fmaf(w[kOffW3 + kMlpH + j], h2, a1);
     }
@@ -382,65 +382,163 @@ __global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ O, c
     }
 }
 
-// Backward pass: each block takes kBwdRows consecutive rows and writes its
-// partial gradient (kMlpParams floats, summed in double then rounded) to
-// gpart[block]; k_grad_reduce adds the block partials in a fixed order.
-constexpr int kBwdRows = 256;
+// Backward pass. Block b walks kBwdChunks chunks of kBwdRows consecutive rows (kBwdBlockRows in all).
+// Per chunk the rows' hidden activations, inputs and output gradients are staged in LDS; four threads
+// per row form dz2 = (dO W3) (1 - h2^2) and 16 entries each of dz1 = (dz2 W2) (1 - h1^2). Every thread
+// then adds, rows in order, its 4 x 4 tile of dW2 = sum_r dz2[r] h1[r]^T and up to three of the other
+// 642 parameters to register accumulators. The block's partial gradient (float) goes to gpart[b];
+// k_grad_reduce adds the partials in block order, in double. Activations are column-major (H[j * n + row]).
+constexpr int kBwdRows = 64;
+constexpr int kBwdChunks = 8;
+constexpr int kBwdBlockRows = kBwdRows * kBwdChunks;
+constexpr int kBwdStride = kMlpH + 4;  // LDS row stride: 16-byte aligned rows for the tile loads
+constexpr int kBwdOther = kMlpParams - kMlpH * kMlpH;  // W1, b1, b2, W3, b3
+constexpr size_t kBwdLds =
+    (size_t)(kMlpH * kMlpH + kMlpOut * kMlpH + 4 * kBwdRows * kBwdStride + kBwdRows * kMlpIn + kBwdRows * kMlpOut) *
+    sizeof(float);
+
+__device__ __forceinline__ float bwd_other_term(int p, int r, const float* dz1s, const float* dz2s, const float* xs,
+                                                const float* dOs, const float* h2s) {
+    // p indexes the parameters outside W2 in the order W1, b1, b2, W3, b3
+    if (p < kMlpH * kMlpIn) return dz1s[r * kBwdStride + p / kMlpIn] * xs[r * kMlpIn + p % kMlpIn];
+    p -= kMlpH * kMlpIn;
+    if (p < kMlpH) return dz1s[r * kBwdStride + p];
+    p -= kMlpH;
+    if (p < kMlpH) return dz2s[r * kBwdStride + p];
+    p -= kMlpH;
+    if (p < kMlpOut * kMlpH) return dOs[r * kMlpOut + p / kMlpH] * h2s[r * kBwdStride + p % kMlpH];
+    p -= kMlpOut * kMlpH;
+    return dOs[r * kMlpOut + p];
+}
+
+__device__ __forceinline__ int bwd_other_offset(int p) {
+    if (p < kMlpH * kMlpIn) return kOffW1 + p;
+    p -= kMlpH * kMlpIn;
+    if (p < kMlpH) return kOffB1 + p;
+    p -= kMlpH;
+    if (p < kMlpH) return kOffB2 + p;
+    p -= kMlpH;
+    if (p < kMlpOut * kMlpH) return kOffW3 + p;
+    return kOffB3 + (p - kMlpOut * kMlpH);
+}
 
 __global__ void __launch_bounds__(256) k_mlp_backward(const float* __restrict__ params, const float* __restrict__ X,
                                                       const float* __restrict__ H1, const float* __restrict__ H2,
                                                       const float* __restrict__ dO, int64_t n,
                                                       float* __restrict__ gpart) {
-    __shared__ float w2[kMlpH * kMlpH];
-    __shared__ float w3[kMlpOut * kMlpH];
-    __shared__ float dz2s[kBwdRows][kMlpH + 1];
-    __shared__ float dz1s[kBwdRows][kMlpH + 1];
-    for (int i = threadIdx.x; i < kMlpH * kMlpH; i += 256) w2[i] = params[kOffW2 + i];
-    for (int i = threadIdx.x; i < kMlpOut * kMlpH; i += 256) w3[i] = params[kOffW3 + i];
-    __syncthreads();
-    const int64_t row0 = (int64_t)blockIdx.x * kBwdRows;
-    // per row: dz2 = (dO W3) (1 - h2^2), dz1 = (dz2 W2) (1 - h1^2)
-    {
-        const int64_t row = row0 + threadIdx.x;
-        const bool ok = row < n;
-        const float d0 = ok ? dO[row * 2] : 0.f, d1 = ok ? dO[row * 2 + 1] : 0.f;
-        for (int j = 0; j < kMlpH; ++j) {
-            const float h2 = ok ? H2[row * kMlpH + j] : 0.f;
-            dz2s[threadIdx.x][j] = (d0 * w3[j] + d1 * w3[kMlpH + j]) * (1.f - h2 * h2);
+    extern __shared__ __align__(16) float lds[];
+    float* w2 = lds;                                  // [j][i]
+    float* w3 = w2 + kMlpH * kMlpH;                   // [o][j]
+    float* h1s = w3 + kMlpOut * kMlpH;                // [r][i], stride kBwdStride
+    float* dz2s = h1s + kBwdRows * kBwdStride;        // [r][j]
+    float* dz1s = dz2s + kBwdRows * kBwdStride;       // [r][i]
+    float* h2s = dz1s + kBwdRows * kBwdStride;        // [r][j]
+    float* xs = h2s + kBwdRows * kBwdStride;          // [r][k]
+    float* dOs = xs + kBwdRows * kMlpIn;              // [r][o]
+    const int t = threadIdx.x;
+    for (int i = t; i < kMlpH * kMlpH; i += 256) w2[i] = params[kOffW2 + i];
+    for (int i = t; i < kMlpOut * kMlpH; i += 256) w3[i] = params[kOffW3 + i];
+    const int j0 = (t >> 4) * 4, i0 = (t & 15) * 4;  // this thread's tile of dW2
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+    float oacc[3] = {0.f, 0.f, 0.f};
+    const int64_t blk0 = (int64_t)blockIdx.x * kBwdBlockRows;
+    for (int ch = 0; ch < kBwdChunks; ++ch) {
+        const int64_t row0 = blk0 + (int64_t)ch * kBwdRows;
+        if (row0 >= n) break;  // uniform over the block
+        __syncthreads();  // the previous chunk's LDS reads are done
+        {  // H1, H2 column-major -> h1s[r][i], h2s[r][j]: every load issued before the LDS stores
+            constexpr int PER = kMlpH * kBwdRows / 256;
+            float v1[PER], v2[PER];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                const int e = t + 256 * m;
+                const int i = e / kBwdRows, r = e % kBwdRows;
+                const int64_t row = row0 + r;
+                v1[m] = row < n ? H1[(int64_t)i * n + row] : 0.f;
+                v2[m] = row < n ? H2[(int64_t)i * n + row] : 0.f;
+            }
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+                const int e = t + 256 * m;
+                const int i = e / kBwdRows, r = e % kBwdRows;
+                h1s[r * kBwdStride + i] = v1[m];
+                h2s[r * kBwdStride + i] = v2[m];
+            }
         }
-        for (int i = 0; i < kMlpH; ++i) {
-            float a = 0.f;
-            for (int j = 0; j < kMlpH; ++j) a = fmaf(dz2s[threadIdx.x][j], w2[j * kMlpH + i], a);
-            const float h1 = ok ? H1[row * kMlpH + i] : 0.f;
-            dz1s[threadIdx.x][i] = a * (1.f - h1 * h1);
+        for (int e = t; e < kBwdRows * kMlpIn; e += 256) {
+            const int64_t idx = row0 * kMlpIn + e;
+            xs[e] = idx < n * kMlpIn ? X[idx] : 0.f;
+        }
+        for (int e = t; e < kBwdRows * kMlpOut; e += 256) {
+            const int64_t idx = row0 * kMlpOut + e;
+            dOs[e] = idx < n * kMlpOut ? dO[idx] : 0.f;
+        }
+        __syncthreads();
+        {  // four threads per row: dz2 in full, a quarter of dz1 each
+            const int r = t >> 2, q = t & 3;
+            const float d0 = dOs[r * kMlpOut], d1 = dOs[r * kMlpOut + 1];
+            float dz2[kMlpH];
+#pragma unroll
+            for (int j = 0; j < kMlpH; ++j) {
+                const float h2 = h2s[r * kBwdStride + j];
+                dz2[j] = (d0 * w3[j] + d1 * w3[kMlpH + j]) * (1.f - h2 * h2);
+            }
+#pragma unroll
+            for (int j = 0; j < kMlpH; ++j)  // compile-time index into dz2: no register-array spill
+                if ((j >> 4) == q) dz2s[r * kBwdStride + j] = dz2[j];
+            float a[kMlpH / 4];  // dz1 for i = 16q .. 16q + 15: four 16-byte LDS reads of W2 per j
+#pragma unroll
+            for (int ii = 0; ii < kMlpH / 4; ++ii) a[ii] = 0.f;
+#pragma unroll
+            for (int j = 0; j < kMlpH; ++j) {
+                const float4* wr = reinterpret_cast<const float4*>(w2 + j * kMlpH + q * (kMlpH / 4));
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float4 wv = wr[v];
+                    a[4 * v] = fmaf(dz2[j], wv.x, a[4 * v]);
+                    a[4 * v + 1] = fmaf(dz2[j], wv.y, a[4 * v + 1]);
+                    a[4 * v + 2] = fmaf(dz2[j], wv.z, a[4 * v + 2]);
+                    a[4 * v + 3] = fmaf(dz2[j], wv.w, a[4 * v + 3]);
+                }
+            }
+#pragma unroll
+            for (int ii = 0; ii < kMlpH / 4; ++ii) {
+                const int i = q * (kMlpH / 4) + ii;
+                const float h1 = h1s[r * kBwdStride + i];
+                dz1s[r * kBwdStride + i] = a[ii] * (1.f - h1 * h1);
+            }
+        }
+        __syncthreads();
+        for (int r = 0; r < kBwdRows; ++r) {  // rows in order
+            const float4 dz = *reinterpret_cast<const float4*>(dz2s + r * kBwdStride + j0);
+            const float4 hv = *reinterpret_cast<const float4*>(h1s + r * kBwdStride + i0);
+            const float dzv[4] = {dz.x, dz.y, dz.z, dz.w}, hh[4] = {hv.x, hv.y, hv.z, hv.w};
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = fmaf(dzv[a], hh[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const int p = t + 256 * m;
+            if (p < kBwdOther)
+                for (int r = 0; r < kBwdRows; ++r)
+                    oacc[m] += bwd_other_term(p, r, dz1s, dz2s, xs, dOs, h2s);
         }
     }
-    __syncthreads();
-    const int nr = (int)min<int64_t>(kBwdRows, n - row0);
     float* gp = gpart + (size_t)blockIdx.x * kMlpParams;
-    // every thread owns some parameter entries and sums over the block's rows in order
-    for (int p = threadIdx.x; p < kMlpParams; p += 256) {
-        double acc = 0.0;
-        if (p < kOffB1) {  // W1[j][i] += dz1[j] x[i]
-            const int j = p / kMlpIn, i = p % kMlpIn;
-            for (int r = 0; r < nr; ++r) acc += (double)dz1s[r][j] * X[(row0 + r) * kMlpIn + i];
-        } else if (p < kOffW2) {
-            const int j = p - kOffB1;
-            for (int r = 0; r < nr; ++r) acc += dz1s[r][j];
-        } else if (p < kOffB2) {  // W2[j][i] += dz2[j] h1[i]
-            const int q = p - kOffW2, j = q / kMlpH, i = q % kMlpH;
-            for (int r = 0; r < nr; ++r) acc += (double)dz2s[r][j] * H1[(row0 + r) * kMlpH + i];
-        } else if (p < kOffW3) {
-            const int j = p - kOffB2;
-            for (int r = 0; r < nr; ++r) acc += dz2s[r][j];
-        } else if (p < kOffB3) {  // W3[o][j] += dO[o] h2[j]
-            const int q = p - kOffW3, o = q / kMlpH, j = q % kMlpH;
-            for (int r = 0; r < nr; ++r) acc += (double)dO[(row0 + r) * 2 + o] * H2[(row0 + r) * kMlpH + j];
-        } else {
-            const int o = p - kOffB3;
-            for (int r = 0; r < nr; ++r) acc += dO[(row0 + r) * 2 + o];
-        }
-        gp[p] = (float)acc;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gp[kOffW2 + (j0 + a) * kMlpH + i0 + b] = acc[a][b];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const int p = t + 256 * m;
+        if (p < kBwdOther) gp[bwd_other_offset(p)] = oacc[m];
     }
 }
 
@@ -448,7 +546,8 @@ __global__ void __launch_bounds__(256) k_grad_reduce(const float* __restrict__ g
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= kMlpParams) return;
     double a = 0.0;
-    for (int b = 0; b < nb; ++b) a += gpart[(size_t)b * kMlpParams + p];
+#pragma unroll 8
+    for (int b = 0; b < nb; ++b) a += gpart[(size_t)b * kMlpParams + p];  // block order; loads run ahead
     grad[p] = (float)a;
 }
 
