@@ -383,13 +383,15 @@ __global__ void __launch_bounds__(256) k_mlp_loss(const float* __restrict__ O, c
 }
 
 // Backward pass. Block b walks kBwdChunks chunks of kBwdRows consecutive rows (kBwdBlockRows in all).
-// Per chunk the rows' hidden activations, inputs and output gradients are staged in LDS; four threads
-// per row form dz2 = (dO W3) (1 - h2^2) and 16 entries each of dz1 = (dz2 W2) (1 - h1^2). Every thread
+// Per chunk the rows' hidden activations, inputs and output gradients are staged in LDS; eight threads
+// per row form 8 entries each of dz2 = (dO W3) (1 - h2^2) and then of dz1 = (dz2 W2) (1 - h1^2). Every thread
 // then adds, rows in order, its 4 x 4 tile of dW2 = sum_r dz2[r] h1[r]^T and up to three of the other
 // 642 parameters to register accumulators. The block's partial gradient (float) goes to gpart[b];
 // k_grad_reduce adds the partials in block order, in double. Activations are column-major (H[j * n + row]).
-constexpr int kBwdRows = 64;
-constexpr int kBwdChunks = 8;
+constexpr int kBwdRows = 32;
+constexpr int kBwdChunks = 16;
+constexpr int kBwdTpr = 256 / kBwdRows;  // threads per row in the delta phase
+constexpr int kBwdPer = kMlpH / kBwdTpr;  // dz1 entries per thread
 constexpr int kBwdBlockRows = kBwdRows * kBwdChunks;
 constexpr int kBwdStride = kMlpH + 4;  // LDS row stride: 16-byte aligned rows for the tile loads
 constexpr int kBwdOther = kMlpParams - kMlpH * kMlpH;  // W1, b1, b2, W3, b3
@@ -478,42 +480,42 @@ __global__ void __launch_bounds__(256) k_mlp_backward(const float* __restrict__ 
             dOs[e] = idx < n * kMlpOut ? dO[idx] : 0.f;
         }
         __syncthreads();
-        {  // four threads per row: dz2 in full, a quarter of dz1 each
-            const int r = t >> 2, q = t & 3;
+        {  // kBwdTpr threads per row, kBwdPer entries each: first dz2, then (after the barrier) dz1
+            const int r = t / kBwdTpr, q = t % kBwdTpr;
             const float d0 = dOs[r * kMlpOut], d1 = dOs[r * kMlpOut + 1];
-            float dz2[kMlpH];
 #pragma unroll
-            for (int j = 0; j < kMlpH; ++j) {
+            for (int jj = 0; jj < kBwdPer; ++jj) {
+                const int j = q * kBwdPer + jj;
                 const float h2 = h2s[r * kBwdStride + j];
-                dz2[j] = (d0 * w3[j] + d1 * w3[kMlpH + j]) * (1.f - h2 * h2);
+                dz2s[r * kBwdStride + j] = (d0 * w3[j] + d1 * w3[kMlpH + j]) * (1.f - h2 * h2);
             }
+            __syncthreads();
+            float a[kBwdPer];
 #pragma unroll
-            for (int j = 0; j < kMlpH; ++j)  // compile-time index into dz2: no register-array spill
-                if ((j >> 4) == q) dz2s[r * kBwdStride + j] = dz2[j];
-            float a[kMlpH / 4];  // dz1 for i = 16q .. 16q + 15: four 16-byte LDS reads of W2 per j
-#pragma unroll
-            for (int ii = 0; ii < kMlpH / 4; ++ii) a[ii] = 0.f;
-#pragma unroll
+            for (int ii = 0; ii < kBwdPer; ++ii) a[ii] = 0.f;
+#pragma unroll 8
             for (int j = 0; j < kMlpH; ++j) {
-                const float4* wr = reinterpret_cast<const float4*>(w2 + j * kMlpH + q * (kMlpH / 4));
+                const float dz = dz2s[r * kBwdStride + j];
+                const float4* wr = reinterpret_cast<const float4*>(w2 + j * kMlpH + q * kBwdPer);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
+                for (int v = 0; v < kBwdPer / 4; ++v) {
                     const float4 wv = wr[v];
-                    a[4 * v] = fmaf(dz2[j], wv.x, a[4 * v]);
-                    a[4 * v + 1] = fmaf(dz2[j], wv.y, a[4 * v + 1]);
-                    a[4 * v + 2] = fmaf(dz2[j], wv.z, a[4 * v + 2]);
-                    a[4 * v + 3] = fmaf(dz2[j], wv.w, a[4 * v + 3]);
+                    a[4 * v] = fmaf(dz, wv.x, a[4 * v]);
+                    a[4 * v + 1] = fmaf(dz, wv.y, a[4 * v + 1]);
+                    a[4 * v + 2] = fmaf(dz, wv.z, a[4 * v + 2]);
+                    a[4 * v + 3] = fmaf(dz, wv.w, a[4 * v + 3]);
                 }
             }
 #pragma unroll
-            for (int ii = 0; ii < kMlpH / 4; ++ii) {
-                const int i = q * (kMlpH / 4) + ii;
+            for (int ii = 0; ii < kBwdPer; ++ii) {
+                const int i = q * kBwdPer + ii;
                 const float h1 = h1s[r * kBwdStride + i];
                 dz1s[r * kBwdStride + i] = a[ii] * (1.f - h1 * h1);
             }
         }
         __syncthreads();
-        for (int r = 0; r < kBwdRows; ++r) {  // rows in order
+#pragma unroll 4
+        for (int r = 0; r < kBwdRows; ++r) {  // rows in order (a full unroll would hoist every row's loads)
             const float4 dz = *reinterpret_cast<const float4*>(dz2s + r * kBwdStride + j0);
             const float4 hv = *reinterpret_cast<const float4*>(h1s + r * kBwdStride + i0);
             const float dzv[4] = {dz.x, dz.y, dz.z, dz.w}, hh[4] = {hv.x, hv.y, hv.z, hv.w};
@@ -526,6 +528,7 @@ __global__ void __launch_bounds__(256) k_mlp_backward(const float* __restrict__ 
         for (int m = 0; m < 3; ++m) {
             const int p = t + 256 * m;
             if (p < kBwdOther)
+#pragma unroll 4
                 for (int r = 0; r < kBwdRows; ++r)
                     oacc[m] += bwd_other_term(p, r, dz1s, dz2s, xs, dOs, h2s);
         }
