@@ -177,8 +177,14 @@ __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
         if (P % NT == 0 || r < P) {
             const int li = (r / NX) * RS + r % NX;
             const su3<T> g = g_from_packed(buf[li], buf[PL + li], buf[2 * PL + li], buf[3 * PL + li], exact != 0);
+            // float: streaming stores of g (2 us faster at 32^4, no cost in the update that reads it)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) G[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
+            for (int k = 0; k < 6; ++k) {
+                if constexpr (sizeof(T) == 4)
+                    nt_store(G + (size_t)k * gps + base + r, g.e[k / 3][k % 3]);
+                else
+                    G[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
+            }
         }
     }
 }

@@ -68,7 +68,12 @@ def test_mixed_stops_in_float_when_tolerance_is_loose():
     res = fx.fix_until(1e-6, 5000)
     assert res.status == gf.GF_OK and res.theta < 1e-6 and res.phase == 0
     ug = links.cpu().numpy()
-    assert abs(landau.theta(ug) - res.theta) < 1e-6 * res.theta + 1e-12
+    # res.theta sums (in double) a divergence formed in float from the float links; the oracle
+    # re-measures the returned links in double. Float rounding of the links and of the divergence's eight-term sums moves each
+    # element of Delta by ~1e-7 against |Delta| ~ 5e-4 at theta ~ 1e-6; uncorrelated over the
+    # 9 * 8^4 elements that shifts theta by ~ 2 * (1e-7 / 5e-4) / sqrt(3.7e4) ~ 2e-6 relative.
+    # The bound is ten times that.
+    assert abs(landau.theta(ug) - res.theta) < 2e-5 * res.theta
 
 
 @pytest.mark.parametrize("precision", ["fp64_18", "fp64_12", "fp32_12"])
