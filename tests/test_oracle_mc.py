@@ -1,6 +1,6 @@
 """Pins of the Monte Carlo generator oracle (heatbath, over-relaxation, multi-hit) on the CPU.
 
-* Philox4x32-10 against the published known-answer vectors.
+* Philox4x32-10 against the published known-answer vectors (tests/golden/philox4x32_10_kat.txt).
 * The Kennedy-Pendleton sampler against the exact moments of sqrt(1 - x^2) e^{alpha x}.
 * The staple sum against the plaquette (every plaquette is counted once by each of its four links).
 * Over-relaxation leaves the action unchanged.
@@ -14,6 +14,7 @@ import pytest
 import scipy.integrate
 import scipy.special
 
+import golden_data
 from oracle import mc, observables, su3
 from paper_1208_1186_amd import synth
 
@@ -23,12 +24,7 @@ def _unit(dims):
     return np.broadcast_to(np.eye(3, dtype=np.complex128), shp + (4, 3, 3)).copy()
 
 
-@pytest.mark.parametrize("ctr,key,want", [
-    ([0, 0, 0, 0], [0, 0], [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]),
-    ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2, [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]),
-    ([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0],
-     [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1]),
-])
+@pytest.mark.parametrize("ctr,key,want", golden_data.philox_kat())
 def test_philox_known_answers(ctr, key, want):
     got = mc.philox4x32_10(np.array(ctr, dtype=np.uint64), np.array(key, dtype=np.uint64))
     assert [int(v) for v in got] == want
