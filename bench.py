@@ -34,13 +34,14 @@ def kernel_bytes(name, vol, L, S, nblk):
     W = 8  # reals per site of the packed divergence (4 complex fields)
     links = 4 * L * S * vol
     field = W * S * vol
+    gauge = 12 * S * vol  # rows 1-2 of g(x)
     return {
-        "update_measure": 2 * links + 2 * field,  # read U, (alpha/2)Delta~; write U', Delta(U')
-        "update": 2 * links + field,           # read U and (alpha/2)Delta~, write U
+        "update_measure": 2 * links + gauge + field,  # read U and g; write U' and Delta(U')
+        "update": 2 * links + field,           # read U and (alpha/2)Delta~ (g formed in place), write U
         "divergence": links + field,           # read U, write Delta
         "fft_xy_fwd": 2 * field,
         "fft_zt_filter": 2 * field,
-        "fft_xy_inv": 2 * field,
+        "fft_xy_inv": field + gauge,           # read (alpha/2)Delta~, write g
         "finalize": 16 * nblk,
     }[name]
 
