@@ -222,3 +222,26 @@ def test_packed_four_field_filter_equivalence():
     rebuilt[..., 1, 1] = 1j * zt[..., 3].imag
     rebuilt[..., 2, 2] = -1j * (zt[..., 3].real + zt[..., 3].imag)
     assert np.max(np.abs(rebuilt - dt)) < 1e-14
+
+
+def test_global_rotation_covariance_with_exact_exponential():
+    """U -> W U W^dag for one W everywhere: Delta -> W Delta W^dag, the filter is linear and exp is
+    covariant, so theta and F agree along the whole trajectory; a transposed or daggered operand
+    anywhere in the update breaks this. Gram-Schmidt reunitarisation of 1 + X is not covariant, so
+    the default update's trajectories part (by more than 1e-3 in theta here)."""
+    u = synth.make_config((6, 4, 4, 4), 22)
+    w = synth.haar_su3((), np.random.default_rng(23))
+    uw = np.einsum("ij,...jk,lk->...il", w, u, w.conj())
+    for exact in (True, False):
+        a, b = u, uw
+        worst = 0.0
+        for _ in range(8):
+            a, *_ = landau.fa_step(a, ALPHA, exact_exp=exact)
+            b, *_ = landau.fa_step(b, ALPHA, exact_exp=exact)
+            worst = max(worst, abs(landau.theta(a) - landau.theta(b)) / landau.theta(a))
+            if exact:
+                assert abs(landau.functional(a) - landau.functional(b)) < 1e-13
+        if exact:
+            assert worst < 1e-11
+        else:
+            assert worst > 1e-3
