@@ -161,6 +161,16 @@ gf_status gf_fix_until_batch(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf
 gf_status gf_fft_tiling(gf_ctx* ctx, int32_t* xy_planes, int32_t* zt_columns);
 
 /*
+ * Override the FFT tiling of this context (a test and measurement aid): one of
+ * the compile-time alternatives for the lattice shape and precision, which
+ * compute the same transforms. GF_EINVAL if the pair is not one of them (the
+ * message lists the planes and columns compiled for the shape), GF_ESTATE
+ * under GF_FLAG_GENERIC_FFT or for a batch context. For GF_MIXED: the active
+ * phase.
+ */
+gf_status gf_set_fft_tiling(gf_ctx* ctx, int32_t xy_planes, int32_t zt_columns);
+
+/*
  * Traversal of the loop kernel (update + divergence + theta/F partials):
  * blocks of 64 sites sweep the (x, y) planes, taking z in groups of z_group
  * planes inside the t loop, so that t neighbours are still cached. gf_init

@@ -116,7 +116,7 @@ void set_xy_tile(Layout& L, int G) {
 void set_zt_tile(Layout& L, int bx) {
     const size_t csz = L.fp32 ? 8 : 16;
     L.bx = bx;
-    L.tsp = L.n[2] * bx + 1;
+    L.tsp = L.n[2] * bx + bx;  // consecutive lanes of a z stage in consecutive LDS slots (see k_fft_zt_ct)
     L.thrB = std::min(1024, std::max(64, round64((bx * L.n[2] * L.n[3] + kEPT - 1) / kEPT)));
     L.ldsB = (size_t)(L.n[2] + L.n[3]) * csz + (size_t)L.n[3] * L.tsp * csz;
 }
@@ -182,7 +182,7 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     for (int b : {16, 8, 4, 2, 1}) {
         if (nx % b != 0) continue;
         const int E = b * nz * nt;
-        const size_t lds = (size_t)(nz + nt) * csz + (size_t)nt * (nz * b + 1) * csz;
+        const size_t lds = (size_t)(nz + nt) * csz + (size_t)nt * (nz * b + b) * csz;
         if (E <= kEPT * 1024 && lds <= 80 * 1024 && (size_t)b * csz <= 128) {
             L.bx = b;
             break;
@@ -1877,6 +1877,26 @@ gf_status gf_fft_tiling(gf_ctx* c, int32_t* xy_planes, int32_t* zt_columns) {
     const gf_ctx* a = active(c);
     *xy_planes = a->L.G;
     *zt_columns = a->L.bx;
+    return GF_OK;
+}
+
+gf_status gf_set_fft_tiling(gf_ctx* c, int32_t xy_planes, int32_t zt_columns) {
+    if (!c) return GF_EINVAL;
+    if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
+    gf_ctx* a = active(c);
+    if (generic_fft(a)) return fail(c, GF_ESTATE, "GF_FLAG_GENERIC_FFT keeps the runtime-shaped kernels' tiling");
+    const std::vector<int> xs = xy_candidates(a->L), zs = zt_candidates(a->L);
+    const bool okx = std::find(xs.begin(), xs.end(), (int)xy_planes) != xs.end();
+    const bool okz = std::find(zs.begin(), zs.end(), (int)zt_columns) != zs.end();
+    if (!okx || !okz) {
+        std::string m = "compiled for this shape: xy_planes {";
+        for (int v : xs) m += " " + std::to_string(v);
+        m += " }, zt_columns {";
+        for (int v : zs) m += " " + std::to_string(v);
+        return fail(c, GF_EINVAL, m + " }");
+    }
+    set_xy_tile(a->L, xy_planes);
+    set_zt_tile(a->L, zt_columns);
     return GF_OK;
 }
 

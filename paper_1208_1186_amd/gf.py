@@ -66,6 +66,7 @@ def _signatures(lib):
         "gf_set_state": (i32, [_P, _P, sz]),
         "gf_fft_tiling": (i32, [_P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "gf_plaquette": (i32, [_P, pd]),
+        "gf_set_fft_tiling": (i32, [_P, i32, i32]),
         "gf_loop_traversal": (i32, [_P, ctypes.POINTER(i32)]),
         "gf_set_loop_traversal": (i32, [_P, i32]),
         "gf_quality": (i32, [_P, pd, pd]),
@@ -232,6 +233,10 @@ def gf_fft_tiling(ctx):
     g, b = ctypes.c_int32(), ctypes.c_int32()
     _check(ctx, load().gf_fft_tiling(ctx, ctypes.byref(g), ctypes.byref(b)))
     return g.value, b.value
+
+
+def gf_set_fft_tiling(ctx, xy_planes, zt_columns):
+    _check(ctx, load().gf_set_fft_tiling(ctx, int(xy_planes), int(zt_columns)))
 
 
 def gf_plaquette(ctx):
@@ -439,6 +444,12 @@ class GaugeFixer:
 
     def set_loop_traversal(self, z_group):
         _check(self.ctx, load().gf_set_loop_traversal(self.ctx, int(z_group)))
+
+    def fft_tiling(self):
+        return gf_fft_tiling(self.ctx)
+
+    def set_fft_tiling(self, xy_planes, zt_columns):
+        gf_set_fft_tiling(self.ctx, xy_planes, zt_columns)
 
     def history(self, n):
         return gf_history(self.ctx, n)

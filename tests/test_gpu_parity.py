@@ -238,6 +238,48 @@ def test_workload_shapes_filter_and_gauge(dims, generic, precision):
     assert np.max(np.abs(out.cpu().numpy() - g_want)) < (1e-13 if precision.startswith("fp64") else 2e-6)
 
 
+def compiled_tilings(fx):
+    """(xy_planes, zt_columns) compiled for the context's shape and precision, from the refusal of an
+    impossible pair (its message lists them)."""
+    with pytest.raises(gf.GfError) as e:
+        fx.set_fft_tiling(0, 0)
+    assert e.value.status == gf.GF_EINVAL
+    msg = str(e.value)
+    xs = [int(v) for v in msg.split("xy_planes {")[1].split("}")[0].split()]
+    zs = [int(v) for v in msg.split("zt_columns {")[1].split("}")[0].split()]
+    return xs, zs
+
+
+@pytest.mark.parametrize("dims", CT_SHAPES + [(48, 48, 48, 8), (32, 32, 32, 32)])
+@pytest.mark.parametrize("precision", ["fp64_18", "fp32_12"])
+def test_every_compiled_tiling(dims, precision):
+    """Every compile-time FFT tiling of the workload shapes, not only the one the autotuner keeps."""
+    u = synth.make_config(dims, 11)
+    d = landau.divergence(u)
+    dt = landau.fa_filter(d)
+    want = 0.5 * ALPHA * dt
+    g_want = landau.gauge_from_delta(dt, ALPHA)
+    fx, _ = fixer_for(u, precision)
+    xs, zs = compiled_tilings(fx)
+    assert fx.fft_tiling()[0] in xs and fx.fft_tiling()[1] in zs
+    d_dev = to_dev(d)
+    out = torch.empty_like(d_dev)
+    fp64 = precision.startswith("fp64")
+    for g in xs:
+        for b in zs:
+            print(f"tiling {dims} {precision} xy={g} zt={b}", flush=True)
+            fx.set_fft_tiling(g, b)
+            assert fx.fft_tiling() == (g, b)
+            gf.gf_stage_filter(fx.ctx, d_dev.data_ptr(), out.data_ptr())
+            assert np.max(np.abs(out.cpu().numpy() - want)) <= (1e-12 if fp64 else 3e-6) * np.max(np.abs(want))
+            gf.gf_stage_gauge(fx.ctx, d_dev.data_ptr(), out.data_ptr())
+            assert np.max(np.abs(out.cpu().numpy() - g_want)) < (1e-13 if fp64 else 2e-6)
+    fxg, _ = fixer_for(u, precision, flags=gf.FLAG_GENERIC_FFT)
+    with pytest.raises(gf.GfError) as e:
+        fxg.set_fft_tiling(xs[0], zs[0])
+    assert e.value.status == gf.GF_ESTATE
+
+
 @pytest.mark.parametrize("dims", CT_SHAPES[:3])
 def test_workload_shapes_loop(dims):
     print(f"workload loop {dims}", flush=True)
