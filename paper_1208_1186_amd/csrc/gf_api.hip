@@ -779,6 +779,7 @@ std::vector<int> zt_candidates(const Layout& L) {
 }
 
 constexpr int kTuneReps = 10;
+constexpr int kTuneRounds = 3;
 
 template <typename T>
 double time_pass(gf_ctx* c, bool xy) {
@@ -856,47 +857,42 @@ gf_status autotune(gf_ctx* c) {
     }
     int bestG = c->L.G, bestB = c->L.bx;
     const std::vector<int> xs = xy_candidates(c->L), zs = zt_candidates(c->L);
-    if (xs.size() > 1) {
-        double best = 1e30;
-        for (int G : xs) {
-            set_xy_tile(c->L, G);
-            const double t = c->L.fp32 ? time_pass<float>(c, true) : time_pass<double>(c, true);
-            if (t < best) {
-                best = t;
-                bestG = G;
+    // Each alternative is timed in kTuneRounds rounds, the order reversed every round so that no place
+    // in the order is favoured (clocks still ramping up, caches still cold), and judged by its best round.
+    auto pick = [&](const std::vector<int>& cand, bool xy, int& bestv) {
+        std::vector<double> t(cand.size(), 1e30);
+        for (int r = 0; r < kTuneRounds; ++r)
+            for (size_t j = 0; j < cand.size(); ++j) {
+                const size_t i = r % 2 == 0 ? j : cand.size() - 1 - j;
+                if (xy)
+                    set_xy_tile(c->L, cand[i]);
+                else
+                    set_zt_tile(c->L, cand[i]);
+                t[i] = std::min(t[i], c->L.fp32 ? time_pass<float>(c, xy) : time_pass<double>(c, xy));
             }
-        }
-    }
+        bestv = cand[std::min_element(t.begin(), t.end()) - t.begin()];
+    };
+    if (xs.size() > 1) pick(xs, true, bestG);
     set_xy_tile(c->L, bestG);
-    if (zs.size() > 1) {
-        double best = 1e30;
-        for (int B : zs) {
-            set_zt_tile(c->L, B);
-            const double t = c->L.fp32 ? time_pass<float>(c, false) : time_pass<double>(c, false);
-            if (t < best) {
-                best = t;
-                bestB = B;
-            }
-        }
-    }
+    if (zs.size() > 1) pick(zs, false, bestB);
     set_zt_tile(c->L, bestB);
     int bestZ = 1;
     const std::vector<int> zbs = zb_candidates(c->L);
     if (zbs.size() > 1) {
         // trial launches: current links -> the other link buffer, divergence -> Q, gauge rows zeroed, a
         // scratch control-block head; D, the control block and the current links are left as they are
-        double best = 1e30;
         (void)hipMemsetAsync(c->tune_ctl, 0, offsetof(Ctl, hist_theta), c->st);
         (void)hipMemsetAsync(c->Gb, 0, 6 * c->L.ps * (c->L.fp32 ? 8 : 16), c->st);
-        for (int z : zbs) {
-            c->L.zb = z;
-            double t = 1e30;
-            GF_DISPATCH(c, time_loop_t, c, t);
-            if (t < best) {
-                best = t;
-                bestZ = z;
+        std::vector<double> tz(zbs.size(), 1e30);
+        for (int r = 0; r < kTuneRounds; ++r)
+            for (size_t j = 0; j < zbs.size(); ++j) {
+                const size_t i = r % 2 == 0 ? j : zbs.size() - 1 - j;
+                c->L.zb = zbs[i];
+                double t = 1e30;
+                GF_DISPATCH(c, time_loop_t, c, t);
+                tz[i] = std::min(tz[i], t);
             }
-        }
+        bestZ = zbs[std::min_element(tz.begin(), tz.end()) - tz.begin()];
     }
     c->L.zb = bestZ;
     (void)hipGetLastError();
