@@ -521,7 +521,12 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
         const T d0 = T(2) * (acc.d0 - tr), d1 = T(2) * (acc.d1 - tr);
         const cx<T> z0 = acc.o01, z1 = acc.o02, z2 = acc.o12;
         const cx<T> out = mu == 0 ? z0 : mu == 1 ? z1 : mu == 2 ? z2 : cx<T>{d0, d1};
-        nt_store(D + (size_t)mu * ps + s, out);
+        // double: streaming stores; float: plain stores, which leave D in the last-level cache for the
+        // (x, y) pass that reads it next (measured 4 us faster there, 2 us slower here in double)
+        if constexpr (sizeof(T) == 4)
+            D[(size_t)mu * ps + s] = out;
+        else
+            nt_store(D + (size_t)mu * ps + s, out);
         if (mu == 0) {
             const double e0 = norm2(z0), e1 = norm2(z1), e2 = norm2(z2);
             const double dd0 = d0, dd1 = d1;
