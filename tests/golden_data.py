@@ -18,9 +18,10 @@ def philox_kat():
 
 
 def fa_landau(name="fa_landau_12x6x4x8_seed11.txt"):
-    """The FA fixture: dict with dims, seed, alpha, input_plaquette, input_F, history [(k, theta, F)],
-    tol, iters_to_tol, final_theta, final_F."""
-    d = {"history": []}
+    """An FA fixture: dict with dims, seed, alpha, eps, input_plaquette, input_F, history [(k, theta, F)],
+    tol, iters_to_tol, final_theta, final_F (and final_plaquette where the file has it)."""
+    from paper_1208_1186_amd import synth
+    d = {"history": [], "eps": synth.EPS_P059}
     with open(os.path.join(GOLDEN, name)) as fh:
         for line in fh:
             if line.startswith("# input:"):
@@ -28,6 +29,9 @@ def fa_landau(name="fa_landau_12x6x4x8_seed11.txt"):
                 d["dims"] = tuple(int(v) for v in cfg[0].strip("(").split(","))
                 d["seed"] = int(cfg[1].strip(", "))
                 d["alpha"] = float(line.split("alpha =")[1])
+                continue
+            if line.startswith("# eps "):
+                d["eps"] = float(line.split("=")[1])
                 continue
             if line.startswith("#") or not line.strip():
                 continue

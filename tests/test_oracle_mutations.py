@@ -279,3 +279,70 @@ def test_mc_pins_catch_mutation(label, monkeypatch):
             caught = True
             break
     assert caught, f"no pin caught: {label}"
+
+
+# ------------------------------------------------------------ observables
+import test_oracle_observables as opins  # noqa: E402
+
+
+def _rect_one_step(u):
+    vol = np.prod(u.shape[:4])
+    tot = 0.0
+    for mu in range(4):
+        for nu in range(4):
+            if mu != nu:
+                um, un = u[..., mu, :, :], u[..., nu, :, :]
+                loop = um @ landau.shift(un, mu, 1) @ su3.dag(landau.shift(um, nu, 1)) @ su3.dag(un)
+                tot += np.sum(su3.trace(loop).real)
+    return float(tot / (36.0 * vol))
+
+
+def _rect_half_norm(u):
+    return 2.0 * _ORIG_RECT(u) - 1.0
+
+
+def _polyakov_no_third(u):
+    return 3.0 * _ORIG_POLY(u)
+
+
+def _polyakov_conjugated(u):
+    return complex(np.conj(_ORIG_POLY(u)))
+
+
+_ORIG_RECT = observables.rectangle
+_ORIG_POLY = observables.polyakov
+
+OBS_MUTATIONS = {
+    "rectangle one step along mu": ("rectangle", _rect_one_step),
+    "rectangle normalised by 18V": ("rectangle", _rect_half_norm),
+    "Polyakov loop without the 1/3": ("polyakov", _polyakov_no_third),
+    "Polyakov loop complex-conjugated": ("polyakov", _polyakov_conjugated),
+    "Polyakov loop from lines multiplied in decreasing t": ("wilson_lines", _lines_reversed),
+}
+
+OBS_PINS = [
+    lambda: opins.test_unit_field(),
+    lambda: opins.test_single_link(0, 0.3),
+    lambda: opins.test_single_link(3, 1.7),
+    lambda: opins.test_abelian_flux(),
+    lambda: opins.test_polyakov_of_temporal_phases(),
+    lambda: opins.test_polyakov_order_of_noncommuting_links(),
+]
+
+
+def test_unmutated_observables_pass_every_pin():
+    for pin in OBS_PINS:
+        pin()
+
+
+@pytest.mark.parametrize("label", sorted(OBS_MUTATIONS))
+def test_observable_pins_catch_mutation(label, monkeypatch):
+    name, fn = OBS_MUTATIONS[label]
+    monkeypatch.setattr(observables, name, fn)
+    failed = 0
+    for pin in OBS_PINS:
+        try:
+            pin()
+        except AssertionError:
+            failed += 1
+    assert failed >= 1, f"no pin caught: {label}"
