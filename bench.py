@@ -108,14 +108,18 @@ def copy_ceiling(torch, dev, mib=1024, reps=10, gf=None):
 TILINGS = {}  # precision -> ((x, y) planes per block, (z, t) columns per block, loop-kernel z group) chosen by the library
 
 
-def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events, only=None):
-    """Time `steps` FA iterations after `warmup`; with_events brackets the kernels named in `only`
-    (all kernels if None) with HIP events on the context's stream."""
+def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events, only=None, full_call=False):
+    """Time `steps` FA iterations after `warmup`: one gf_advance(steps) call, bracketed by device
+    synchronisations (the links stay in the context's working layout, no egress inside the region).
+    with_events brackets the kernels named in `only` (all kernels if None) with HIP events on the
+    context's stream. Returns (seconds, result, kernel times, blocks, egress seconds, full-call seconds):
+    the egress (links written back to the canonical tensor, once per call) is timed on its own, and with
+    full_call a gf_iterate(steps) call (iterations + egress, what a caller of gf_iterate sees) as well."""
     links = u_dev.clone()
     fx = gf.GaugeFixer(links, precision, check_every=max(steps, warmup, 1))
     TILINGS[precision] = tuple(gf.gf_fft_tiling(fx.ctx)) + (fx.loop_traversal(),)
     if warmup:
-        fx.iterate(warmup)
+        fx.advance(warmup)
     torch.cuda.synchronize()
     if with_events:
         if only is None:
@@ -123,16 +127,27 @@ def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events, only=Non
         else:
             gf.gf_set_timing_mask(fx.ctx, only)
     t0 = time.perf_counter()
-    res = fx.iterate(steps)
+    res = fx.advance(steps)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ktimes = gf.gf_kernel_times(fx.ctx) if with_events else None
     if with_events:
         gf.gf_set_timing(fx.ctx, False)
+    t0 = time.perf_counter()
+    fx.sync_links()
+    torch.cuda.synchronize()
+    egress = time.perf_counter() - t0
+    full = None
+    if full_call:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fx.iterate(steps)
+        torch.cuda.synchronize()
+        full = time.perf_counter() - t0
     nblk = (u_dev.shape[0] * u_dev.shape[1] * u_dev.shape[2] * u_dev.shape[3] + 255) // 256
     fx.close()
     del links
-    return dt, res, ktimes, nblk
+    return dt, res, ktimes, nblk, egress, full
 
 
 def time_to_theta(gf, torch, u_dev, precision, tol=1e-15):
@@ -145,6 +160,19 @@ def time_to_theta(gf, torch, u_dev, precision, tol=1e-15):
     dt = time.perf_counter() - t0
     fx.close()
     return dt, r
+
+
+def fp32_theta_floor(gf, torch, u_dev, n=400):
+    """The smallest theta FP32-12 arithmetic reaches on this input (float rounding of the links and of the
+    divergence sets a floor; the mixed scheme hands over to double precision above it)."""
+    import numpy as np
+    links = u_dev.clone()
+    fx = gf.GaugeFixer(links, "fp32_12", check_every=50)
+    fx.advance(n)
+    th, _ = fx.history(n + 1)
+    fx.close()
+    k = int(np.argmin(th))
+    return {"theta_min": float(th[k]), "at_update": k, "updates": n}
 
 
 def mixed_workload(gf, torch, synth, dev, dims=(48, 48, 48, 8)):
@@ -393,6 +421,38 @@ def cpu_baseline(u, budget_s=12.0, workers=None, max_iter=8):
     return n / dt, n, dt, workers
 
 
+def host_info():
+    """The host the oracle runs on: CPU model, logical CPUs, and the CPUs this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = sorted(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        aff = []
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity_cpus": len(aff),
+            "affinity": f"{aff[0]}-{aff[-1]}" if aff and aff == list(range(aff[0], aff[-1] + 1)) else aff}
+
+
+def oracle_iteration_s(synth, dims, eps, workers, n=2):
+    """Seconds per FA iteration of the oracle (divergence, theta, F, filter, g, update) on one input."""
+    from oracle import landau
+    landau.FFT_WORKERS = workers
+    u = synth.make_config(dims, 0, eps)
+    t0 = time.perf_counter()
+    for _ in range(n):
+        u, *_ = landau.fa_step(u, 0.08)
+        landau.theta(u)
+        landau.functional(u)
+    return (time.perf_counter() - t0) / n
+
+
 def cpu_solve_small(synth, dims=(8, 8, 8, 8), workers=1):
     """The oracle's whole solve to theta < 1e-15 on a small lattice (seed 0): seconds and iterations."""
     from oracle import landau
@@ -483,10 +543,12 @@ def main():
     L, S = STORAGE[prec]
     log(f"timing {prec}: warmup {args.warmup}, steps {args.steps}")
     # the timed region: events around the loop kernel only (its duration gives the roofline)
-    dt, res, ktimes_dom, nblk = timed_rate(gf, torch, u_dev, prec, args.steps, args.warmup, with_events=True,
-                                           only=["update_measure"])
+    dt, res, ktimes_dom, nblk, egress_s, full_s = timed_rate(gf, torch, u_dev, prec, args.steps, args.warmup,
+                                                             with_events=True, only=["update_measure"],
+                                                             full_call=True)
     # a second pass with every kernel bracketed, for the per-kernel table
-    _, _, ktimes, _ = timed_rate(gf, torch, u_dev, prec, min(args.steps, 100), args.warmup, with_events=True)
+    _, _, ktimes, _, _, _ = timed_rate(gf, torch, u_dev, prec, min(args.steps, 100), args.warmup,
+                                       with_events=True)
     ms_per_step = 1e3 * dt / args.steps
     rate = args.steps / dt
     b_alg = (8 * L + 8 * 8) * S  # bytes/site/iteration: links read+written once, packed field 8 passes
@@ -522,16 +584,18 @@ def main():
         for p2 in ["fp64_12", "fp32_12"]:
             if p2 == prec:
                 continue
-            d2, r2, _, _ = timed_rate(gf, torch, u_dev, p2, args.steps, args.warmup, with_events=False)
+            d2, r2, _, _, _, _ = timed_rate(gf, torch, u_dev, p2, args.steps, args.warmup, with_events=False)
             L2, S2 = STORAGE[p2]
             extras[f"{p2}_it_per_s"] = round(args.steps / d2, 1)
             extras[f"{p2}_model_GBps"] = round((8 * L2 + 64) * S2 * vol * args.steps / d2 / 1e9, 1)
             log(f"{p2}: {args.steps / d2:.1f} it/s")
+        extras["fp32_12_theta_floor"] = fp32_theta_floor(gf, torch, u_dev)
+        log(f"fp32_12 theta floor: {extras['fp32_12_theta_floor']}")
         # FP32-12 on 32^3 x 64: 403 MB of links, beyond the 256 MB last-level cache that the 32^4 FP32-12
         # working set (201 MB of links) fits in
         dims_c = (32, 32, 32, 64)
         u_c = torch.from_numpy(synth.make_config(dims_c, 0, synth.EPS_P059)).to(dev)
-        d3, _, _, _ = timed_rate(gf, torch, u_c, "fp32_12", args.steps, args.warmup, with_events=False)
+        d3, _, _, _, _, _ = timed_rate(gf, torch, u_c, "fp32_12", args.steps, args.warmup, with_events=False)
         vol_c = 32 * 32 * 32 * 64
         extras["fp32_12_32x32x32x64_it_per_s"] = round(args.steps / d3, 1)
         extras["fp32_12_32x32x32x64_model_GBps"] = round((8 * 12 + 64) * 4 * vol_c * args.steps / d3 / 1e9, 1)
@@ -559,11 +623,14 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
+        host = host_info()
         crate, cn, cdt, workers = cpu_baseline(u)
         cpu = {"value": round(crate, 4), "unit": "FA iterations/s", "cores": workers, "kind": "oracle",
-               "sample": f"first {cn} FA iterations of {nx}x{ny}x{nz}x{nt} seed 0 (FP64 NumPy, scipy.fft "
-                         f"workers={workers}), {cdt:.1f}s"}
-        log(f"oracle: {crate:.3f} it/s over {cn} iterations")
+               "sample": f"first {cn} FA iterations of {nx}x{ny}x{nz}x{nt} seed 0 (FP64 NumPy; scipy.fft "
+                         f"workers={workers}, the matrix arithmetic on one thread), {cdt:.1f}s",
+               **host}
+        log(f"oracle: {crate:.3f} it/s over {cn} iterations on {host['cpu_model']} "
+            f"({host['os_cpu_count']} CPUs, affinity {host['affinity_cpus']})")
         if not args.no_extras:
             # numpy's own matrix arithmetic is single-threaded here; only scipy.fft takes the workers
             r1, n1, d1, _ = cpu_baseline(u, budget_s=8.0, workers=1, max_iter=3)
@@ -573,7 +640,29 @@ def main():
                                                          f"(scipy.fft workers=1), {d1:.1f}s"}
             ts, its = cpu_solve_small(synth, workers=1)
             extras["cpu_oracle_solve_8x8x8x8"] = {"s_to_theta_1e-15": round(ts, 2), "iters": its, "cores": 1}
-            log(f"oracle 1 thread: {r1:.3f} it/s; 8^4 solve {ts:.2f}s ({its} iterations)")
+            ts16, its16 = cpu_solve_small(synth, dims=(16, 16, 16, 16), workers=workers)
+            extras["cpu_oracle_solve_16x16x16x16"] = {"s_to_theta_1e-15": round(ts16, 2), "iters": its16,
+                                                      "cores": workers}
+            log(f"oracle 1 thread: {r1:.3f} it/s; 8^4 solve {ts:.2f}s ({its} iterations); "
+                f"16^4 solve {ts16:.2f}s ({its16} iterations, {workers} FFT workers)")
+            # time to theta < 1e-15 on the host, extrapolated: the GPU's FP64 update count on the same input
+            # (the same algorithm; FP64 counts equal the oracle's, as the parity tests check) times the
+            # oracle's measured seconds per iteration
+            ext = {}
+            it32 = extras.get("fp64_18_iters_to_theta_1e-15")
+            if it32:
+                per = cdt / cn
+                ext["32x32x32x32"] = {"s_per_iteration": round(per, 3), "iters": it32,
+                                      "s_to_theta_1e-15": round(per * it32, 1), "cores": workers}
+            mx = extras.get("mixed_48x48x48x8", {}).get("fp64_18")
+            if mx:
+                per48 = oracle_iteration_s(synth, (48, 48, 48, 8), synth.EPS_P060, workers)
+                ext["48x48x48x8"] = {"s_per_iteration": round(per48, 3), "iters": mx["iters"],
+                                     "s_to_theta_1e-15": round(per48 * mx["iters"], 1), "cores": workers}
+            if ext:
+                extras["cpu_oracle_time_to_theta_extrapolated"] = {
+                    "kind": "extrapolation: GPU FP64-18 update count x oracle seconds per iteration", **ext}
+                log(f"oracle time to theta (extrapolated): {ext}")
         if not args.no_extras and not args.no_wilson:
             extras["wilson_cpu_baseline"] = cpu_baseline_wilson(u)
             log(f"oracle correlator: {extras['wilson_cpu_baseline']['sample']}")
@@ -594,7 +683,14 @@ def main():
         "config": {"workload": f"{nx}x{ny}x{nz}x{nt} SU(3) Landau FA steepest descent, {prec} link storage, "
                                f"seed 0, plaquette~0.59, Haar gauge transform, alpha 0.08",
                    "lattice": list(dims), "storage": prec, "alpha": 0.08},
+        "timing": "value = steps / wall time of one gf_advance(steps) call between device synchronisations "
+                  "(steps FA iterations, one theta/F read-back, links left in the working layout); "
+                  "egress_ms = writing the links back to the canonical tensor (once per call); "
+                  "full_call_it_per_s = steps / (gf_iterate(steps): the iterations plus that egress)",
+        "egress_ms": round(1e3 * egress_s, 4),
+        "full_call_it_per_s": round(args.steps / full_s, 2),
         "hbm_model_GBps": round(b_alg * vol * rate / 1e9, 1),
+        "hbm_model_frac": round(b_alg * vol * rate / 1e9 / HBM_PEAK_GBS, 4),
         "hbm_model_bytes_per_site": b_alg,
         "roofline": roofline,
         "cpu_baseline": cpu,

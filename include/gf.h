@@ -89,7 +89,8 @@ typedef struct {
     double theta;          /* quality of the current links */
     double F;              /* functional of the current links */
     int32_t phase;         /* 0: FP32 bulk (GF_MIXED only), 1: FP64 */
-    int32_t fallbacks;     /* reserved */
+    int32_t fallbacks;     /* GF_FLAG_LEARNED: learned updates rejected by the device guard and
+                              replaced by a plain FA update (0 otherwise) */
     double seconds;        /* wall time of the call */
 } gf_result;
 
@@ -109,6 +110,15 @@ gf_status gf_init(gf_ctx** ctx, const gf_params* params, void* d_links,
 
 /* Apply exactly n >= 0 updates (no stopping test); result holds theta, F after them. */
 gf_status gf_iterate(gf_ctx* ctx, int64_t n, gf_result* result);
+
+/*
+ * gf_iterate without the egress: exactly n >= 0 updates (Section 1: one FA iteration each), leaving the
+ * links in the context's working layout; the caller's d_links are NOT written. gf_get_links(ctx, d_links)
+ * writes them out, and so does the next gf_iterate or gf_fix_until. For callers that only read theta and
+ * F between calls (and for timing the iteration itself). Plain contexts only: GF_MIXED and batch
+ * contexts return GF_ESTATE and change nothing.
+ */
+gf_status gf_advance(gf_ctx* ctx, int64_t n, gf_result* result);
 
 /*
  * Iterate until theta < theta_tol (theta measured before each update), or
@@ -171,13 +181,17 @@ gf_status gf_fft_tiling(gf_ctx* ctx, int32_t* xy_planes, int32_t* zt_columns);
 gf_status gf_set_fft_tiling(gf_ctx* ctx, int32_t xy_planes, int32_t zt_columns);
 
 /*
- * Traversal of the loop kernel (update + divergence + theta/F partials):
- * blocks of 64 sites sweep the (x, y) planes, taking z in groups of z_group
- * planes inside the t loop, so that t neighbours are still cached. gf_init
- * times the groupings that fit the shape (1, and 2, 4, 8 where they divide
- * Nz) on the first context of a shape and precision in the process and keeps
- * the fastest. Partials are summed by site block, so every grouping gives
- * bitwise the same results. gf_set_loop_traversal overrides the choice for
+ * Traversal of the loop kernel (update + divergence + theta/F partials).
+ * z_group >= 1: blocks of 64 sites sweep the (x, y) planes, taking z in groups
+ * of z_group planes inside the t loop, so that t neighbours are still cached.
+ * z_group == 0 (t-march): each block owns 64 sites of the (x, y, z) volume and
+ * steps through t, keeping its own updated U_t of one step for the divergence
+ * of the next, so U_t(x - t) and g(x - t) are not fetched again. gf_init times
+ * the traversals that fit the shape (1; 2, 4, 8 where they divide Nz and 64
+ * divides Nx*Ny; 0 where 64 divides Nx*Ny*Nz, Nt >= 4 and there are >= 32
+ * blocks) on the first context of a shape and precision in the process and
+ * keeps the fastest. Partials are summed by site block, so every traversal
+ * gives bitwise the same results. gf_set_loop_traversal overrides the choice for
  * this context (a test and measurement aid); GF_EINVAL if z_group is not one
  * of the candidates. For GF_MIXED: the active phase.
  */

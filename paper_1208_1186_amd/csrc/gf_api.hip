@@ -80,7 +80,8 @@ struct Layout {
     size_t ps;        // plane stride (elements) of every SoA array
     int nblk;         // blocks of the one-site-per-thread kernels
     int nblk_fused;   // blocks of the loop kernel (kFusedSites sites each)
-    int zb = 1;       // loop-kernel traversal: z planes per group inside the t loop (autotuned)
+    int zb = 1;       // loop-kernel traversal: z planes per group inside the t loop, or 0: blocks step
+                      // through t (autotuned)
     bool fp32;
     int ne;           // 9 or 6 complex entries stored per link
     // forward / inverse (x, y) pass over single-field planes
@@ -371,7 +372,9 @@ void tstart(gf_ctx* c, int kid) {
     if (c->ev.empty()) {
         c->ev.resize(2 * kEventPairs);
         c->ev_kid.resize(kEventPairs);
-        for (auto& e : c->ev) (void)hipEventCreate(&e);
+        // timing only: no system-scope fence (cache write-back) when an event completes, which would
+        // slow the kernels that follow it
+        for (auto& e : c->ev) (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     }
     if (c->npend == kEventPairs) {
         (void)hipStreamSynchronize(c->st);
@@ -570,13 +573,19 @@ void launch_update_t(gf_ctx* c) {
     tstop(c);
 }
 
+// Blocks of the loop kernel: one per site block, or (t-march) one per 64-site run of the (x, y, z) volume.
+int loop_blocks(const Layout& L) {
+    return L.zb == 0 ? (int)(L.vol / L.n[3] / kFusedSites) : L.nblk_fused;
+}
+
 // Loop kernel from k to k + 1 updates: links Lb[k] -> Lb[k+1], divergence -> D.
 template <typename T, int NE>
 void launch_fused_t(gf_ctx* c, long long k) {
     const Layout& L = c->L;
     const int a = (int)(k & 1);
     tstart(c, GF_K_UPDATE_MEASURE);
-    hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused, c->nact), dim3(kFusedThreads), 0, c->st,
+    auto kern = L.zb == 0 ? k_update_measure<T, NE, true> : k_update_measure<T, NE, false>;
+    hipLaunchKernelGGL(kern, dim3(loop_blocks(L), c->nact), dim3(kFusedThreads), 0, c->st,
                        links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
                        cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl, reinterpret_cast<cx<T>*>(c->Acc), bt(c),
                        L.zb);
@@ -784,7 +793,9 @@ constexpr int kTuneRounds = 3;
 template <typename T>
 double time_pass(gf_ctx* c, bool xy) {
     hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return 1e30;
+    if (hipEventCreateWithFlags(&a, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&b, hipEventDisableSystemFence) != hipSuccess)
+        return 1e30;
     auto run = [&]() {
         if (xy)
             launch_xy<T, false>(c, c->D, c->Q, 1, false);
@@ -805,9 +816,13 @@ double time_pass(gf_ctx* c, bool xy) {
     return ms;
 }
 
-// z groupings the loop kernel can take on this shape (1 always).
+// Traversals the loop kernel can take on this shape: z groupings (1 always), and 0 (blocks step through
+// t) when the (x, y, z) volume is a multiple of 64 sites, t has at least 4 steps and there are at least
+// 32 blocks.
 std::vector<int> zb_candidates(const Layout& L) {
     std::vector<int> v{1};
+    const int64_t vs = (int64_t)L.n[0] * L.n[1] * L.n[2];
+    if (vs % kFusedSites == 0 && L.n[3] >= 4 && vs / kFusedSites >= 32) v.push_back(0);
     if ((L.n[0] * L.n[1]) % kFusedSites != 0) return v;
     for (int z : {2, 4, 8})
         if (L.n[2] % z == 0 && L.n[2] > z) v.push_back(z);
@@ -819,14 +834,17 @@ void time_loop_t(gf_ctx* c, double& ms_out) {
     const Layout& L = c->L;
     const int a = cur(c);
     auto run = [&]() {
-        hipLaunchKernelGGL((k_update_measure<T, NE>), dim3(L.nblk_fused), dim3(kFusedThreads), 0, c->st,
+        auto kern = L.zb == 0 ? k_update_measure<T, NE, true> : k_update_measure<T, NE, false>;
+        hipLaunchKernelGGL(kern, dim3(loop_blocks(L)), dim3(kFusedThreads), 0, c->st,
                            links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
                            cxp<T>(c->Q), L.ps, c->geom, c->part, c->tune_ctl, static_cast<cx<T>*>(nullptr),
                            Batch{nullptr, 0}, L.zb);
     };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ms_out = 1e30;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return;
+    if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess)
+        return;
     run();
     run();
     (void)hipEventRecord(e0, c->st);
@@ -1708,6 +1726,17 @@ gf_status gf_iterate(gf_ctx* c, int64_t n, gf_result* r) {
     }
 }
 
+gf_status gf_advance(gf_ctx* c, int64_t n, gf_result* r) {
+    if (!c) return GF_EINVAL;
+    if (c->batch || c->L.mixed) return fail(c, GF_ESTATE, "gf_advance takes plain (non-mixed, non-batch) contexts");
+    if (n < 0) return fail(c, GF_EINVAL, "n must be >= 0");
+    try {
+        return run_loop(c, -1.0, n, r, false);
+    } catch (...) {
+        return fail(c, GF_EINVAL, "unexpected host exception");
+    }
+}
+
 gf_status gf_fix_until(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
     if (!c) return GF_EINVAL;
     if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
@@ -1909,7 +1938,9 @@ gf_status gf_set_loop_traversal(gf_ctx* c, int32_t z_group) {
     gf_ctx* a = active(c);
     const std::vector<int> v = zb_candidates(a->L);
     if (std::find(v.begin(), v.end(), (int)z_group) == v.end())
-        return fail(c, GF_EINVAL, "z_group must be 1 or a divisor 2, 4, 8 of Nz below Nz (and 64 must divide Nx*Ny)");
+        return fail(c, GF_EINVAL,
+                    "z_group must be 1, a divisor 2, 4, 8 of Nz below Nz (64 dividing Nx*Ny), or 0 (t-march: 64 "
+                    "dividing Nx*Ny*Nz, Nt >= 4, at least 32 blocks)");
     a->L.zb = z_group;
     return GF_OK;
 }

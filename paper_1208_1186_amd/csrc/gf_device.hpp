@@ -20,26 +20,30 @@ template <typename T>
 __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+// Every product of two complex numbers is written with explicit fused multiply-adds (one product
+// rounded, the other fused), so no result depends on where the compiler chooses to contract: the loop
+// kernel forms the same updated link at two places (a lane's own link, and the back neighbour's link
+// for the divergence) and needs both to give the same bits.
 template <typename T>
 __device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+    return {fma(a.re, b.re, -(a.im * b.im)), fma(a.re, b.im, a.im * b.re)};
 }
 // a * conj(b)
 template <typename T>
 __device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
-    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+    return {fma(a.re, b.re, a.im * b.im), fma(a.im, b.re, -(a.re * b.im))};
 }
 // conj(a) * conj(b)
 template <typename T>
 __device__ __forceinline__ cx<T> cmulcc(cx<T> a, cx<T> b) {
-    return {a.re * b.re - a.im * b.im, -(a.re * b.im + a.im * b.re)};
+    return {fma(a.re, b.re, -(a.im * b.im)), -fma(a.re, b.im, a.im * b.re)};
 }
 template <typename T>
 __device__ __forceinline__ cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
 template <typename T>
 __device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.re * s, a.im * s}; }
 template <typename T>
-__device__ __forceinline__ T norm2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ T norm2(cx<T> a) { return fma(a.re, a.re, a.im * a.im); }
 // acc + a*b
 template <typename T>
 __device__ __forceinline__ cx<T> cfma(cx<T> acc, cx<T> a, cx<T> b) {
@@ -113,6 +117,22 @@ __device__ __forceinline__ void reunitarize(su3<T>& m) {
     third_row(m.e[0], m.e[1], m.e[2]);
 }
 
+// Row Gram-Schmidt in double precision whatever the storage type: a float matrix is promoted, projected
+// onto SU(3) in double and rounded back, so the bulk float iterations keep their reunitarisation in FP64.
+template <typename T>
+__device__ __forceinline__ void reunitarize_fp64(su3<T>& m) {
+    if constexpr (sizeof(T) == 8) {
+        reunitarize(m);
+    } else {
+        su3<double> d;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) d.e[k / 3][k % 3] = {(double)m.e[k / 3][k % 3].re, (double)m.e[k / 3][k % 3].im};
+        reunitarize(d);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) m.e[k / 3][k % 3] = {(T)d.e[k / 3][k % 3].re, (T)d.e[k / 3][k % 3].im};
+    }
+}
+
 // c = a * b
 template <typename T>
 __device__ __forceinline__ su3<T> mul(const su3<T>& a, const su3<T>& b) {
@@ -159,6 +179,22 @@ __device__ __forceinline__ su3<T> mul_rows(const su3<T>& a, const su3<T>& b) {
             c.e[i][j] = s;
         }
     return c;
+}
+
+// U'_mu(x) = gl U_mu(x) gr^dag with gl = g(x), gr = g(x + mu): rows 1-2 formed, row 3 rebuilt from
+// unitarity (double), or rows 1-2 re-orthonormalised in double precision (float). The loop kernel calls
+// it for a lane's own link and for the back neighbour's updated link U'_mu(x - mu) (gl = g(x - mu),
+// gr = g(x)); the same inlined code on the same operands gives the same bits as the neighbour's own
+// result, so the divergence is that of the stored links in every traversal.
+template <typename T>
+__device__ __forceinline__ su3<T> updated_link(const su3<T>& gl, const su3<T>& u, const su3<T>& gr) {
+    su3<T> un = mul_adj<T, 2>(mul_rows<T, 2>(gl, u), gr);
+    if constexpr (sizeof(T) == 4) {
+        reunitarize_fp64(un);
+    } else {
+        third_row(un.e[0], un.e[1], un.e[2]);
+    }
+    return un;
 }
 
 // exp(X) of an anti-Hermitian traceless 3x3 matrix in closed form (Cayley-Hamilton): with the
@@ -252,7 +288,7 @@ __device__ __forceinline__ su3<T> g_from_packed(cx<T> z0, cx<T> z1, cx<T> z2, cx
         g.e[1][1] = {T(1), z3.im};
         g.e[1][2] = z2;
     }
-    reunitarize(g);
+    reunitarize_fp64(g);
     return g;
 }
 

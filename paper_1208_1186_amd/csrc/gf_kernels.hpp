@@ -342,8 +342,8 @@ __device__ __forceinline__ su3<T> g_at_packed(const cx<T>* __restrict__ Z, size_
 }
 
 // U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag in place, g = reunitarize(1 + Z(x)) with
-// Z holding (alpha/2) Delta~ packed. Used by the single-stage entry point;
-// float links are re-orthonormalised on write, double links stored as computed.
+// Z holding (alpha/2) Delta~ packed. Used by the single-stage entry point; the
+// arithmetic is the loop kernel's (updated_link).
 template <typename T, int NE>
 __global__ void __launch_bounds__(kSiteThreads) k_update(Links<T, NE> L, const cx<T>* __restrict__ Z, size_t zps,
                                                          Geom g, int exact) {
@@ -353,15 +353,10 @@ __global__ void __launch_bounds__(kSiteThreads) k_update(Links<T, NE> L, const c
     int c[4];
     site_coords(g, s, c);
     const su3<T> g0 = g_at_packed(Z, zps, s, exact != 0);
-    constexpr int NR = NE == 9 ? 3 : 2;
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         const su3<T> g1 = g_at_packed(Z, zps, site_fwd(g, s, c, mu), exact != 0);
-        const su3<T> u = L.load(mu, s);
-        const su3<T> gu = mul_rows<T, NR>(g0, u);
-        su3<T> un = mul_adj<T, NR>(gu, g1);
-        if constexpr (sizeof(T) == 4) reunitarize(un);
-        L.store(mu, s, un);
+        L.store(mu, s, updated_link(g0, L.load(mu, s), g1));
     }
 }
 
@@ -376,13 +371,21 @@ struct AhAcc {
         o01 = o02 = o12 = {T(0), T(0)};
         d0 = d1 = d2 = T(0);
     }
-    __device__ __forceinline__ void add(const su3<T>& x, T sign) {
-        o01 = o01 + cscale(x.e[0][1] - conj(x.e[1][0]), sign);
-        o02 = o02 + cscale(x.e[0][2] - conj(x.e[2][0]), sign);
-        o12 = o12 + cscale(x.e[1][2] - conj(x.e[2][1]), sign);
-        d0 += sign * x.e[0][0].im;
-        d1 += sign * x.e[1][1].im;
-        d2 += sign * x.e[2][2].im;
+    __device__ __forceinline__ void set(const su3<T>& x) {
+        o01 = x.e[0][1] - conj(x.e[1][0]);
+        o02 = x.e[0][2] - conj(x.e[2][0]);
+        o12 = x.e[1][2] - conj(x.e[2][1]);
+        d0 = x.e[0][0].im;
+        d1 = x.e[1][1].im;
+        d2 = x.e[2][2].im;
+    }
+    __device__ __forceinline__ void sub(const AhAcc& b) {
+        o01 = o01 - b.o01;
+        o02 = o02 - b.o02;
+        o12 = o12 - b.o12;
+        d0 -= b.d0;
+        d1 -= b.d1;
+        d2 -= b.d2;
     }
 };
 
@@ -407,56 +410,48 @@ __device__ __forceinline__ double xor_sum4(double v) {
     return __hiloint2double(bh[0], bl[0]) + __hiloint2double(bh[1], bl[1]);
 }
 
-// Reads links Lin and the gauge rows G and writes U' = g U g(x+mu)^dag to
-// Lout, the divergence of U' to D and one FP64 partial (F, theta) per block.
-// Four lanes per site, one direction each: a wave covers 16 consecutive sites
-// x 4 directions, so every load and store is a 16-site run in one plane. Lane
-// mu updates U_mu(x) and forms U'_mu(x - mu) = g(x - mu) U_mu(x - mu) g(x)^dag
-// from the old neighbour link (no thread reads another thread's output, so
-// the step needs every link from HBM once); the four lanes add their
-// anti-Hermitian parts across lanes. All loads are issued before any
-// arithmetic, so a wave waits for one memory round trip. Lin and Lout must differ.
+// Loop kernel: reads links Lin and the gauge rows G and writes U' = g U g(x+mu)^dag to Lout, the
+// divergence of U' to D and one FP64 partial (F, theta) per block of 64 sites. Four lanes per site, one
+// direction each: a wave covers 16 consecutive sites x 4 directions, so every load and store is a
+// 16-site run in one plane. Lane mu updates U_mu(x) and needs U'_mu(x - mu) for the divergence; all
+// loads are issued before any arithmetic, so a wave waits for one memory round trip per site block.
+// Lin and Lout must differ.
+//
+// Traversals (autotuned per shape and precision; partials are stored by site block, so every traversal
+// gives the same bits):
+//  zb >= 1  one block per site block. The blocks sweep each (x, y) plane; with zb > 1 (zb divides Nz,
+//           64 divides the plane) the planes are visited with z in groups of zb inside the t loop,
+//           (z mod zb, t, z / zb), so that a site's t neighbour was read zb planes earlier and may still
+//           be in the XCD's L2. Lane mu forms U'_mu(x - mu) from the old neighbour link and g.
+//  zb == 0  t-march: one block per 64-site run of the (x, y, z) volume, stepping through t. The lane of
+//           direction t keeps the anti-Hermitian part of its own U'_t from the previous step, which is
+//           the U'_t(x - t) of this one, so U_t(x - t) and g(x - t) are never fetched again (except at
+//           the block's first step). The blocks of one XCD (consecutive runs, xcd_remap) hold a slab of
+//           the (x, y, z) volume and step through t together, so the y and z neighbours they read are in
+//           that XCD's L2. Needs Nx Ny Nz to be a multiple of 64.
 constexpr int kFusedThreads = 256;
 constexpr int kFusedSites = kFusedThreads / 4;
 
-// With acc_g set (six planes, ps apart) the lane of direction 0 also
-// accumulates the total gauge transform in place: A(x) <- reunitarize(g(x) A(x)).
-// Traversal: the blocks of 64 sites sweep each (x, y) plane; with zb > 1 (zb divides Nz, 64 divides
-// the plane) the planes are visited with z in groups of zb inside the t loop, (z mod zb, t, z / zb), so
-// that a site's t neighbour was read zb planes earlier instead of Nz and is still in the XCD's L2 (the
-// price: one plane in zb reads its z neighbour from farther back). The autotuner picks zb per shape and
-// precision. Block partials are stored by site block, so the choice does not change any result bit.
 template <typename T, int NE>
-__global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> Lin, Links<T, NE> Lout,
-                                                                  const cx<T>* __restrict__ G, cx<T>* __restrict__ D,
-                                                                  size_t ps, Geom g, double2* __restrict__ part,
-                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g, Batch bt,
-                                                                  int zb) {
-    {
-        const size_t bo = boff(bt);
-        Lin.p = bshift(Lin.p, bo);
-        Lout.p = bshift(Lout.p, bo);
-        G = bshift(G, bo);
-        D = bshift(D, bo);
-        part = bshift(part, bo);
-        ctl = bshift(ctl, bo);
-        acc_g = bshift(acc_g, bo);
-    }
-    if (ctl->done) return;
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int lane = threadIdx.x & 63;
-    const int mu = lane >> 4;
-    int sb = b;  // site block: sites sb*64 .. sb*64 + 63
-    if (zb > 1) {
-        const int bpp = (g.n[0] * g.n[1]) / kFusedSites;
-        const int P = b / bpp, off = b - P * bpp;
-        const int z = P % zb + zb * (P / (zb * g.n[3]));
-        const int t = (P / zb) % g.n[3];
-        sb = (z + g.n[2] * t) * bpp + off;
-    }
-    const int64_t s = (int64_t)sb * kFusedSites + (threadIdx.x >> 6) * 16 + (lane & 15);
-    const bool valid = s < g.vol;
-    double fsum = 0.0, tsum = 0.0;
+struct LoopIO {
+    Links<T, NE> Lin, Lout;
+    const cx<T>* __restrict__ G;
+    cx<T>* __restrict__ D;
+    cx<T>* __restrict__ acc_g;
+    size_t ps;
+};
+
+// One site block: site s of this lane (valid if inside the lattice), direction mu. With keep set
+// (t-march), the lane of direction t stores its own anti-Hermitian part there (an LDS slot of its site),
+// and with reuse (after the block's first step) it takes the back neighbour's from there first. Returns
+// this block's partial sums in thread 0.
+template <typename T, int NE>
+__device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const Geom& g, int64_t s, bool valid,
+                                                int mu, bool reuse, AhAcc<T>* keep, double& fsum,
+                                                double& tsum) {
+    const size_t ps = io.ps;
+    fsum = 0.0;
+    tsum = 0.0;
     AhAcc<T> acc;
     acc.zero();
     if (valid) {
@@ -465,21 +460,23 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
         const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
         const int nm = mu == 0 ? g.n[0] : mu == 1 ? g.n[1] : mu == 2 ? g.n[2] : g.n[3];
         const int64_t sm = mu == 0 ? g.stride[0] : mu == 1 ? g.stride[1] : mu == 2 ? g.stride[2] : g.stride[3];
-        const int64_t sf = cm == nm - 1 ? s - (int64_t)(nm - 1) * sm : s + sm;
-        const int64_t sb = cm == 0 ? s + (int64_t)(nm - 1) * sm : s - sm;
-        // every load first
+        const int64_t sfw = cm == nm - 1 ? s - (int64_t)(nm - 1) * sm : s + sm;
+        const int64_t sbk = cm == 0 ? s + (int64_t)(nm - 1) * sm : s - sm;
+        // every load first; a lane that reuses its kept back neighbour reads its own site instead (lines
+        // already on their way for its own link and g, so no extra traffic, and no branch around the loads)
+        const int64_t sld = reuse ? s : sbk;
         su3<T> g0, gfw, gb, u, ub;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            g0.e[k / 3][k % 3] = G[(size_t)k * ps + s];
-            gfw.e[k / 3][k % 3] = G[(size_t)k * ps + sf];
-            gb.e[k / 3][k % 3] = G[(size_t)k * ps + sb];
+            g0.e[k / 3][k % 3] = io.G[(size_t)k * ps + s];
+            gfw.e[k / 3][k % 3] = io.G[(size_t)k * ps + sfw];
+            gb.e[k / 3][k % 3] = io.G[(size_t)k * ps + sld];
         }
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
             // float: the own link streams past the cache (measured 3 % faster); double: plain loads
-            u.e[k / 3][k % 3] = sizeof(T) == 4 ? nt_load(Lin.p + Lin.at(mu, k, s)) : Lin.p[Lin.at(mu, k, s)];
-            ub.e[k / 3][k % 3] = Lin.p[Lin.at(mu, k, sb)];
+            u.e[k / 3][k % 3] = sizeof(T) == 4 ? nt_load(io.Lin.p + io.Lin.at(mu, k, s)) : io.Lin.p[io.Lin.at(mu, k, s)];
+            ub.e[k / 3][k % 3] = io.Lin.p[io.Lin.at(mu, k, sld)];
         }
         third_row(g0.e[0], g0.e[1], g0.e[2]);
         third_row(gfw.e[0], gfw.e[1], gfw.e[2]);
@@ -488,23 +485,21 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
             third_row(u.e[0], u.e[1], u.e[2]);
             third_row(ub.e[0], ub.e[1], ub.e[2]);
         }
-        // rows 1-2 of g0 U g(x+mu)^dag; row 3 from unitarity (float: re-orthonormalised first)
-        su3<T> un = mul_adj<T, 2>(mul_rows<T, 2>(g0, u), gfw);
-        if constexpr (sizeof(T) == 4) {
-            reunitarize(un);
-        } else {
-            third_row(un.e[0], un.e[1], un.e[2]);
-        }
-        Lout.store(mu, s, un);
+        const su3<T> un = updated_link(g0, u, gfw);
+        io.Lout.store(mu, s, un);
         fsum = (double)un.e[0][0].re + (double)un.e[1][1].re + (double)un.e[2][2].re;
-        acc.add(un, T(-1));
-        acc.add(mul_adj<T, 3>(mul(gb, ub), g0), T(1));  // U'_mu(x - mu)
-        if (acc_g != nullptr && mu == 0) {
-            su3<T> a = g_rows_at(acc_g, ps, s);
+        AhAcc<T> own;
+        own.set(un);
+        acc.set(updated_link(gb, ub, g0));  // U'_mu(x - mu)
+        if (reuse) acc = *keep;
+        acc.sub(own);
+        if (keep != nullptr && mu == 3) *keep = own;
+        if (io.acc_g != nullptr && mu == 0) {
+            su3<T> a = g_rows_at(io.acc_g, ps, s);
             a = mul_rows<T, 2>(g0, a);
-            reunitarize(a);
+            reunitarize_fp64(a);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc_g[(size_t)k * ps + s] = a.e[k / 3][k % 3];
+            for (int k = 0; k < 6; ++k) io.acc_g[(size_t)k * ps + s] = a.e[k / 3][k % 3];
         }
     }
     acc.o01.re = xor_sum4(acc.o01.re);
@@ -524,9 +519,9 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
         // double: streaming stores; float: plain stores, which leave D in the last-level cache for the
         // (x, y) pass that reads it next (measured 4 us faster there, 2 us slower here in double)
         if constexpr (sizeof(T) == 4)
-            D[(size_t)mu * ps + s] = out;
+            io.D[(size_t)mu * ps + s] = out;
         else
-            nt_store(D + (size_t)mu * ps + s, out);
+            nt_store(io.D + (size_t)mu * ps + s, out);
         if (mu == 0) {
             const double e0 = norm2(z0), e1 = norm2(z1), e2 = norm2(z2);
             const double dd0 = d0, dd1 = d1;
@@ -534,10 +529,60 @@ __global__ void __launch_bounds__(kFusedThreads) k_update_measure(Links<T, NE> L
         }
     }
     block_sum2<kFusedThreads>(fsum, tsum);
-    if (threadIdx.x == 0) {
-        part[sb] = make_double2(fsum, tsum);
-        if (b == 0) ctl->pending = 1;
+}
+
+// With acc_g set (six planes, ps apart) the lane of direction 0 also accumulates the total gauge
+// transform in place: A(x) <- reunitarize(g(x) A(x)) (in double precision). TM: the t-march traversal
+// (zb is then ignored); its own instantiation, so that the flat traversals keep their register budget.
+template <typename T, int NE, bool TM>
+__global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE> Lin, Links<T, NE> Lout,
+                                                                  const cx<T>* __restrict__ G, cx<T>* __restrict__ D,
+                                                                  size_t ps, Geom g, double2* __restrict__ part,
+                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g, Batch bt,
+                                                                  int zb) {
+    LoopIO<T, NE> io{Lin, Lout, G, D, acc_g, ps};
+    {
+        const size_t bo = boff(bt);
+        io.Lin.p = bshift(io.Lin.p, bo);
+        io.Lout.p = bshift(io.Lout.p, bo);
+        io.G = bshift(io.G, bo);
+        io.D = bshift(io.D, bo);
+        io.acc_g = bshift(io.acc_g, bo);
+        part = bshift(part, bo);
+        ctl = bshift(ctl, bo);
     }
+    if (ctl->done) return;
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int lane = threadIdx.x & 63;
+    const int mu = lane >> 4;
+    const int in_block = (threadIdx.x >> 6) * 16 + (lane & 15);  // site of this lane within its site block
+    double fsum, tsum;
+    if constexpr (TM) {
+        // block b owns spatial sites b*64 .. b*64 + 63 at every t
+        __shared__ AhAcc<T> keep[kFusedSites];
+        const int64_t vs = g.stride[3];
+        const int sbt = (int)(vs / kFusedSites);  // site blocks per t slice
+#pragma unroll 1
+        for (int t = 0; t < g.n[3]; ++t) {
+            const int64_t s = (int64_t)b * kFusedSites + in_block + vs * t;
+            loop_site_block<T, NE>(io, g, s, true, mu, t > 0 && mu == 3, &keep[in_block], fsum, tsum);
+            if (threadIdx.x == 0) part[b + sbt * t] = make_double2(fsum, tsum);
+            __syncthreads();  // the block sum's LDS slots are written again in the next step
+        }
+    } else {
+        int sb = b;  // site block: sites sb*64 .. sb*64 + 63
+        if (zb > 1) {
+            const int bpp = (g.n[0] * g.n[1]) / kFusedSites;
+            const int P = b / bpp, off = b - P * bpp;
+            const int z = P % zb + zb * (P / (zb * g.n[3]));
+            const int t = (P / zb) % g.n[3];
+            sb = (z + g.n[2] * t) * bpp + off;
+        }
+        const int64_t s = (int64_t)sb * kFusedSites + in_block;
+        loop_site_block<T, NE>(io, g, s, s < g.vol, mu, false, nullptr, fsum, tsum);
+        if (threadIdx.x == 0) part[sb] = make_double2(fsum, tsum);
+    }
+    if (threadIdx.x == 0 && b == 0) ctl->pending = 1;
 }
 
 // ------------------------------------------------ mixed-precision hand-over

@@ -57,6 +57,7 @@ def _signatures(lib):
         "gf_workspace_bytes": (sz, [pp]),
         "gf_init": (i32, [ctypes.POINTER(_P), pp, _P, _P, sz, _P]),
         "gf_iterate": (i32, [_P, i64, pr]),
+        "gf_advance": (i32, [_P, i64, pr]),
         "gf_fix_until": (i32, [_P, dbl, i64, pr]),
         "gf_batch_workspace_bytes": (sz, [i32, _P]),
         "gf_init_batch": (i32, [ctypes.POINTER(_P), i32, _P, _P, _P, sz, _P]),
@@ -176,6 +177,12 @@ def _check(ctx, st, allow=(GF_OK,)):
 def gf_iterate(ctx, n):
     r = gf_result()
     _check(ctx, load().gf_iterate(ctx, int(n), ctypes.byref(r)))
+    return r
+
+
+def gf_advance(ctx, n):
+    r = gf_result()
+    _check(ctx, load().gf_advance(ctx, int(n), ctypes.byref(r)))
     return r
 
 
@@ -430,6 +437,14 @@ class GaugeFixer:
     def fix_until(self, tol=1e-15, max_iter=100000):
         st, r = gf_fix_until(self.ctx, tol, max_iter)
         return _res(st, r)
+
+    def advance(self, n):
+        """n updates without writing the links back to the tensor (sync_links() does that)."""
+        return _res(GF_OK, gf_advance(self.ctx, n))
+
+    def sync_links(self):
+        """Write the context's current links into the tensor given at construction."""
+        gf_get_links(self.ctx, self.links.data_ptr())
 
     def quality(self):
         return gf_quality(self.ctx)

@@ -1,13 +1,15 @@
 """The HIP path against the stored FA fixture (tests/golden/fa_landau_*.txt, written from the oracle).
 
-Tolerances are those of the FP64 parity tests: theta to 1e-10 relative, F to 1e-13 absolute, the same
-number of updates to the stopping tolerance (theta falls by about a factor three per update near the
-end, far above the 1e-10 relative difference of the two paths).
+Tolerances are those of the FP64 parity tests: theta to tolerances.theta_bound (1e-10 relative, plus the
+rounding of Delta's entries that dominates near convergence), F to 1e-13 absolute, the same number of
+updates to the stopping tolerance (theta falls by about a factor three per update near the end, far
+above the difference of the two paths).
 """
 import numpy as np
 import pytest
 
 import golden_data
+from tolerances import theta_bound
 from paper_1208_1186_amd import gf, synth
 
 torch = pytest.importorskip("torch")
@@ -32,12 +34,13 @@ def test_fa_matches_golden(precision):
     fx.iterate(steps)
     th, f = fx.history(steps + 1)
     want = np.array([(h[1], h[2]) for h in g["history"]])
-    assert np.max(np.abs(th - want[:, 0]) / want[:, 0]) < 1e-10
+    vol = int(np.prod(g["dims"]))
+    assert np.all(np.abs(th - want[:, 0]) <= theta_bound(want[:, 0], vol))
     assert np.max(np.abs(f - want[:, 1])) < 1e-13
     fx.close()
     links = torch.from_numpy(np.ascontiguousarray(u)).to("cuda:0")
     fx = gf.GaugeFixer(links, precision, alpha=g["alpha"], check_every=1)
     res = fx.fix_until(g["tol"], 1000)
     assert res.status == gf.GF_OK and res.iters == g["iters_to_tol"]
-    assert abs(res.theta - g["final_theta"]) < 1e-10 * g["final_theta"]
+    assert abs(res.theta - g["final_theta"]) <= theta_bound(g["final_theta"], vol)
     assert abs(res.F - g["final_F"]) < 1e-13

@@ -313,14 +313,27 @@ def test_plaquette_matches_oracle_and_is_invariant(dims, precision):
     assert fx.plaquette() == pytest.approx(want, abs=1e-12 if precision != "fp32_12" else 1e-6)
 
 
-@pytest.mark.parametrize("dims,prec", [((8, 8, 16, 4), "fp64_18"), ((8, 8, 8, 6), "fp32_12"), ((16, 8, 12, 4), "fp64_12")])
+def traversals(dims):
+    """Loop-kernel traversals the library accepts on this shape: z groupings 1, 2, 4, 8 (a divisor of Nz
+    below Nz, 64 dividing Nx*Ny) and 0, the t-march (64 dividing Nx*Ny*Nz, Nt >= 4, >= 32 blocks)."""
+    nx, ny, nz, nt = dims
+    out = [1] + [z for z in (2, 4, 8) if (nx * ny) % 64 == 0 and nz % z == 0 and nz > z]
+    if (nx * ny * nz) % 64 == 0 and nt >= 4 and nx * ny * nz // 64 >= 32:
+        out.append(0)
+    return out
+
+
+@pytest.mark.parametrize("dims,prec", [((16, 8, 16, 4), "fp64_18"), ((16, 16, 8, 6), "fp32_12"),
+                                       ((16, 8, 24, 4), "fp64_12"), ((8, 8, 16, 8), "fp32_18")])
 def test_loop_traversal_does_not_change_results(dims, prec):
-    """Every z grouping of the loop kernel gives bitwise the same links and theta/F history."""
+    """Every traversal of the loop kernel (z groupings and the t-march) gives bitwise the same links and
+    theta/F history."""
     u = synth.make_config(dims, 17)
     runs = []
-    for zb in (1, 2, 4):
-        if dims[2] % zb or dims[2] == zb:
-            continue
+    zbs = traversals(dims)
+    assert 0 in zbs or dims == (8, 8, 16, 8)
+    for zb in zbs:
+        print(f"traversal {dims} {prec} zb={zb}", flush=True)
         links = torch.from_numpy(u).cuda()
         fx = gf.GaugeFixer(links, prec)
         fx.set_loop_traversal(zb)
@@ -335,7 +348,30 @@ def test_loop_traversal_does_not_change_results(dims, prec):
     fx = gf.GaugeFixer(torch.from_numpy(u).cuda(), prec)
     with pytest.raises(gf.GfError):
         fx.set_loop_traversal(3)
+    if 0 not in zbs:
+        with pytest.raises(gf.GfError):
+            fx.set_loop_traversal(0)
     fx.close()
+
+
+@pytest.mark.parametrize("dims,prec", [((32, 32, 32, 32), "fp64_18"), ((32, 32, 32, 32), "fp32_12"),
+                                       ((48, 48, 48, 8), "fp64_18"), ((48, 48, 48, 8), "fp32_12")])
+def test_loop_traversals_full_size(dims, prec):
+    """The workload lattices: the t-march and the plain sweep agree bitwise over three updates (the
+    oracle's trajectory at 32^4 is checked in test_gpu_headline.py with the traversal the autotuner keeps)."""
+    print(f"traversals full size {dims} {prec}", flush=True)
+    u = synth.make_config(dims, 0)
+    runs = []
+    for zb in (1, 0):
+        links = torch.from_numpy(u).cuda()
+        fx = gf.GaugeFixer(links, prec, check_every=3)
+        fx.set_loop_traversal(zb)
+        fx.iterate(3)
+        runs.append((links.cpu(), fx.history(4)))
+        fx.close()
+        del links
+    assert torch.equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1][0], runs[1][1][0]) and np.array_equal(runs[0][1][1], runs[1][1][1])
 
 
 @pytest.mark.parametrize("dims,precision,alpha", [((8, 8, 8, 8), "fp64_18", 0.08), ((12, 6, 4, 8), "fp64_18", 1.5),
