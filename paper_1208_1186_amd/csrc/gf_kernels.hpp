@@ -457,9 +457,13 @@ __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const G
     if (valid) {
         int c[4];
         site_coords(g, s, c);
+        // extents as wave-uniform values first: a select among fields of g by the per-lane mu would be
+        // turned into a per-lane indexed load, which puts a copy of g in scratch memory
+        const int n0 = __builtin_amdgcn_readfirstlane(g.n[0]), n1 = __builtin_amdgcn_readfirstlane(g.n[1]);
+        const int n2 = __builtin_amdgcn_readfirstlane(g.n[2]), n3 = __builtin_amdgcn_readfirstlane(g.n[3]);
         const int cm = mu == 0 ? c[0] : mu == 1 ? c[1] : mu == 2 ? c[2] : c[3];
-        const int nm = mu == 0 ? g.n[0] : mu == 1 ? g.n[1] : mu == 2 ? g.n[2] : g.n[3];
-        const int64_t sm = mu == 0 ? g.stride[0] : mu == 1 ? g.stride[1] : mu == 2 ? g.stride[2] : g.stride[3];
+        const int nm = mu == 0 ? n0 : mu == 1 ? n1 : mu == 2 ? n2 : n3;
+        const int64_t sm = mu == 0 ? 1 : mu == 1 ? (int64_t)n0 : mu == 2 ? (int64_t)n0 * n1 : (int64_t)n0 * n1 * n2;
         const int64_t sfw = cm == nm - 1 ? s - (int64_t)(nm - 1) * sm : s + sm;
         const int64_t sbk = cm == 0 ? s + (int64_t)(nm - 1) * sm : s - sm;
         // every load first; a lane that reuses its kept back neighbour reads its own site instead (lines
