@@ -127,6 +127,24 @@ gf_status gf_advance(gf_ctx* ctx, int64_t n, gf_result* result);
 gf_status gf_fix_until(gf_ctx* ctx, double theta_tol, int64_t max_iter, gf_result* result);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): gf_init + gf_fix_until + gf_destroy in one call, with the
+ * workspace taken from the library's own device-resident scratch instead of a caller buffer.
+ * The scratch is a file-scope device array of GF_NOALLOC_SCRATCH_BYTES (128 MiB) per GPU, held from the
+ * first call on that GPU until the process ends; the call allocates no device memory and calls no HIP
+ * allocation routine (the small context object lives on the host heap for the duration of the call).
+ * d_links: canonical links (V*36 complex double), read and overwritten with the result (on GF_ENOTCONV
+ * with the last iterate). stream: hipStream_t (NULL = default stream); the call synchronises it.
+ * GF_ENOTSUP (nothing touched) if gf_workspace_bytes(params) exceeds the scratch: up to 16^4 in every
+ * precision, 32^3 x 4 in FP64-12 or FP32-12. Every call on one GPU shares its scratch: calls that overlap
+ * on the same GPU (other host threads, other streams) race and must be serialised by the caller.
+ * gf_last_error(NULL) describes a failure.
+ */
+#define GF_NOALLOC_SCRATCH_BYTES (128ull << 20)
+gf_status gf_fix_until_noalloc(const gf_params* params, void* d_links, void* stream, double theta_tol,
+                               int64_t max_iter, gf_result* result);
+
+/*
  * Batches of independent lattices (many uneven configurations, one GPU).
  * The gauge fixing of Section 1 of the paper acts on each configuration on
  * its own (the paper fixes one lattice at a time); a batch advances every configuration of the same

@@ -1643,8 +1643,10 @@ size_t gf_workspace_bytes(const gf_params* params) {
     return L.total;
 }
 
-gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_workspace, size_t workspace_bytes,
-                  void* stream) {
+// gf_init's work. heads: if set, two host slots of kHeadBytes for the control-block read-back (a plain
+// context takes the first, a GF_MIXED context's children one each) instead of pinned host memory.
+gf_status init_ctx(gf_ctx** out, const gf_params* params, void* d_links, void* d_workspace, size_t workspace_bytes,
+                   void* stream, unsigned char* heads) {
     try {
         if (!out) {
             g_init_error = "ctx output pointer is NULL";
@@ -1678,8 +1680,9 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
         double* links = reinterpret_cast<double*>(d_links);
         unsigned char* ws = reinterpret_cast<unsigned char*>(d_workspace);
         hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+        auto slot = [&](int i) { return heads ? reinterpret_cast<Ctl*>(heads + (size_t)i * kHeadBytes) : nullptr; };
         if (!L.mixed) {
-            s = init_plain(c, *params, L, links, ws, st, true);
+            s = init_plain(c, *params, L, links, ws, st, true, nullptr, slot(0));
         } else {
             c->p = *params;
             c->L = L;
@@ -1697,7 +1700,7 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
                 Layout Lc;
                 plan_plain(&q, Lc, err);
                 // the double child keeps the input links untouched in its buffer 0 until the hand-over
-                s = init_plain(c->child[i], q, Lc, links, ws + L.child_off[i], st, i == 0);
+                s = init_plain(c->child[i], q, Lc, links, ws + L.child_off[i], st, i == 0, nullptr, slot(i));
                 if (s != GF_OK) c->err = c->child[i]->err;
             }
         }
@@ -1708,6 +1711,81 @@ gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_
         }
         *out = c;
         return GF_OK;
+    } catch (...) {
+        g_init_error = "unexpected host exception";
+        return GF_EINVAL;
+    }
+}
+
+gf_status gf_init(gf_ctx** out, const gf_params* params, void* d_links, void* d_workspace, size_t workspace_bytes,
+                  void* stream) {
+    return init_ctx(out, params, d_links, d_workspace, workspace_bytes, stream, nullptr);
+}
+
+// ----------------------------------------------------- entry point that allocates nothing
+// The workspace of gf_fix_until_noalloc: a file-scope device array, one copy per GPU, held until the
+// process ends. Host code takes its device address from hipGetSymbolAddress (once per device, with
+// that device current) and never passes the array's own name to a kernel or a copy.
+__device__ __align__(256) unsigned char scratch[GF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ws[kNoallocDevices];
+// control-block read-back slots (two: the children of a GF_MIXED context), per device
+alignas(64) unsigned char g_noalloc_heads[kNoallocDevices][2 * kHeadBytes];
+
+gf_status noalloc_workspace(void** ws, unsigned char** heads) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoallocDevices) {
+        g_init_error = "gf_fix_until_noalloc: no current HIP device (or device index >= 64)";
+        return GF_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ws[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g_init_error = std::string("gf_fix_until_noalloc: hipGetSymbolAddress of the scratch failed: ") +
+                           hipGetErrorString(e);
+            return GF_EDEVICE;
+        }
+        g_noalloc_ws[dev] = p;
+    }
+    *ws = g_noalloc_ws[dev];
+    *heads = g_noalloc_heads[dev];
+    return GF_OK;
+}
+
+gf_status gf_fix_until_noalloc(const gf_params* params, void* d_links, void* stream, double theta_tol,
+                               int64_t max_iter, gf_result* result) {
+    try {
+        Layout L;
+        std::string err;
+        gf_status s = plan_layout(params, L, err);
+        if (s != GF_OK) {
+            g_init_error = err;
+            return s;
+        }
+        if (!d_links) {
+            g_init_error = "links pointer is NULL";
+            return GF_EINVAL;
+        }
+        if (L.total > (size_t)GF_NOALLOC_SCRATCH_BYTES) {
+            g_init_error = "gf_fix_until_noalloc: this lattice and precision need " + std::to_string(L.total) +
+                           " bytes of workspace; the scratch holds " + std::to_string((size_t)GF_NOALLOC_SCRATCH_BYTES) +
+                           " (use gf_init with a workspace of your own)";
+            return GF_ENOTSUP;
+        }
+        void* ws = nullptr;
+        unsigned char* heads = nullptr;
+        if ((s = noalloc_workspace(&ws, &heads)) != GF_OK) return s;
+        gf_ctx* c = nullptr;
+        s = init_ctx(&c, params, d_links, ws, GF_NOALLOC_SCRATCH_BYTES, stream, heads);
+        if (s != GF_OK) return s;
+        s = gf_fix_until(c, theta_tol, max_iter, result);
+        if (s != GF_OK && s != GF_ENOTCONV) g_init_error = c->err;
+        gf_destroy(c);
+        return s;
     } catch (...) {
         g_init_error = "unexpected host exception";
         return GF_EINVAL;

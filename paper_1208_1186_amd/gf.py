@@ -59,6 +59,7 @@ def _signatures(lib):
         "gf_iterate": (i32, [_P, i64, pr]),
         "gf_advance": (i32, [_P, i64, pr]),
         "gf_fix_until": (i32, [_P, dbl, i64, pr]),
+        "gf_fix_until_noalloc": (i32, [pp, _P, _P, dbl, i64, pr]),
         "gf_batch_workspace_bytes": (sz, [i32, _P]),
         "gf_init_batch": (i32, [ctypes.POINTER(_P), i32, _P, _P, _P, sz, _P]),
         "gf_fix_until_batch": (i32, [_P, dbl, i64, _P]),
@@ -184,6 +185,27 @@ def gf_advance(ctx, n):
     r = gf_result()
     _check(ctx, load().gf_advance(ctx, int(n), ctypes.byref(r)))
     return r
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def gf_fix_until_noalloc(links, precision="fp64_18", tol=1e-15, max_iter=100000, alpha=0.08, switch_theta=1e-8,
+                         check_every=10, flags=0, stream=None):
+    """gf_init + gf_fix_until + gf_destroy on the library's own scratch (no device allocation): links is a
+    contiguous complex128 CUDA tensor (Nt, Nz, Ny, Nx, 4, 3, 3), overwritten with the result. Returns
+    (status, Result); raises GfError for statuses other than GF_OK and GF_ENOTCONV."""
+    import torch
+    if not links.is_cuda or links.dtype != torch.complex128 or not links.is_contiguous() or links.dim() != 7:
+        raise ValueError("links must be a contiguous complex128 CUDA tensor (Nt, Nz, Ny, Nx, 4, 3, 3)")
+    nt, nz, ny, nx = links.shape[:4]
+    params = make_params((nx, ny, nz, nt), precision, alpha, switch_theta, check_every, flags)
+    st_obj = stream if stream is not None else torch.cuda.current_stream(links.device)
+    r = gf_result()
+    st = load().gf_fix_until_noalloc(ctypes.byref(params), _P(links.data_ptr()), _P(st_obj.cuda_stream),
+                                     float(tol), int(max_iter), ctypes.byref(r))
+    _check(None, st, allow=(GF_OK, GF_ENOTCONV))
+    return st, _res(st, r)
 
 
 def gf_fix_until(ctx, tol, max_iter):
