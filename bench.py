@@ -30,20 +30,30 @@ def log(msg):
 
 
 def kernel_bytes(name, vol, L, S, nblk):
-    """Algorithmic HBM bytes of one launch: every array the kernel must touch, once."""
+    """Algorithmic HBM bytes of one launch: every array the kernel must touch, once. The library keeps the
+    links as the input links U0 and the accumulated gauge transform H (rows 1-2, 12 reals per site): the
+    loop kernel reads U0 and H and writes the divergence; the inverse (x, y) pass reads the filtered field
+    and H and writes the updated H."""
     W = 8  # reals per site of the packed divergence (4 complex fields)
     links = 4 * L * S * vol
     field = W * S * vol
-    gauge = 12 * S * vol  # rows 1-2 of g(x)
+    gauge = 12 * S * vol  # rows 1-2 of a transform
     return {
-        "update_measure": 2 * links + gauge + field,  # read U and g; write U' and Delta(U')
-        "update": 2 * links + field,           # read U and (alpha/2)Delta~ (g formed in place), write U
-        "divergence": links + field,           # read U, write Delta
+        "update_measure": links + gauge + field,  # read U0 and H; write Delta
+        "divergence": links + gauge + field,      # the same kernel as a standalone measurement
+        "update": 2 * gauge + field,              # read (alpha/2)Delta~ and H, write H
         "fft_xy_fwd": 2 * field,
         "fft_zt_filter": 2 * field,
-        "fft_xy_inv": field + gauge,           # read (alpha/2)Delta~, write g
+        "fft_xy_inv": field + 2 * gauge,          # read (alpha/2)Delta~ and H, write H
         "finalize": 16 * nblk,
     }[name]
+
+
+def iteration_bytes_per_site(L, S):
+    """Algorithmic bytes per site of one whole FA iteration as the library stores the links (U0 and H):
+    the three FFT passes, the gauge update of H and the loop kernel."""
+    W = 8
+    return (2 * W + 2 * W + (W + 24) + (4 * L + 12 + W)) * S
 
 
 STORAGE = {"fp64_18": (18, 8), "fp64_12": (12, 8), "fp32_12": (12, 4), "fp32_18": (18, 4)}
@@ -692,6 +702,8 @@ def main():
         "hbm_model_GBps": round(b_alg * vol * rate / 1e9, 1),
         "hbm_model_frac": round(b_alg * vol * rate / 1e9 / HBM_PEAK_GBS, 4),
         "hbm_model_bytes_per_site": b_alg,
+        "iteration_bytes_per_site": iteration_bytes_per_site(L, S),
+        "iteration_GBps": round(iteration_bytes_per_site(L, S) * vol * rate / 1e9, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kern,

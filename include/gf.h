@@ -70,7 +70,8 @@ enum {
                                       Cayley-Hamilton) instead of reunitarize(1 + (alpha/2) Delta~) */
     GF_FLAG_NO_FA = 1u << 1,       /* plain steepest descent: K(p) = 1 instead of p2max/p^2 */
     GF_FLAG_GENERIC_FFT = 1u << 2, /* use the runtime-shaped FFT kernels even where a compile-time one exists */
-    GF_FLAG_ACCUMULATE_GAUGE = 1u << 3, /* keep G(x) with U = G U_input G(x+mu)^dag (gf_get_gauge) */
+    GF_FLAG_ACCUMULATE_GAUGE = 1u << 3, /* accepted and ignored: the accumulated transform G(x) with
+                                           U = G U_input G(x+mu)^dag is what every context stores (gf_get_gauge) */
     GF_FLAG_LEARNED = 1u << 4,          /* reserve the learned preconditioner (gf_mlp_set_weights) */
     GF_FLAG_RECORD_SPECTRA = 1u << 5    /* reserve spectrum recording (gf_record_spectra) */
 };
@@ -232,9 +233,10 @@ gf_status gf_get_links(gf_ctx* ctx, void* d_out);
 
 /*
  * Write the accumulated gauge transform G (canonical matrix field, V*9
- * complex double) with U_current(x) = G(x) U_input(x) G(x+mu)^dag. Needs
- * GF_FLAG_ACCUMULATE_GAUGE (always on for GF_MIXED); else GF_ESTATE.
- * Float contexts re-orthonormalise G after every update.
+ * complex double) with U_current(x) = G(x) U_input(x) G(x+mu)^dag. Every
+ * context keeps G (it stores the links in this form: the input links and G,
+ * rows 1-2, which every update replaces by reunitarize(g G), the
+ * re-orthonormalisation in double precision in every precision).
  */
 gf_status gf_get_gauge(gf_ctx* ctx, void* d_out);
 

@@ -3,8 +3,10 @@
 // The context carves the caller's workspace into: a device control block
 // (theta, F, stop flag, iteration count, history), per-block reduction
 // partials, FFT twiddle and sin^2 tables, the divergence buffer D, the FFT
-// buffer Q, the gauge rows G and two link buffers (the loop kernel reads one
-// and writes the other: after k updates the links are in buffer k & 1).
+// buffer Q, the input links U0 (never written after gf_init) and two buffers
+// of the accumulated gauge transform H (rows 1-2): after k updates the current
+// links are H U0 H(x+mu)^dag with H in buffer k & 1 (the inverse (x, y) pass of
+// update k reads buffer k & 1 and writes the other).
 // Every kernel is queued on the caller's stream; the loop reads the control
 // block back every check_every iterations, and kernels queued after the stop
 // flag is set return at once, so the iterate is exactly the one the stopping
@@ -93,12 +95,11 @@ struct Layout {
     // inverse (x, y) pass of four fields + gauge rows
     int thrC, eptC;
     size_t ldsC;
-    bool acc;         // keep the accumulated gauge transform
     bool learned;     // reserve the network parameters and the multiplier table
     bool record;      // reserve two spectra and the per-tuple record
     int ntuples;      // distinct momentum tuples (N_mu/2 + 1 per axis)
     // workspace offsets
-    size_t off_ctl, off_tune, off_part, off_sin2, off_tw, off_d, off_q, off_g, off_acc, off_links[2], off_mlp, off_mtab,
+    size_t off_ctl, off_tune, off_part, off_sin2, off_tw, off_d, off_q, off_h[2], off_links, off_mlp, off_mtab,
         off_spec[4], off_rec, total;
     // GF_MIXED: a float child (bulk) and a double child (polish) share the workspace
     bool mixed;
@@ -156,13 +157,8 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
         return GF_EINVAL;
     }
     L.vol = vol;
-    L.acc = (p->flags & GF_FLAG_ACCUMULATE_GAUGE) != 0;
     L.learned = (p->flags & GF_FLAG_LEARNED) != 0;
     L.record = (p->flags & GF_FLAG_RECORD_SPECTRA) != 0;
-    if (L.learned && L.acc) {
-        err = "GF_FLAG_LEARNED cannot be combined with an accumulated gauge transform (GF_FLAG_ACCUMULATE_GAUGE, GF_MIXED)";
-        return GF_EINVAL;
-    }
     L.ntuples = (L.n[0] / 2 + 1) * (L.n[1] / 2 + 1) * (L.n[2] / 2 + 1) * (L.n[3] / 2 + 1);
     L.fp32 = p->precision == GF_FP32_12 || p->precision == GF_FP32_18;
     L.ne = (p->precision == GF_FP64_12 || p->precision == GF_FP32_12) ? 6 : 9;
@@ -219,14 +215,12 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     o = align_up(o + 4 * L.ps * csz, kAlign);
     L.off_q = o;
     o = align_up(o + 4 * L.ps * csz, kAlign);
-    L.off_g = o;
-    o = align_up(o + 6 * L.ps * csz, kAlign);
-    L.off_acc = o;
-    if (L.acc) o = align_up(o + 6 * L.ps * csz, kAlign);
     for (int i = 0; i < 2; ++i) {
-        L.off_links[i] = o;
-        o = align_up(o + (size_t)4 * L.ne * L.ps * csz, kAlign);
+        L.off_h[i] = o;
+        o = align_up(o + 6 * L.ps * csz, kAlign);
     }
+    L.off_links = o;
+    o = align_up(o + (size_t)4 * L.ne * L.ps * csz, kAlign);
     L.off_mlp = o;
     if (L.learned) o = align_up(o + kMlpParams * sizeof(float), kAlign);
     L.off_mtab = o;
@@ -288,9 +282,8 @@ struct gf_ctx {
     void* tw[4];
     void* D;      // divergence of the current links (four packed fields)
     void* Q;      // FFT work buffer (four packed fields)
-    void* Gb;     // gauge rows (six planes)
-    void* Lb[2];  // links after k updates live in Lb[k & 1]
-    void* Acc;    // accumulated gauge transform rows (or nullptr)
+    void* U0;     // the input links (SoA planes)
+    void* Hb[2];  // accumulated gauge transform rows after k updates in Hb[k & 1]
     // learned preconditioner state
     TupleGeom tg;
     float* mlp;          // network parameters (workspace copy)
@@ -399,8 +392,8 @@ double inv3v(const gf_ctx* c) { return 1.0 / (3.0 * (double)c->L.vol); }
 double inv12v(const gf_ctx* c) { return 1.0 / (12.0 * (double)c->L.vol); }
 
 template <typename T, int NE>
-Links<T, NE> links_of(gf_ctx* c, int i) {
-    return Links<T, NE>{reinterpret_cast<cx<T>*>(c->Lb[i & 1]), c->L.ps};
+Links<T, NE> links_of(gf_ctx* c) {
+    return Links<T, NE>{reinterpret_cast<cx<T>*>(c->U0), c->L.ps};
 }
 template <typename T>
 cx<T>* cxp(void* p) {
@@ -468,14 +461,15 @@ bool launch_zt_ct(gf_ctx* c, void* Z, T coef, int no_fa, int force, const T* mta
 }
 
 template <typename T>
-bool launch_gauge_ct(gf_ctx* c, int force) {
+bool launch_gauge_ct(gf_ctx* c, int force, const void* hin, void* hout) {
     const Layout& L = c->L;
 #define GF_X(A, B)                                                                                             \
     if (L.n[0] == A && L.n[1] == B) {                                                                          \
         hipLaunchKernelGGL((k_fft_xy_gauge_ct<T, A, B>), dim3(L.n[2] * L.n[3], c->nact),                       \
                            dim3(ct_threads(4 * A * B, gauge_ept(A, B))), gauge_ct_lds(A, B, sizeof(cx<T>)),    \
-                           c->st, reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps,             \
-                           twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c), exact_exp(c));                    \
+                           c->st, reinterpret_cast<const cx<T>*>(c->Q), L.ps,                                  \
+                           reinterpret_cast<const cx<T>*>(hin), cxp<T>(hout), L.ps, twp<T>(c, 0), twp<T>(c, 1), \
+                           c->ctl, force, bt(c), exact_exp(c));                                                \
         return true;                                                                                           \
     }
     GF_GAUGE_CASES(GF_X)
@@ -528,48 +522,26 @@ void launch_zt(gf_ctx* c, void* Z, int force) {
     tstop(c);
 }
 
+// Inverse (x, y) pass + gauge: hout = reunitarize(g hin) (hin null: g itself).
 template <typename T>
-void launch_gauge_pass(gf_ctx* c, int force) {
+void launch_gauge_pass(gf_ctx* c, int force, const void* hin, void* hout) {
     const Layout& L = c->L;
     tstart(c, GF_K_FFT_XY_INV);
-    if (!generic_fft(c) && launch_gauge_ct<T>(c, force)) {
+    if (!generic_fft(c) && launch_gauge_ct<T>(c, force, hin, hout)) {
         tstop(c);
         return;
     }
+    const cx<T>* hi = reinterpret_cast<const cx<T>*>(hin);
     if (L.eptC == kEPT)
         hipLaunchKernelGGL((k_fft_xy_gauge<T, kEPT>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
-                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
+                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, hi, cxp<T>(hout), L.ps, L.n[0], L.n[1], L.rs,
                            c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c),
                            exact_exp(c));
     else
         hipLaunchKernelGGL((k_fft_xy_gauge<T, 16>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
-                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, cxp<T>(c->Gb), L.ps, L.n[0], L.n[1], L.rs,
+                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, hi, cxp<T>(hout), L.ps, L.n[0], L.n[1], L.rs,
                            c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c),
                            exact_exp(c));
-    tstop(c);
-}
-
-// Standalone measurement of the current links: Delta -> D, theta and F.
-template <typename T, int NE>
-void launch_measure_t(gf_ctx* c) {
-    const Layout& L = c->L;
-    tstart(c, GF_K_DIVERGENCE);
-    hipLaunchKernelGGL((k_divergence<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c, cur(c)),
-                       cxp<T>(c->D), L.ps, c->geom, c->part);
-    tstop(c);
-    tstart(c, GF_K_FINALIZE);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, L.nblk, inv3v(c), inv12v(c), c->ctl, 0,
-                       Batch{nullptr, 0});
-    tstop(c);
-}
-
-// In-place update of the current links from (alpha/2) Delta~ packed in Q.
-template <typename T, int NE>
-void launch_update_t(gf_ctx* c) {
-    const Layout& L = c->L;
-    tstart(c, GF_K_UPDATE);
-    hipLaunchKernelGGL((k_update<T, NE>), dim3(L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c, cur(c)),
-                       reinterpret_cast<const cx<T>*>(c->Q), L.ps, c->geom, exact_exp(c));
     tstop(c);
 }
 
@@ -578,29 +550,54 @@ int loop_blocks(const Layout& L) {
     return L.zb == 0 ? (int)(L.vol / L.n[3] / kFusedSites) : L.nblk_fused;
 }
 
-// Loop kernel from k to k + 1 updates: links Lb[k] -> Lb[k+1], divergence -> D.
+template <typename T, int NE>
+void launch_loop_kernel(gf_ctx* c, const void* h, int force, Ctl* ctl, void* dst, int nact) {
+    const Layout& L = c->L;
+    auto kern = L.zb == 0 ? k_update_measure<T, NE, true> : k_update_measure<T, NE, false>;
+    hipLaunchKernelGGL(kern, dim3(loop_blocks(L), nact), dim3(kFusedThreads), 0, c->st, links_of<T, NE>(c),
+                       reinterpret_cast<const cx<T>*>(h), cxp<T>(dst), L.ps, c->geom, c->part, ctl, bt(c), L.zb,
+                       force);
+}
+
+// Standalone measurement of the current links (transform in buffer k & 1): Delta -> D, theta and F.
+template <typename T, int NE>
+void launch_measure_t(gf_ctx* c) {
+    tstart(c, GF_K_DIVERGENCE);
+    launch_loop_kernel<T, NE>(c, c->Hb[cur(c)], 1, c->ctl, c->D, 1);
+    tstop(c);
+    tstart(c, GF_K_FINALIZE);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, c->st, c->part, c->L.nblk_fused, inv3v(c), inv12v(c),
+                       c->ctl, 0, Batch{nullptr, 0});
+    tstop(c);
+}
+
+// Update of the current links from (alpha/2) Delta~ packed in Q: H <- reunitarize(g H) in place.
+template <typename T, int NE>
+void launch_update_t(gf_ctx* c) {
+    const Layout& L = c->L;
+    tstart(c, GF_K_UPDATE);
+    hipLaunchKernelGGL(k_h_update<T>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st, reinterpret_cast<const cx<T>*>(c->Q),
+                       L.ps, cxp<T>(c->Hb[cur(c)]), L.ps, L.vol, exact_exp(c));
+    tstop(c);
+}
+
+// Loop kernel after update k (transform of k + 1 updates): divergence -> D, partials.
 template <typename T, int NE>
 void launch_fused_t(gf_ctx* c, long long k) {
-    const Layout& L = c->L;
-    const int a = (int)(k & 1);
     tstart(c, GF_K_UPDATE_MEASURE);
-    auto kern = L.zb == 0 ? k_update_measure<T, NE, true> : k_update_measure<T, NE, false>;
-    hipLaunchKernelGGL(kern, dim3(loop_blocks(L), c->nact), dim3(kFusedThreads), 0, c->st,
-                       links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
-                       cxp<T>(c->D), L.ps, c->geom, c->part, c->ctl, reinterpret_cast<cx<T>*>(c->Acc), bt(c),
-                       L.zb);
+    launch_loop_kernel<T, NE>(c, c->Hb[(k + 1) & 1], 0, c->ctl, c->D, c->nact);
     tstop(c);
 }
 
 template <typename T, int NE>
 void launch_pack_t(gf_ctx* c, const double* src) {
-    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, src,
-                       links_of<T, NE>(c, cur(c)), c->L.vol, sizeof(T) == 4 ? 1 : 0);
+    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, src, links_of<T, NE>(c),
+                       c->L.vol, sizeof(T) == 4 ? 1 : 0);
 }
 template <typename T, int NE>
 void launch_unpack_t(gf_ctx* c, double* dst) {
-    hipLaunchKernelGGL((k_unpack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c, cur(c)),
-                       dst, c->L.vol);
+    hipLaunchKernelGGL((k_unpack_h<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c),
+                       reinterpret_cast<const cx<T>*>(c->Hb[cur(c)]), c->geom, dst);
 }
 
 #define GF_DISPATCH(c, fn, ...)                                                                  \
@@ -629,7 +626,7 @@ gf_status one_iteration(gf_ctx* c, long long k) {
                                reinterpret_cast<const float*>(c->sin2), c->tg, coef, c->ctl, 0,
                                reinterpret_cast<float*>(c->mtab));
         launch_zt<float>(c, c->Q, 0);
-        launch_gauge_pass<float>(c, 0);
+        launch_gauge_pass<float>(c, 0, c->Hb[k & 1], c->Hb[(k + 1) & 1]);
     } else {
         launch_xy<double, false>(c, c->D, c->Q, 0, true);
         if (c->net_this)
@@ -637,7 +634,7 @@ gf_status one_iteration(gf_ctx* c, long long k) {
                                reinterpret_cast<const double*>(c->sin2), c->tg, coef, c->ctl, 0,
                                reinterpret_cast<double*>(c->mtab));
         launch_zt<double>(c, c->Q, 0);
-        launch_gauge_pass<double>(c, 0);
+        launch_gauge_pass<double>(c, 0, c->Hb[k & 1], c->Hb[(k + 1) & 1]);
     }
     GF_DISPATCH(c, launch_fused_t, c, k);
     return launched(c, "loop launch");
@@ -726,18 +723,19 @@ void field_unpack(gf_ctx* c, const void* src, void* dst) {
                        reinterpret_cast<const cx<T>*>(src), c->L.ps, reinterpret_cast<double*>(dst), c->L.vol);
 }
 template <typename T>
-void gauge_unpack(gf_ctx* c, void* dst) {
+void gauge_unpack(gf_ctx* c, const void* rows, void* dst) {
     hipLaunchKernelGGL(k_gauge_unpack<T>, dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
-                       reinterpret_cast<const cx<T>*>(c->Gb), c->L.ps, reinterpret_cast<double*>(dst), c->L.vol);
+                       reinterpret_cast<const cx<T>*>(rows), c->L.ps, reinterpret_cast<double*>(dst), c->L.vol);
 }
 
-// Forward FFT of Q, filter, and either the plain inverse (x, y) pass (gauge = false) or the gauge pass.
+// Forward FFT of Q, filter, and either the plain inverse (x, y) pass (gauge null) or the gauge pass writing
+// g itself (rows 1-2) to gauge.
 template <typename T>
-void stage_spectral(gf_ctx* c, bool gauge) {
+void stage_spectral(gf_ctx* c, void* gauge) {
     launch_xy<T, false>(c, c->Q, c->Q, 1, false);
     launch_zt<T>(c, c->Q, 1);
     if (gauge)
-        launch_gauge_pass<T>(c, 1);
+        launch_gauge_pass<T>(c, 1, nullptr, gauge);
     else
         launch_xy<T, true>(c, c->Q, c->Q, 1, false);
 }
@@ -831,15 +829,8 @@ std::vector<int> zb_candidates(const Layout& L) {
 
 template <typename T, int NE>
 void time_loop_t(gf_ctx* c, double& ms_out) {
-    const Layout& L = c->L;
-    const int a = cur(c);
-    auto run = [&]() {
-        auto kern = L.zb == 0 ? k_update_measure<T, NE, true> : k_update_measure<T, NE, false>;
-        hipLaunchKernelGGL(kern, dim3(loop_blocks(L)), dim3(kFusedThreads), 0, c->st,
-                           links_of<T, NE>(c, a), links_of<T, NE>(c, 1 - a), reinterpret_cast<const cx<T>*>(c->Gb),
-                           cxp<T>(c->Q), L.ps, c->geom, c->part, c->tune_ctl, static_cast<cx<T>*>(nullptr),
-                           Batch{nullptr, 0}, L.zb);
-    };
+    // trial launches on the current links: divergence -> Q, partials of a scratch control-block head
+    auto run = [&]() { launch_loop_kernel<T, NE>(c, c->Hb[cur(c)], 1, c->tune_ctl, c->Q, 1); };
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ms_out = 1e30;
     if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
@@ -897,10 +888,9 @@ gf_status autotune(gf_ctx* c) {
     int bestZ = 1;
     const std::vector<int> zbs = zb_candidates(c->L);
     if (zbs.size() > 1) {
-        // trial launches: current links -> the other link buffer, divergence -> Q, gauge rows zeroed, a
-        // scratch control-block head; D, the control block and the current links are left as they are
+        // trial launches write Q, the block partials and a scratch control-block head; D, the control
+        // block, the links and the transform are left as they are
         (void)hipMemsetAsync(c->tune_ctl, 0, offsetof(Ctl, hist_theta), c->st);
-        (void)hipMemsetAsync(c->Gb, 0, 6 * c->L.ps * (c->L.fp32 ? 8 : 16), c->st);
         std::vector<double> tz(zbs.size(), 1e30);
         for (int r = 0; r < kTuneRounds; ++r)
             for (size_t j = 0; j < zbs.size(); ++j) {
@@ -1016,8 +1006,8 @@ void carve(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsi
     for (int d = 0; d < 4; ++d) c->tw[d] = ws + L.off_tw + (size_t)d * kMaxExtent * 16;
     c->D = ws + L.off_d;
     c->Q = ws + L.off_q;
-    c->Gb = ws + L.off_g;
-    c->Acc = L.acc ? ws + L.off_acc : nullptr;
+    c->U0 = ws + L.off_links;
+    for (int i = 0; i < 2; ++i) c->Hb[i] = ws + L.off_h[i];
     c->mlp = L.learned ? reinterpret_cast<float*>(ws + L.off_mlp) : nullptr;
     c->mtab = L.learned ? ws + L.off_mtab : nullptr;
     for (int i = 0; i < 4; ++i) c->spec[i] = L.record ? ws + L.off_spec[i] : nullptr;
@@ -1027,7 +1017,6 @@ void carve(gf_ctx* c, const gf_params& p, const Layout& L, double* d_links, unsi
         c->tg.h[d] = L.n[d] / 2 + 1;
     }
     c->tg.count = L.ntuples;
-    for (int i = 0; i < 2; ++i) c->Lb[i] = ws + L.off_links[i];
     c->k_host = 0;
     c->phase = L.fp32 ? 0 : 1;
     for (int d = 0; d < 4; ++d) {
@@ -1084,13 +1073,13 @@ gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_l
         return s;
     GF_DISPATCH(c, launch_pack_t, c, c->links_user);
     s = launched(c, "pack launch");
-    if (s == GF_OK && c->Acc) {
+    if (s == GF_OK) {  // no update applied yet: H = 1 in buffer 0
         if (L.fp32)
-            hipLaunchKernelGGL(k_gauge_identity<float>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st, cxp<float>(c->Acc),
-                               L.ps, L.vol);
+            hipLaunchKernelGGL(k_gauge_identity<float>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st,
+                               cxp<float>(c->Hb[0]), L.ps, L.vol);
         else
             hipLaunchKernelGGL(k_gauge_identity<double>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st,
-                               cxp<double>(c->Acc), L.ps, L.vol);
+                               cxp<double>(c->Hb[0]), L.ps, L.vol);
         s = launched(c, "identity launch");
     }
     if (s == GF_OK && measure) s = launch_measure(c);
@@ -1184,10 +1173,10 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
             if (tol > 0.0 && !(a->h_head->theta < tol)) return fail(c, GF_ENOTCONV, "max_iter reached before theta < tol");
             return GF_OK;
         }
-        // hand-over: the double child's buffer 0 holds the input links
-        hipLaunchKernelGGL(k_apply_accumulated<9>, dim3(b->L.nblk), dim3(kSiteThreads), 0, b->st,
-                           links_of<double, 9>(b, 0), reinterpret_cast<const cx<float>*>(a->Acc), a->L.ps,
-                           reinterpret_cast<cx<double>*>(b->Acc), b->L.ps, b->geom);
+        // hand-over: the double child holds the input links; it takes over the float transform in double
+        hipLaunchKernelGGL(k_promote_h, dim3(b->L.nblk), dim3(kSiteThreads), 0, b->st,
+                           reinterpret_cast<const cx<float>*>(a->Hb[cur(a)]), a->L.ps,
+                           reinterpret_cast<cx<double>*>(b->Hb[cur(b)]), b->L.ps, b->L.vol);
         s = launched(b, "hand-over launch");
         if (s == GF_OK) s = launch_measure(b);
         if (s == GF_OK) s = read_head(b);
@@ -1211,8 +1200,8 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
 
 template <typename T, int NE>
 void launch_plaquette_t(gf_ctx* c) {
-    hipLaunchKernelGGL((k_plaquette<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
-                       links_of<T, NE>(c, cur(c)), c->geom, c->part);
+    hipLaunchKernelGGL((k_plaquette_h<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c),
+                       reinterpret_cast<const cx<T>*>(c->Hb[cur(c)]), c->geom, c->part);
     hipLaunchKernelGGL(k_plaquette_sum, dim3(1), dim3(256), 0, c->st, c->part, c->L.nblk,
                        1.0 / (18.0 * (double)c->L.vol), c->ctl);
 }
@@ -1526,9 +1515,9 @@ gf_status advance_group(gf_ctx* c, BatchGroup& g, double tol, std::vector<BatchO
                         continue;
                     }
                     gf_ctx* w = g.view[1][i];
-                    hipLaunchKernelGGL(k_apply_accumulated<9>, dim3(w->L.nblk), dim3(kSiteThreads), 0, w->st,
-                                       links_of<double, 9>(w, 0), reinterpret_cast<const cx<float>*>(v->Acc),
-                                       v->L.ps, reinterpret_cast<cx<double>*>(w->Acc), w->L.ps, w->geom);
+                    hipLaunchKernelGGL(k_promote_h, dim3(w->L.nblk), dim3(kSiteThreads), 0, w->st,
+                                       reinterpret_cast<const cx<float>*>(v->Hb[cur(v)]), v->L.ps,
+                                       reinterpret_cast<cx<double>*>(w->Hb[cur(w)]), w->L.ps, w->L.vol);
                     s = launched(w, "hand-over launch");
                     if (s == GF_OK) s = launch_measure(w);
                     if (s != GF_OK) return fail(c, s, w->err);
@@ -2106,11 +2095,11 @@ gf_status gf_stage_filter(gf_ctx* c, const void* d_in, void* d_out) {
     if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
     if (c->L.fp32) {
         field_pack<float>(c, d_in, c->Q);
-        stage_spectral<float>(c, false);
+        stage_spectral<float>(c, nullptr);
         field_unpack<float>(c, c->Q, d_out);
     } else {
         field_pack<double>(c, d_in, c->Q);
-        stage_spectral<double>(c, false);
+        stage_spectral<double>(c, nullptr);
         field_unpack<double>(c, c->Q, d_out);
     }
     gf_status s = launched(c, "filter launch");
@@ -2123,14 +2112,16 @@ gf_status gf_stage_gauge(gf_ctx* c, const void* d_in, void* d_out) {
     if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (c->L.mixed) c = active(c);
     if (!d_in || !d_out) return fail(c, GF_EINVAL, "null pointer");
+    // g goes to the transform buffer the next update would overwrite anyway
+    void* rows = c->Hb[1 - cur(c)];
     if (c->L.fp32) {
         field_pack<float>(c, d_in, c->Q);
-        stage_spectral<float>(c, true);
-        gauge_unpack<float>(c, d_out);
+        stage_spectral<float>(c, rows);
+        gauge_unpack<float>(c, rows, d_out);
     } else {
         field_pack<double>(c, d_in, c->Q);
-        stage_spectral<double>(c, true);
-        gauge_unpack<double>(c, d_out);
+        stage_spectral<double>(c, rows);
+        gauge_unpack<double>(c, rows, d_out);
     }
     gf_status s = launched(c, "gauge launch");
     if (s != GF_OK) return s;
@@ -2216,15 +2207,10 @@ gf_status gf_get_gauge(gf_ctx* c, void* d_out) {
     if (c->batch) return fail(c, GF_ESTATE, "a batch context only takes the batch calls");
     if (!d_out) return fail(c, GF_EINVAL, "d_out is NULL");
     gf_ctx* a = active(c);
-    if (!a->Acc) return fail(c, GF_ESTATE, "the accumulated gauge transform is not kept (GF_FLAG_ACCUMULATE_GAUGE)");
     if (a->L.fp32)
-        hipLaunchKernelGGL(k_gauge_unpack<float>, dim3(a->L.nblk), dim3(kSiteThreads), 0, a->st,
-                           reinterpret_cast<const cx<float>*>(a->Acc), a->L.ps, reinterpret_cast<double*>(d_out),
-                           a->L.vol);
+        gauge_unpack<float>(a, a->Hb[cur(a)], d_out);
     else
-        hipLaunchKernelGGL(k_gauge_unpack<double>, dim3(a->L.nblk), dim3(kSiteThreads), 0, a->st,
-                           reinterpret_cast<const cx<double>*>(a->Acc), a->L.ps, reinterpret_cast<double*>(d_out),
-                           a->L.vol);
+        gauge_unpack<double>(a, a->Hb[cur(a)], d_out);
     gf_status s = launched(a, "gauge unpack launch");
     if (s == GF_OK) s = check_hip(a, hipStreamSynchronize(a->st), "sync");
     return s == GF_OK ? s : fail(c, s, a->err);

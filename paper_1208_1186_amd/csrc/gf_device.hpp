@@ -97,6 +97,13 @@ __device__ __forceinline__ void third_row(const cx<T>* r1, const cx<T>* r2, cx<T
     r3[2] = conj(cmul(r1[0], r2[1]) - cmul(r1[1], r2[0]));
 }
 
+// 1/sqrt(x) in double from the hardware estimate and one Newton step, y (3 - x y^2) / 2, which squares its
+// relative error: ample for results that are then rounded to float.
+__device__ __forceinline__ double rsqrt_newton(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
+
 // Row Gram-Schmidt onto SU(3): normalise r1, orthogonalise and normalise r2,
 // rebuild r3 from unitarity and det = 1.
 template <typename T>
@@ -117,19 +124,42 @@ __device__ __forceinline__ void reunitarize(su3<T>& m) {
     third_row(m.e[0], m.e[1], m.e[2]);
 }
 
-// Row Gram-Schmidt in double precision whatever the storage type: a float matrix is promoted, projected
-// onto SU(3) in double and rounded back, so the bulk float iterations keep their reunitarisation in FP64.
+// Row Gram-Schmidt in double precision whatever the storage type: rows 1-2 of a float matrix are
+// promoted, orthonormalised in double and rounded back, and row 3 is rebuilt from them in float, so the
+// bulk float iterations keep their reunitarisation in FP64.
 template <typename T>
 __device__ __forceinline__ void reunitarize_fp64(su3<T>& m) {
     if constexpr (sizeof(T) == 8) {
         reunitarize(m);
     } else {
-        su3<double> d;
+        cx<double> r1[3], r2[3];
+        double n1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) d.e[k / 3][k % 3] = {(double)m.e[k / 3][k % 3].re, (double)m.e[k / 3][k % 3].im};
-        reunitarize(d);
+        for (int j = 0; j < 3; ++j) {
+            r1[j] = {(double)m.e[0][j].re, (double)m.e[0][j].im};
+            r2[j] = {(double)m.e[1][j].re, (double)m.e[1][j].im};
+            n1 += norm2(r1[j]);
+        }
+        const double i1 = rsqrt_newton(n1);
+        cx<double> d = {0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < 9; ++k) m.e[k / 3][k % 3] = {(T)d.e[k / 3][k % 3].re, (T)d.e[k / 3][k % 3].im};
+        for (int j = 0; j < 3; ++j) {
+            r1[j] = cscale(r1[j], i1);
+            d = cfma(d, conj(r1[j]), r2[j]);
+        }
+        double n2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            r2[j] = r2[j] - cmul(d, r1[j]);
+            n2 += norm2(r2[j]);
+        }
+        const double i2 = rsqrt_newton(n2);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            m.e[0][j] = {(T)r1[j].re, (T)r1[j].im};
+            m.e[1][j] = {(T)(r2[j].re * i2), (T)(r2[j].im * i2)};
+        }
+        third_row(m.e[0], m.e[1], m.e[2]);
     }
 }
 
@@ -181,19 +211,14 @@ __device__ __forceinline__ su3<T> mul_rows(const su3<T>& a, const su3<T>& b) {
     return c;
 }
 
-// U'_mu(x) = gl U_mu(x) gr^dag with gl = g(x), gr = g(x + mu): rows 1-2 formed, row 3 rebuilt from
-// unitarity (double), or rows 1-2 re-orthonormalised in double precision (float). The loop kernel calls
-// it for a lane's own link and for the back neighbour's updated link U'_mu(x - mu) (gl = g(x - mu),
-// gr = g(x)); the same inlined code on the same operands gives the same bits as the neighbour's own
-// result, so the divergence is that of the stored links in every traversal.
+// The link gl U gr^dag (gl, gr: the transform at x and at x + mu): rows 1-2 formed, row 3 rebuilt from
+// unitarity. The loop kernel calls it for a lane's own link and for the back neighbour's link U_mu(x - mu);
+// the same inlined code on the same operands gives the same bits as the neighbour's own result, so every
+// traversal of the lattice computes the same divergence.
 template <typename T>
 __device__ __forceinline__ su3<T> updated_link(const su3<T>& gl, const su3<T>& u, const su3<T>& gr) {
     su3<T> un = mul_adj<T, 2>(mul_rows<T, 2>(gl, u), gr);
-    if constexpr (sizeof(T) == 4) {
-        reunitarize_fp64(un);
-    } else {
-        third_row(un.e[0], un.e[1], un.e[2]);
-    }
+    third_row(un.e[0], un.e[1], un.e[2]);
     return un;
 }
 

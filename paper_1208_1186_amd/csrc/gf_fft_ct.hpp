@@ -138,20 +138,22 @@ __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     }
 }
 
-// Inverse (x, y) pass of the four fields of one (z, t) plane, then g rows 1-2 -> G.
+// Inverse (x, y) pass of the four fields of one (z, t) plane, then g and the update of the stored
+// transform, Hout = reunitarize(g Hin) (rows 1-2); with Hin null, g itself goes to Hout.
 constexpr int gauge_ept(int nx, int ny) { return 4 * nx * ny <= 8 * 1024 ? 8 : 16; }
 
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
-    k_fft_xy_gauge_ct(const cx<T>* __restrict__ Q, size_t zps, cx<T>* __restrict__ G, size_t gps,
-                      const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
-                      int force, Batch bt, int exact) {
+    k_fft_xy_gauge_ct(const cx<T>* __restrict__ Q, size_t zps, const cx<T>* __restrict__ Hin,
+                      cx<T>* __restrict__ Hout, size_t gps, const cx<T>* __restrict__ twgx,
+                      const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl, int force, Batch bt, int exact) {
     constexpr int RS = NX + 1, P = NX * NY, PL = NY * RS, E = 4 * P;
     constexpr int NT = ct_threads(E, gauge_ept(NX, NY));
     {
         const size_t bo = boff(bt);
         Q = bshift(Q, bo);
-        G = bshift(G, bo);
+        Hin = bshift(Hin, bo);
+        Hout = bshift(Hout, bo);
         twgx = bshift(twgx, bo);
         twgy = bshift(twgy, bo);
         ctl = bshift(ctl, bo);
@@ -180,15 +182,15 @@ __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
         const int r = r0 + threadIdx.x;
         if (P % NT == 0 || r < P) {
             const int li = (r / NX) * RS + r % NX;
-            const su3<T> g = g_from_packed(buf[li], buf[PL + li], buf[2 * PL + li], buf[3 * PL + li], exact != 0);
-            // float: streaming stores of g (2 us faster at 32^4, no cost in the update that reads it)
+            su3<T> g = g_from_packed(buf[li], buf[PL + li], buf[2 * PL + li], buf[3 * PL + li], exact != 0);
+            if (Hin != nullptr) {
+                su3<T> h;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                if constexpr (sizeof(T) == 4)
-                    nt_store(G + (size_t)k * gps + base + r, g.e[k / 3][k % 3]);
-                else
-                    G[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
+                for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = Hin[(size_t)k * gps + base + r];
+                g = gauge_times(g, h);
             }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Hout[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
         }
     }
 }

@@ -1,14 +1,20 @@
 // HIP kernels of the Fourier-accelerated steepest-descent iteration.
 //
-// One loop iteration, from k to k + 1 applied updates (paper, Section 1 for
-// the method, Section 2.2 for the per-element FFT split 2D + 2D):
+// The links are kept implicitly: the input links U0 never change, and the
+// gauge transform H accumulated by the updates is stored instead (rows 1-2,
+// six planes), so that the current links are U_mu(x) = H(x) U0_mu(x)
+// H(x+mu)^dag. One update U -> g U g(x+mu)^dag is then H -> g H: 96 bytes per
+// site written instead of the 576 of four FP64 links (the iteration is
+// memory-bound). One loop iteration, from k to k + 1 applied updates (paper,
+// Section 1 for the method, Section 2.2 for the per-element FFT split 2D + 2D):
 //   k_fft_xy<fwd>   Delta (buffer D) -> 2D FFT over (x, y) -> buffer Q; block 0
-//                   also reduces the theta/F partials left by the previous step
+//                   also reduces the theta/F partials left by the loop kernel
 //   k_fft_zt        in Q: 2D FFT over (z, t), times (alpha/2) K(p) / V, inverse
 //   k_fft_xy_gauge  Q -> inverse 2D FFT over (x, y) -> g = reunitarize(1 +
-//                   (alpha/2) Delta~), rows 1-2 stored in buffer G
-//   k_update_measure  U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag (links ping-pong),
-//                   Delta of the new links -> D, FP64 block partials of F, theta
+//                   (alpha/2) Delta~), H_{k+1} = reunitarize(g H_k) -> the
+//                   other transform buffer
+//   k_update_measure  the links H U0 H(x+mu)^dag of H_{k+1}: their divergence
+//                   -> D, FP64 block partials of F and theta
 // The partials are reduced by the next iteration's k_fft_xy (or by k_finalize
 // before the host reads the control block), in a fixed order.
 //
@@ -46,29 +52,6 @@ __global__ void __launch_bounds__(kSiteThreads) k_pack(const double* __restrict_
 #pragma unroll
         for (int k = 0; k < 9; ++k) v.e[k / 3][k % 3] = {(T)u.e[k / 3][k % 3].re, (T)u.e[k / 3][k % 3].im};
         L.store(mu, s, v);
-    }
-}
-
-// SoA planes -> canonical links; a two-row link gets its third row rebuilt in double.
-template <typename T, int NE>
-__global__ void __launch_bounds__(kSiteThreads) k_unpack(Links<T, NE> L, double* __restrict__ canon, int64_t vol) {
-    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
-    if (s >= vol) return;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        su3<double> u;
-#pragma unroll
-        for (int k = 0; k < NE; ++k) {
-            cx<T> e = L.p[L.at(mu, k, s)];
-            u.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
-        }
-        if constexpr (NE == 6) third_row(u.e[0], u.e[1], u.e[2]);
-        double* dst = canon + (s * 4 + mu) * 18;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) {
-            dst[2 * k] = u.e[k / 3][k % 3].re;
-            dst[2 * k + 1] = u.e[k / 3][k % 3].im;
-        }
     }
 }
 
@@ -147,6 +130,56 @@ __global__ void __launch_bounds__(kSiteThreads) k_gauge_unpack(const cx<T>* __re
     }
 }
 
+// Row 1-2 planes of a transform at site s, promoted to double, row 3 rebuilt in double.
+template <typename T>
+__device__ __forceinline__ su3<double> rows_at_fp64(const cx<T>* __restrict__ G, size_t gps, int64_t s) {
+    su3<double> g;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const cx<T> e = G[(size_t)k * gps + s];
+        g.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
+    }
+    third_row(g.e[0], g.e[1], g.e[2]);
+    return g;
+}
+
+// Egress: the current links U_mu(x) = H(x) U0_mu(x) H(x+mu)^dag -> canonical links (complex double
+// [s][mu][3][3]), formed in double from the stored factors (float factors promoted exactly); with
+// two-row storage rows 1-2 are formed and row 3 is rebuilt from them, as for the stored links.
+template <typename T, int NE>
+__global__ void __launch_bounds__(kSiteThreads) k_unpack_h(Links<T, NE> U0, const cx<T>* __restrict__ H, Geom g,
+                                                           double* __restrict__ canon) {
+    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
+    if (s >= g.vol) return;
+    int c[4];
+    site_coords(g, s, c);
+    const su3<double> h0 = rows_at_fp64(H, U0.ps, s);
+#pragma unroll
+    for (int mu = 0; mu < 4; ++mu) {
+        su3<double> u;
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+            const cx<T> e = U0.p[U0.at(mu, k, s)];
+            u.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
+        }
+        if constexpr (NE == 6) third_row(u.e[0], u.e[1], u.e[2]);
+        const su3<double> h1 = rows_at_fp64(H, U0.ps, site_fwd(g, s, c, mu));
+        su3<double> v;
+        if constexpr (NE == 6) {  // two-row storage: the third row of the result is rebuilt from its first two
+            v = mul_adj<double, 2>(mul_rows<double, 2>(h0, u), h1);
+            third_row(v.e[0], v.e[1], v.e[2]);
+        } else {
+            v = mul_adj<double, 3>(mul(h0, u), h1);
+        }
+        double* dst = canon + (s * 4 + mu) * 18;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            dst[2 * k] = v.e[k / 3][k % 3].re;
+            dst[2 * k + 1] = v.e[k / 3][k % 3].im;
+        }
+    }
+}
+
 // ------------------------------------------------------------ reductions
 // Fixed-order FP64 sum of n block partials (F part, theta part) by the
 // calling block, independent of its size: 256 virtual lanes each add every
@@ -215,11 +248,31 @@ __global__ void __launch_bounds__(256) k_finalize(const double2* __restrict__ pa
     reduce_partials(part, n, inv3v, inv12v, ctl, mode);
 }
 
-// Plaquette (gauge invariant, for checks): per site the six (mu < nu) loops
-// Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] = Re sum_ij A_ij conj(B_ij)
-// with A = U_mu(x) U_nu(x+mu), B = U_nu(x) U_mu(x+nu); one FP64 partial per block.
+// Current link U_mu(y) = H(y) U0_mu(y) H(y+mu)^dag (all three rows), yf the site y + mu.
 template <typename T, int NE>
-__global__ void __launch_bounds__(kSiteThreads) k_plaquette(Links<T, NE> L, Geom g, double2* __restrict__ part) {
+__device__ __forceinline__ su3<T> link_h(const Links<T, NE>& U0, const cx<T>* __restrict__ H, int mu, int64_t y,
+                                         int64_t yf) {
+    const su3<T> u = U0.load(mu, y);
+    return mul_adj<T, 3>(mul(g_rows_at(H, U0.ps, y), u), g_rows_at(H, U0.ps, yf));
+}
+
+// y + d for a direction d known only at run time (a switch, so that no array is indexed by d).
+__device__ __forceinline__ int64_t fwd_site(const Geom& g, int64_t y, const int cy[4], int d) {
+    switch (d) {
+        case 0: return site_fwd(g, y, cy, 0);
+        case 1: return site_fwd(g, y, cy, 1);
+        case 2: return site_fwd(g, y, cy, 2);
+        default: return site_fwd(g, y, cy, 3);
+    }
+}
+
+// Plaquette of the current links (gauge invariant, for checks): per site the six (mu < nu) loops
+// Re Tr[U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag] = Re sum_ij A_ij conj(B_ij)
+// with A = U_mu(x) U_nu(x+mu), B = U_nu(x) U_mu(x+nu), every link formed from H and U0; one FP64
+// partial per block.
+template <typename T, int NE>
+__global__ void __launch_bounds__(kSiteThreads) k_plaquette_h(Links<T, NE> U0, const cx<T>* __restrict__ H, Geom g,
+                                                              double2* __restrict__ part) {
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
     double sum = 0.0, none = 0.0;
     if (s < g.vol) {
@@ -227,11 +280,17 @@ __global__ void __launch_bounds__(kSiteThreads) k_plaquette(Links<T, NE> L, Geom
         site_coords(g, s, c);
 #pragma unroll 1
         for (int mu = 0; mu < 4; ++mu) {
-            const su3<T> um = L.load(mu, s);
+            const int64_t sm = fwd_site(g, s, c, mu);
+            int cm[4];
+            site_coords(g, sm, cm);
+            const su3<T> um = link_h(U0, H, mu, s, sm);
 #pragma unroll 1
             for (int nu = mu + 1; nu < 4; ++nu) {
-                const su3<T> a = mul(um, L.load(nu, site_fwd(g, s, c, mu)));
-                const su3<T> b = mul(L.load(nu, s), L.load(mu, site_fwd(g, s, c, nu)));
+                const int64_t sn = fwd_site(g, s, c, nu);
+                int cn[4];
+                site_coords(g, sn, cn);
+                const su3<T> a = mul(um, link_h(U0, H, nu, sm, fwd_site(g, sm, cm, nu)));
+                const su3<T> b = mul(link_h(U0, H, nu, s, sn), link_h(U0, H, mu, sn, fwd_site(g, sn, cn, mu)));
 #pragma unroll
                 for (int k = 0; k < 9; ++k) {
                     const cx<T> x = a.e[k / 3][k % 3], y = b.e[k / 3][k % 3];
@@ -291,73 +350,35 @@ __global__ void k_set_tol(Ctl* ctl, double tol) {
     }
 }
 
-// ------------------------------------------------------------- divergence
-// Delta(x) from sum_mu [U_mu(x - mu) - U_mu(x)]; per-block FP64 partial sums
-// of Re Tr U_mu(x) (for F) and of Tr Delta Delta^dag (for theta).
-template <typename T, int NE>
-__global__ void __launch_bounds__(kSiteThreads) k_divergence(Links<T, NE> L, cx<T>* __restrict__ Z, size_t zps,
-                                                             Geom g, double2* __restrict__ part) {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t s = (int64_t)b * kSiteThreads + threadIdx.x;
-    double fsum = 0.0, tsum = 0.0;
-    if (s < g.vol) {
-        int c[4];
-        site_coords(g, s, c);
-        su3<T> m;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) m.e[i][j] = {T(0), T(0)};
-#pragma unroll
-        for (int mu = 0; mu < 4; ++mu) {
-            const su3<T> u = L.load(mu, s);
-            const su3<T> ub = L.load(mu, site_back(g, s, c, mu));
-#pragma unroll
-            for (int i = 0; i < 3; ++i)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) m.e[i][j] = m.e[i][j] + (ub.e[i][j] - u.e[i][j]);
-            fsum += (double)u.e[0][0].re + (double)u.e[1][1].re + (double)u.e[2][2].re;
-        }
-        const cx<T> z0 = m.e[0][1] - conj(m.e[1][0]);
-        const cx<T> z1 = m.e[0][2] - conj(m.e[2][0]);
-        const cx<T> z2 = m.e[1][2] - conj(m.e[2][1]);
-        const T tr = (m.e[0][0].im + m.e[1][1].im + m.e[2][2].im) / T(3);
-        const T d0 = T(2) * (m.e[0][0].im - tr), d1 = T(2) * (m.e[1][1].im - tr);
-        Z[s] = z0;
-        Z[zps + s] = z1;
-        Z[2 * zps + s] = z2;
-        Z[3 * zps + s] = {d0, d1};
-        const double e0 = norm2(z0), e1 = norm2(z1), e2 = norm2(z2);
-        const double dd0 = d0, dd1 = d1;
-        tsum = 2.0 * (e0 + e1 + e2) + dd0 * dd0 + dd1 * dd1 + (dd0 + dd1) * (dd0 + dd1);
-    }
-    block_sum2<kSiteThreads>(fsum, tsum);
-    if (threadIdx.x == 0) part[b] = make_double2(fsum, tsum);
-}
-
 // ------------------------------------------------------- single update
 template <typename T>
 __device__ __forceinline__ su3<T> g_at_packed(const cx<T>* __restrict__ Z, size_t zps, int64_t s, bool exact) {
     return g_from_packed(Z[s], Z[zps + s], Z[2 * zps + s], Z[3 * zps + s], exact);
 }
 
-// U_mu(x) -> g(x) U_mu(x) g(x+mu)^dag in place, g = reunitarize(1 + Z(x)) with
-// Z holding (alpha/2) Delta~ packed. Used by the single-stage entry point; the
-// arithmetic is the loop kernel's (updated_link).
-template <typename T, int NE>
-__global__ void __launch_bounds__(kSiteThreads) k_update(Links<T, NE> L, const cx<T>* __restrict__ Z, size_t zps,
-                                                         Geom g, int exact) {
-    const int b = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t s = (int64_t)b * kSiteThreads + threadIdx.x;
-    if (s >= g.vol) return;
-    int c[4];
-    site_coords(g, s, c);
-    const su3<T> g0 = g_at_packed(Z, zps, s, exact != 0);
+// H <- reunitarize(g H): rows 1-2 of g times H (third row rebuilt), Gram-Schmidt (in double for float).
+template <typename T>
+__device__ __forceinline__ su3<T> gauge_times(const su3<T>& g, su3<T> h) {
+    third_row(h.e[0], h.e[1], h.e[2]);
+    su3<T> r = mul_rows<T, 2>(g, h);
+    reunitarize_fp64(r);
+    return r;
+}
+
+// One update of the stored transform in place, H(x) <- reunitarize(g(x) H(x)), g = reunitarize(1 + Z(x))
+// with Z holding (alpha/2) Delta~ packed: the current links become g U g(x+mu)^dag. Used by the
+// single-stage entry point (the loop does the same in the inverse (x, y) pass).
+template <typename T>
+__global__ void __launch_bounds__(kSiteThreads) k_h_update(const cx<T>* __restrict__ Z, size_t zps, cx<T>* __restrict__ H,
+                                                           size_t hps, int64_t vol, int exact) {
+    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
+    if (s >= vol) return;
+    su3<T> h;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const su3<T> g1 = g_at_packed(Z, zps, site_fwd(g, s, c, mu), exact != 0);
-        L.store(mu, s, updated_link(g0, L.load(mu, s), g1));
-    }
+    for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = H[(size_t)k * hps + s];
+    const su3<T> r = gauge_times(g_at_packed(Z, zps, s, exact != 0), h);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) H[(size_t)k * hps + s] = r.e[k / 3][k % 3];
 }
 
 // ------------------------------------------------ loop kernel: update + divergence
@@ -410,22 +431,22 @@ __device__ __forceinline__ double xor_sum4(double v) {
     return __hiloint2double(bh[0], bl[0]) + __hiloint2double(bh[1], bl[1]);
 }
 
-// Loop kernel: reads links Lin and the gauge rows G and writes U' = g U g(x+mu)^dag to Lout, the
-// divergence of U' to D and one FP64 partial (F, theta) per block of 64 sites. Four lanes per site, one
-// direction each: a wave covers 16 consecutive sites x 4 directions, so every load and store is a
-// 16-site run in one plane. Lane mu updates U_mu(x) and needs U'_mu(x - mu) for the divergence; all
-// loads are issued before any arithmetic, so a wave waits for one memory round trip per site block.
-// Lin and Lout must differ.
+// Loop kernel: the divergence of the current links U_mu(x) = H(x) U0_mu(x) H(x+mu)^dag to D and one
+// FP64 partial (F, theta) per block of 64 sites. Four lanes per site, one direction each: a wave covers
+// 16 consecutive sites x 4 directions, so every load and store is a 16-site run in one plane. Lane mu
+// forms U_mu(x) and the back neighbour's U_mu(x - mu) (the divergence needs both; neither is stored);
+// all loads are issued before any arithmetic, so a wave waits for one memory round trip per site block.
+// Per site it reads the four U0 links and H (736 B in FP64-18) and writes Delta (64 B).
 //
 // Traversals (autotuned per shape and precision; partials are stored by site block, so every traversal
 // gives the same bits):
 //  zb >= 1  one block per site block. The blocks sweep each (x, y) plane; with zb > 1 (zb divides Nz,
 //           64 divides the plane) the planes are visited with z in groups of zb inside the t loop,
 //           (z mod zb, t, z / zb), so that a site's t neighbour was read zb planes earlier and may still
-//           be in the XCD's L2. Lane mu forms U'_mu(x - mu) from the old neighbour link and g.
+//           be in the XCD's L2.
 //  zb == 0  t-march: one block per 64-site run of the (x, y, z) volume, stepping through t. The lane of
-//           direction t keeps the anti-Hermitian part of its own U'_t from the previous step, which is
-//           the U'_t(x - t) of this one, so U_t(x - t) and g(x - t) are never fetched again (except at
+//           direction t keeps the anti-Hermitian part of its own U_t from the previous step, which is
+//           the U_t(x - t) of this one, so U0_t(x - t) and H(x - t) are never fetched again (except at
 //           the block's first step). The blocks of one XCD (consecutive runs, xcd_remap) hold a slab of
 //           the (x, y, z) volume and step through t together, so the y and z neighbours they read are in
 //           that XCD's L2. Needs Nx Ny Nz to be a multiple of 64.
@@ -434,10 +455,9 @@ constexpr int kFusedSites = kFusedThreads / 4;
 
 template <typename T, int NE>
 struct LoopIO {
-    Links<T, NE> Lin, Lout;
-    const cx<T>* __restrict__ G;
+    Links<T, NE> U0;
+    const cx<T>* __restrict__ H;
     cx<T>* __restrict__ D;
-    cx<T>* __restrict__ acc_g;
     size_t ps;
 };
 
@@ -467,44 +487,35 @@ __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const G
         const int64_t sfw = cm == nm - 1 ? s - (int64_t)(nm - 1) * sm : s + sm;
         const int64_t sbk = cm == 0 ? s + (int64_t)(nm - 1) * sm : s - sm;
         // every load first; a lane that reuses its kept back neighbour reads its own site instead (lines
-        // already on their way for its own link and g, so no extra traffic, and no branch around the loads)
+        // already on their way for its own link and H, so no extra traffic, and no branch around the loads)
         const int64_t sld = reuse ? s : sbk;
-        su3<T> g0, gfw, gb, u, ub;
+        su3<T> h0, hfw, hb, u, ub;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            g0.e[k / 3][k % 3] = io.G[(size_t)k * ps + s];
-            gfw.e[k / 3][k % 3] = io.G[(size_t)k * ps + sfw];
-            gb.e[k / 3][k % 3] = io.G[(size_t)k * ps + sld];
+            h0.e[k / 3][k % 3] = io.H[(size_t)k * ps + s];
+            hfw.e[k / 3][k % 3] = io.H[(size_t)k * ps + sfw];
+            hb.e[k / 3][k % 3] = io.H[(size_t)k * ps + sld];
         }
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
-            // float: the own link streams past the cache (measured 3 % faster); double: plain loads
-            u.e[k / 3][k % 3] = sizeof(T) == 4 ? nt_load(io.Lin.p + io.Lin.at(mu, k, s)) : io.Lin.p[io.Lin.at(mu, k, s)];
-            ub.e[k / 3][k % 3] = io.Lin.p[io.Lin.at(mu, k, sld)];
+            u.e[k / 3][k % 3] = io.U0.p[io.U0.at(mu, k, s)];
+            ub.e[k / 3][k % 3] = io.U0.p[io.U0.at(mu, k, sld)];
         }
-        third_row(g0.e[0], g0.e[1], g0.e[2]);
-        third_row(gfw.e[0], gfw.e[1], gfw.e[2]);
-        third_row(gb.e[0], gb.e[1], gb.e[2]);
+        third_row(h0.e[0], h0.e[1], h0.e[2]);
+        third_row(hfw.e[0], hfw.e[1], hfw.e[2]);
+        third_row(hb.e[0], hb.e[1], hb.e[2]);
         if constexpr (NE == 6) {
             third_row(u.e[0], u.e[1], u.e[2]);
             third_row(ub.e[0], ub.e[1], ub.e[2]);
         }
-        const su3<T> un = updated_link(g0, u, gfw);
-        io.Lout.store(mu, s, un);
+        const su3<T> un = updated_link(h0, u, hfw);  // U_mu(x)
         fsum = (double)un.e[0][0].re + (double)un.e[1][1].re + (double)un.e[2][2].re;
         AhAcc<T> own;
         own.set(un);
-        acc.set(updated_link(gb, ub, g0));  // U'_mu(x - mu)
+        acc.set(updated_link(hb, ub, h0));  // U_mu(x - mu)
         if (reuse) acc = *keep;
         acc.sub(own);
         if (keep != nullptr && mu == 3) *keep = own;
-        if (io.acc_g != nullptr && mu == 0) {
-            su3<T> a = g_rows_at(io.acc_g, ps, s);
-            a = mul_rows<T, 2>(g0, a);
-            reunitarize_fp64(a);
-#pragma unroll
-            for (int k = 0; k < 6; ++k) io.acc_g[(size_t)k * ps + s] = a.e[k / 3][k % 3];
-        }
     }
     acc.o01.re = xor_sum4(acc.o01.re);
     acc.o01.im = xor_sum4(acc.o01.im);
@@ -520,12 +531,8 @@ __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const G
         const T d0 = T(2) * (acc.d0 - tr), d1 = T(2) * (acc.d1 - tr);
         const cx<T> z0 = acc.o01, z1 = acc.o02, z2 = acc.o12;
         const cx<T> out = mu == 0 ? z0 : mu == 1 ? z1 : mu == 2 ? z2 : cx<T>{d0, d1};
-        // double: streaming stores; float: plain stores, which leave D in the last-level cache for the
-        // (x, y) pass that reads it next (measured 4 us faster there, 2 us slower here in double)
-        if constexpr (sizeof(T) == 4)
-            io.D[(size_t)mu * ps + s] = out;
-        else
-            nt_store(io.D + (size_t)mu * ps + s, out);
+        // plain stores: D is read again by the (x, y) pass right after this kernel
+        io.D[(size_t)mu * ps + s] = out;
         if (mu == 0) {
             const double e0 = norm2(z0), e1 = norm2(z1), e2 = norm2(z2);
             const double dd0 = d0, dd1 = d1;
@@ -535,27 +542,24 @@ __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const G
     block_sum2<kFusedThreads>(fsum, tsum);
 }
 
-// With acc_g set (six planes, ps apart) the lane of direction 0 also accumulates the total gauge
-// transform in place: A(x) <- reunitarize(g(x) A(x)) (in double precision). TM: the t-march traversal
-// (zb is then ignored); its own instantiation, so that the flat traversals keep their register budget.
+// force: measure even when the control block says the loop has stopped (a standalone measurement).
+// TM: the t-march traversal (zb is then ignored); its own instantiation, so that the other traversals
+// keep their register budget.
 template <typename T, int NE, bool TM>
-__global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE> Lin, Links<T, NE> Lout,
-                                                                  const cx<T>* __restrict__ G, cx<T>* __restrict__ D,
-                                                                  size_t ps, Geom g, double2* __restrict__ part,
-                                                                  Ctl* ctl, cx<T>* __restrict__ acc_g, Batch bt,
-                                                                  int zb) {
-    LoopIO<T, NE> io{Lin, Lout, G, D, acc_g, ps};
+__global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE> U0, const cx<T>* __restrict__ H,
+                                                                     cx<T>* __restrict__ D, size_t ps, Geom g,
+                                                                     double2* __restrict__ part, Ctl* ctl, Batch bt,
+                                                                     int zb, int force) {
+    LoopIO<T, NE> io{U0, H, D, ps};
     {
         const size_t bo = boff(bt);
-        io.Lin.p = bshift(io.Lin.p, bo);
-        io.Lout.p = bshift(io.Lout.p, bo);
-        io.G = bshift(io.G, bo);
+        io.U0.p = bshift(io.U0.p, bo);
+        io.H = bshift(io.H, bo);
         io.D = bshift(io.D, bo);
-        io.acc_g = bshift(io.acc_g, bo);
         part = bshift(part, bo);
         ctl = bshift(ctl, bo);
     }
-    if (ctl->done) return;
+    if (!force && ctl->done) return;
     const int b = xcd_remap(blockIdx.x, gridDim.x);
     const int lane = threadIdx.x & 63;
     const int mu = lane >> 4;
@@ -590,7 +594,7 @@ __global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE
 }
 
 // ------------------------------------------------ mixed-precision hand-over
-// Rows 1-2 of the identity in the six planes of an accumulated gauge transform.
+// Rows 1-2 of the identity in the six planes of a transform.
 template <typename T>
 __global__ void __launch_bounds__(kSiteThreads) k_gauge_identity(cx<T>* __restrict__ A, size_t ps, int64_t vol) {
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
@@ -599,39 +603,22 @@ __global__ void __launch_bounds__(kSiteThreads) k_gauge_identity(cx<T>* __restri
     for (int k = 0; k < 6; ++k) A[(size_t)k * ps + s] = {(k == 0 || k == 4) ? T(1) : T(0), T(0)};
 }
 
-// U_mu(x) <- G(x) U_mu(x) G(x+mu)^dag in place on double links, G taken from
-// the float accumulated transform, promoted to double and re-orthonormalised
-// (the same computation at x and at every x - mu, so neighbours agree). The
-// double G is also stored (rows 1-2) in Aout, where accumulation continues.
-template <int NE>
-__global__ void __launch_bounds__(kSiteThreads) k_apply_accumulated(Links<double, NE> L,
-                                                                    const cx<float>* __restrict__ A, size_t aps,
-                                                                    cx<double>* __restrict__ Aout, size_t ops,
-                                                                    Geom g) {
+// The float transform accumulated by the bulk iterations, promoted to double and re-orthonormalised in
+// double: the double-precision phase continues from the same links, H U0 H(x+mu)^dag, with U0 the
+// untouched input in double.
+__global__ void __launch_bounds__(kSiteThreads) k_promote_h(const cx<float>* __restrict__ A, size_t aps,
+                                                            cx<double>* __restrict__ B, size_t bps, int64_t vol) {
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
-    if (s >= g.vol) return;
-    auto load_g = [&](int64_t site) {
-        su3<double> m;
+    if (s >= vol) return;
+    su3<double> m;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const cx<float> e = A[(size_t)k * aps + site];
-            m.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
-        }
-        reunitarize(m);
-        return m;
-    };
-    int c[4];
-    site_coords(g, s, c);
-    const su3<double> g0 = load_g(s);
-#pragma unroll
-    for (int k = 0; k < 6; ++k) Aout[(size_t)k * ops + s] = g0.e[k / 3][k % 3];
-    constexpr int NR = NE == 9 ? 3 : 2;
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const su3<double> g1 = load_g(site_fwd(g, s, c, mu));
-        const su3<double> u = L.load(mu, s);
-        L.store(mu, s, mul_adj<double, NR>(mul_rows<double, NR>(g0, u), g1));
+    for (int k = 0; k < 6; ++k) {
+        const cx<float> e = A[(size_t)k * aps + s];
+        m.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
     }
+    reunitarize(m);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) B[(size_t)k * bps + s] = m.e[k / 3][k % 3];
 }
 
 // --------------------------------------------------------------------- FFT
@@ -760,17 +747,19 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
 
 // Inverse 2D FFT over (x, y) of all four packed fields of one (z, t) plane,
 // then g(x) = reunitarize(1 + (alpha/2) Delta~(x)) for every site of the
-// plane; rows 1-2 of g go to G (six planes, gps apart).
+// plane and the update of the stored transform, Hout = reunitarize(g Hin)
+// (rows 1-2, six planes gps apart); with Hin null, g itself goes to Hout.
 template <typename T, int EPT>
 __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const cx<T>* __restrict__ Q, size_t zps,
-                                                       cx<T>* __restrict__ G, size_t gps, int nx, int ny, int rs,
-                                                       FftPlan px, FftPlan py, const cx<T>* __restrict__ twgx,
-                                                       const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
-                                                       int force, Batch bt, int exact) {
+                                                       const cx<T>* __restrict__ Hin, cx<T>* __restrict__ Hout,
+                                                       size_t gps, int nx, int ny, int rs, FftPlan px, FftPlan py,
+                                                       const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
+                                                       const Ctl* __restrict__ ctl, int force, Batch bt, int exact) {
     {
         const size_t bo = boff(bt);
         Q = bshift(Q, bo);
-        G = bshift(G, bo);
+        Hin = bshift(Hin, bo);
+        Hout = bshift(Hout, bo);
         twgx = bshift(twgx, bo);
         twgy = bshift(twgy, bo);
         ctl = bshift(ctl, bo);
@@ -797,9 +786,15 @@ __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const c
     for (int r = threadIdx.x; r < P; r += nthr) {
         const int row = r / nx, x = r - row * nx;
         const int li = row * rs + x;
-        const su3<T> g = g_from_packed(buf[li], buf[pl + li], buf[2 * pl + li], buf[3 * pl + li], exact != 0);
+        su3<T> g = g_from_packed(buf[li], buf[pl + li], buf[2 * pl + li], buf[3 * pl + li], exact != 0);
+        if (Hin != nullptr) {
+            su3<T> h;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) G[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
+            for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = Hin[(size_t)k * gps + base + r];
+            g = gauge_times(g, h);
+        }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Hout[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
     }
 }
 

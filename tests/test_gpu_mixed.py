@@ -91,12 +91,15 @@ def test_accumulated_gauge_matches_oracle(precision):
     assert np.max(np.abs(g - info["gauge"])) < (1e-11 if fp64 else 1e-4)
 
 
-def test_gauge_not_kept_without_flag():
+def test_gauge_kept_without_flag():
+    """Every context stores the accumulated transform (the links are kept as G U_input G(x+mu)^dag), so
+    gf_get_gauge works without GF_FLAG_ACCUMULATE_GAUGE and maps the input onto the result."""
     u = synth.make_config((4, 4, 4, 4), 4)
-    fx = gf.GaugeFixer(to_dev(u), "fp64_18")
-    with pytest.raises(gf.GfError) as e:
-        fx.get_gauge()
-    assert e.value.status == gf.GF_ESTATE
+    links = to_dev(u)
+    fx = gf.GaugeFixer(links, "fp64_18")
+    fx.iterate(7)
+    g = fx.get_gauge().cpu().numpy()
+    assert np.max(np.abs(landau.apply_gauge(u, g) - links.cpu().numpy())) < 1e-12
 
 
 def test_mixed_48x48x48x8_full_size():
