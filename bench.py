@@ -120,28 +120,32 @@ TILINGS = {}  # precision -> ((x, y) planes per block, (z, t) columns per block,
 
 def timed_rate(gf, torch, u_dev, precision, steps, warmup, with_events, only=None, full_call=False):
     """Time `steps` FA iterations after `warmup`: one gf_advance(steps) call, bracketed by device
-    synchronisations (the links stay in the context's working layout, no egress inside the region).
-    with_events brackets the kernels named in `only` (all kernels if None) with HIP events on the
-    context's stream. Returns (seconds, result, kernel times, blocks, egress seconds, full-call seconds):
-    the egress (links written back to the canonical tensor, once per call) is timed on its own, and with
-    full_call a gf_iterate(steps) call (iterations + egress, what a caller of gf_iterate sees) as well."""
+    synchronisations (the links stay in the context's working layout, no egress inside the region), with
+    no per-kernel events inside it (on this runtime an event pair around a kernel adds about 20 us to the
+    step, so the timed region carries none). with_events then runs the same `steps` again on the same
+    context with HIP events around the kernels named in `only` (all kernels if None), on the context's
+    stream, for the per-kernel durations. Returns (seconds, result, kernel times, blocks, egress seconds,
+    full-call seconds): the egress (links written back to the canonical tensor, once per call) is timed on
+    its own, and with full_call a gf_iterate(steps) call (iterations + egress, what a caller of gf_iterate
+    sees) as well."""
     links = u_dev.clone()
     fx = gf.GaugeFixer(links, precision, check_every=max(steps, warmup, 1))
     TILINGS[precision] = tuple(gf.gf_fft_tiling(fx.ctx)) + (fx.loop_traversal(),)
     if warmup:
         fx.advance(warmup)
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = fx.advance(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ktimes = None
     if with_events:
         if only is None:
             gf.gf_set_timing(fx.ctx, True)
         else:
             gf.gf_set_timing_mask(fx.ctx, only)
-    t0 = time.perf_counter()
-    res = fx.advance(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ktimes = gf.gf_kernel_times(fx.ctx) if with_events else None
-    if with_events:
+        fx.advance(steps)
+        ktimes = gf.gf_kernel_times(fx.ctx)
         gf.gf_set_timing(fx.ctx, False)
     t0 = time.perf_counter()
     fx.sync_links()
@@ -283,12 +287,16 @@ def learned_workload(gf, torch, synth):
     """Train the spectral-preconditioner network on 16^4 plain-FA trajectories (on the GPU, with the
     library's kernels), then compare iterations and wall time to theta < 1e-15 against plain FA."""
     from paper_1208_1186_amd import learn
-    log("learned preconditioner: recording 64 16^4 trajectories and training")
+    log(f"learned preconditioner: recording {learn.TRAIN_TRAJECTORIES} 16^4 trajectories and training")
     params, info = learn.train_default()
     out = {"train": info, "eval": []}
     tot = {"plain_iters": 0, "learned_iters": 0, "plain_s": 0.0, "learned_s": 0.0}
     for dims, seeds, eps in [((32, 32, 32, 32), range(10000, 10004), synth.EPS_P059),
                              ((48, 48, 48, 8), range(20000, 20004), synth.EPS_P060)]:
+        # one untimed solve of each kind first: the first context of a shape in a process autotunes
+        u = synth.make_config(dims, seeds[0], eps)
+        learn.solve(u)
+        learn.solve(u, params=params)
         for seed in seeds:
             u = synth.make_config(dims, seed, eps)
             r0, t_0, _ = learn.solve(u)
@@ -552,7 +560,7 @@ def main():
     prec = args.precision
     L, S = STORAGE[prec]
     log(f"timing {prec}: warmup {args.warmup}, steps {args.steps}")
-    # the timed region: events around the loop kernel only (its duration gives the roofline)
+    # the timed region (no events), then the same steps with events around the loop kernel (the roofline)
     dt, res, ktimes_dom, nblk, egress_s, full_s = timed_rate(gf, torch, u_dev, prec, args.steps, args.warmup,
                                                              with_events=True, only=["update_measure"],
                                                              full_call=True)
@@ -694,7 +702,9 @@ def main():
                                f"seed 0, plaquette~0.59, Haar gauge transform, alpha 0.08",
                    "lattice": list(dims), "storage": prec, "alpha": 0.08},
         "timing": "value = steps / wall time of one gf_advance(steps) call between device synchronisations "
-                  "(steps FA iterations, one theta/F read-back, links left in the working layout); "
+                  "(steps FA iterations, one theta/F read-back, links left in the working layout, no per-kernel "
+                  "events); roofline.avg_launch_ms from HIP events around the loop kernel on the context's stream "
+                  "over the same number of steps run right after on the same context; "
                   "egress_ms = writing the links back to the canonical tensor (once per call); "
                   "full_call_it_per_s = steps / (gf_iterate(steps): the iterations plus that egress)",
         "egress_ms": round(1e3 * egress_s, 4),

@@ -35,39 +35,47 @@ PROBE_SCALE = 0.7  # the recorder's probe step scales every multiplier by this
 
 
 def collect(dims, seeds, n_iter, eps=synth.EPS_P059, precision="fp64_18", alpha=0.08, device="cuda:0",
-            every=1, theta_min=1e-13, probe_scale=PROBE_SCALE, log=None):
+            every=1, theta_min=1e-13, probe_scale=PROBE_SCALE, log=None, chunk=32):
     """Record plain-FA trajectories of the given seeds; returns (X, TGT, n_samples) as CUDA tensors.
 
     A sample pairs iteration r with r + 1; iterations are kept while theta_r > theta_min (below, the
-    spectra are rounding noise), every `every`-th one.
+    spectra are rounding noise), every `every`-th one. The inputs are generated on the host `chunk` seeds
+    at a time (worker processes), so that host memory holds one chunk of configurations.
     """
     import torch
     T = n_tuples(dims)
     xs, ts = [], []
     seeds = list(seeds)
-    configs = synth.make_configs([dims] * len(seeds), seeds, eps)  # host worker processes
-    for seed, u in zip(seeds, configs):
-        links = torch.from_numpy(u).to(device)
-        fx = gf.GaugeFixer(links, precision, alpha=alpha, flags=gf.FLAG_RECORD_SPECTRA)
-        rec, theta = fx.record(n_iter, probe_scale)
-        fx.close()
-        live = int(np.argmax(theta <= theta_min)) if np.any(theta <= theta_min) else n_iter
-        last = min(live, n_iter - 1) - 1  # the last usable record has a successor
-        if last < 0:
-            continue
-        n = last // every + 1
-        th = torch.as_tensor(theta, dtype=torch.float64, device=device)
-        X = torch.empty((n * T, 6), dtype=torch.float32, device=device)
-        TG = torch.empty((n * T, 3), dtype=torch.float32, device=device)
-        gf.gf_mlp_make_samples(rec.data_ptr(), n_iter, th.data_ptr(), 0, every, n, 0, probe_scale, dims,
-                               X.data_ptr(), TG.data_ptr(), torch.cuda.current_stream().cuda_stream)
-        torch.cuda.current_stream().synchronize()
-        xs.append(X)
-        ts.append(TG)
+    for c0 in range(0, len(seeds), chunk):
+        part = seeds[c0:c0 + chunk]
+        configs = synth.make_configs([dims] * len(part), part, eps)  # host worker processes
+        for seed, u in zip(part, configs):
+            links = torch.from_numpy(u).to(device)
+            fx = gf.GaugeFixer(links, precision, alpha=alpha, flags=gf.FLAG_RECORD_SPECTRA)
+            rec, theta = fx.record(n_iter, probe_scale)
+            fx.close()
+            del links
+            live = int(np.argmax(theta <= theta_min)) if np.any(theta <= theta_min) else n_iter
+            last = min(live, n_iter - 1) - 1  # the last usable record has a successor
+            if last < 0:
+                continue
+            n = last // every + 1
+            th = torch.as_tensor(theta, dtype=torch.float64, device=device)
+            X = torch.empty((n * T, 6), dtype=torch.float32, device=device)
+            TG = torch.empty((n * T, 3), dtype=torch.float32, device=device)
+            gf.gf_mlp_make_samples(rec.data_ptr(), n_iter, th.data_ptr(), 0, every, n, 0, probe_scale, dims,
+                                   X.data_ptr(), TG.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            torch.cuda.current_stream().synchronize()
+            del rec
+            xs.append(X)
+            ts.append(TG)
+        del configs
         if log:
-            log(f"recorded seed {seed}: {n} samples")
+            log(f"recorded seeds {part[0]}..{part[-1]}")
     X = torch.cat(xs)
+    del xs
     TG = torch.cat(ts)
+    del ts
     return X, TG, X.shape[0] // T
 
 
@@ -104,10 +112,15 @@ def train(X, TG, T, n_samples, epochs=20, batch=16, lr=2e-3, seed=0, params=None
     return p, hist
 
 
-def train_default(dims=(16, 16, 16, 16), n_train=64, n_iter=60, epochs=60, batch=32, lr=1e-3, seed=0,
-                  first_seed=100, log=None):
-    """The training recipe used for the learned workload: record n_train plain-FA trajectories of
-    seeded dims lattices (seeds first_seed..), then Adam over whole samples. Returns (params, info)."""
+TRAIN_TRAJECTORIES = 500  # plain-FA trajectories of seeded 16^4 lattices, seeds 1..500
+TRAIN_EPOCHS = 20
+
+
+def train_default(dims=(16, 16, 16, 16), n_train=TRAIN_TRAJECTORIES, n_iter=60, epochs=TRAIN_EPOCHS, batch=32,
+                  lr=1e-3, seed=0, first_seed=1, log=None):
+    """The training recipe of the learned workload: record n_train plain-FA trajectories of seeded dims
+    lattices (seeds first_seed.., every update while theta > 1e-13), then Adam over whole samples.
+    Returns (params, info)."""
     t0 = time.perf_counter()
     X, TG, ns = collect(dims, range(first_seed, first_seed + n_train), n_iter, log=log)
     t_rec = time.perf_counter() - t0
@@ -115,9 +128,10 @@ def train_default(dims=(16, 16, 16, 16), n_train=64, n_iter=60, epochs=60, batch
     params, hist = train(X, TG, n_tuples(dims), ns, epochs=epochs, batch=batch, lr=lr, seed=seed, log=log)
     import torch
     torch.cuda.synchronize()
-    info = {"lattice": list(dims), "trajectories": n_train, "samples": int(ns), "record_s": round(t_rec, 2),
-            "train_s": round(time.perf_counter() - t0, 2), "epochs": epochs,
-            "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}
+    info = {"lattice": list(dims), "trajectories": n_train, "seeds": [first_seed, first_seed + n_train - 1],
+            "samples": int(ns), "record_s": round(t_rec, 2), "train_s": round(time.perf_counter() - t0, 2),
+            "epochs": epochs, "loss_first_last": [round(hist[0], 4), round(hist[-1], 4)]}
+    del X, TG
     return params, info
 
 

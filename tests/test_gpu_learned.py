@@ -206,12 +206,22 @@ def test_fallback_rescues_corrupted_weights():
     assert landau.theta(links.cpu().numpy()) < 1e-15
 
 
-def test_trained_network_gains_over_plain_fa():
-    """Train the network on the GPU (library kernels) on recorded 16^4 trajectories, then solve held-out
-    16^4 configurations with and without it: fewer iterations in total, theta < 1e-15 by the oracle."""
+@pytest.fixture(scope="module")
+def trained():
+    """The learned workload's recipe: 500 plain-FA trajectories of 16^4 lattices (seeds 1..500) recorded and
+    trained on with the library's kernels."""
+    print("training on 500 16^4 trajectories", flush=True)
+    params, info = learn.train_default((16, 16, 16, 16), log=lambda m: print(m, flush=True))
+    print(info, flush=True)
+    return params, info
+
+
+def test_trained_network_gains_over_plain_fa(trained):
+    """Held-out 16^4 configurations solved with and without the trained network: fewer iterations in
+    total, theta < 1e-15 by the oracle."""
+    params, info = trained
+    assert info["trajectories"] == 500 and info["loss_first_last"][1] < info["loss_first_last"][0]
     dims = (16, 16, 16, 16)
-    params, info = learn.train_default(dims)  # 64 trajectories, the learned workload's recipe
-    assert info["loss_first_last"][1] < info["loss_first_last"][0]
     plain, learned = 0, 0
     for seed in (800, 801, 802):
         u = synth.make_config(dims, seed)
@@ -223,3 +233,20 @@ def test_trained_network_gains_over_plain_fa():
         learned += r1.iters
     print(f"plain {plain} learned {learned} iterations", flush=True)
     assert learned < plain
+
+
+@pytest.mark.parametrize("dims,seed,eps", [((32, 32, 32, 32), 10000, synth.EPS_P059),
+                                           ((48, 48, 48, 8), 20000, synth.EPS_P060)])
+def test_trained_network_converges_on_evaluation_lattices(trained, dims, seed, eps):
+    """The evaluation lattices of the learned workload (larger than the 16^4 training lattices): the learned
+    solve (with its plain-FA fallback) reaches theta < 1e-15 by the oracle and keeps the plaquette."""
+    from oracle import observables
+    params, _ = trained
+    u = synth.make_config(dims, seed, eps)
+    r0, _, _ = learn.solve(u)
+    r1, _, links = learn.solve(u, params=params)
+    out = links.cpu().numpy()
+    print(f"{dims}: plain {r0.iters}, learned {r1.iters} iterations, {r1.fallbacks} fallbacks", flush=True)
+    assert r1.status == gf.GF_OK and r1.theta < 1e-15
+    assert landau.theta(out) < 1e-15
+    assert abs(observables.plaquette(out) - observables.plaquette(u)) < 1e-12
