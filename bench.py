@@ -239,11 +239,11 @@ def batch_workload(gf, torch, synth, dev, n=64, tol=1e-15):
            "shapes": {f"{d[0]}x{d[1]}x{d[2]}x{d[3]}": shapes.count(d) for d in sorted(set(shapes))},
            "precision": "mixed (float 12-real bulk to theta<1e-8, double 18-real polish)", "tol": tol}
 
-    def run_batched():
+    def run_batched(flags=0):
         links = [b.clone() for b in base]
         torch.cuda.synchronize()
         t = time.perf_counter()
-        bf = gf.BatchFixer(links, "mixed", check_every=10)
+        bf = gf.BatchFixer(links, "mixed", check_every=10, flags=flags)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t
         st, res = bf.fix_until(tol, 100000)
@@ -277,9 +277,20 @@ def batch_workload(gf, torch, synth, dev, n=64, tol=1e-15):
                          "site_iterations_per_s": round(sum(v * r.iters for v, r in zip(vols, res_s)) / dt_s, 1),
                          "max_theta": max(r.theta for r in res_s)}
     out["batched_speedup"] = round(dt_s / dt_b, 3)
+    # every pass one launch over all active configurations of all shapes (runtime-shaped FFT bodies)
+    dt_f, st_f, res_f, init_f = min((run_batched(gf.FLAG_BATCH_FUSED) for _ in range(2)), key=lambda x: x[0])
+    site_iters_f = sum(v * r.iters for v, r in zip(vols, res_f))
+    nshape = len(set(shapes))
+    out["fused"] = {"wall_s_to_all_theta": round(dt_f, 4), "of_which_set_up_s": round(init_f, 4),
+                    "status": int(st_f), "site_iterations_per_s": round(site_iters_f / dt_f, 1),
+                    "iters_min_max": [min(r.iters for r in res_f), max(r.iters for r in res_f)],
+                    "max_theta": max(r.theta for r in res_f),
+                    "launches_per_iteration": 4, "launches_per_iteration_shape_groups": 4 * nshape,
+                    "speedup_over_shape_groups": round(dt_b / dt_f, 3)}
     out["same_results_as_one_by_one"] = all(a.iters == b.iters and a.theta == b.theta and a.F == b.F
                                             for a, b in zip(res_b, res_s))
-    log(f"batch: {dt_b:.3f}s batched vs {dt_s:.3f}s one by one, {site_iters / dt_b / 1e6:.1f} M site-it/s")
+    log(f"batch: {dt_b:.3f}s batched vs {dt_s:.3f}s one by one, {site_iters / dt_b / 1e6:.1f} M site-it/s; "
+        f"fused {dt_f:.3f}s")
     return out
 
 

@@ -73,7 +73,11 @@ enum {
     GF_FLAG_ACCUMULATE_GAUGE = 1u << 3, /* accepted and ignored: the accumulated transform G(x) with
                                            U = G U_input G(x+mu)^dag is what every context stores (gf_get_gauge) */
     GF_FLAG_LEARNED = 1u << 4,          /* reserve the learned preconditioner (gf_mlp_set_weights) */
-    GF_FLAG_RECORD_SPECTRA = 1u << 5    /* reserve spectrum recording (gf_record_spectra) */
+    GF_FLAG_RECORD_SPECTRA = 1u << 5,   /* reserve spectrum recording (gf_record_spectra) */
+    GF_FLAG_BATCH_FUSED = 1u << 6       /* batches: every pass of an iteration is one launch over all active
+                                           configurations of every shape (runtime-shaped FFT kernels, the plain
+                                           loop sweep); single contexts: the same kernels, so that a single
+                                           solve and a fused batch give the same bits */
 };
 
 typedef struct {
@@ -155,6 +159,14 @@ gf_status gf_fix_until_noalloc(const gf_params* params, void* d_links, void* str
  * and flags equal; GF_FLAG_LEARNED and GF_FLAG_RECORD_SPECTRA not allowed).
  * GF_MIXED configurations iterate in float until theta < switch_theta (or the
  * float descent stalls) and finish in double precision, as in gf_init.
+ * Without GF_FLAG_BATCH_FUSED each shape group runs its own launches (the
+ * compile-time FFT kernels of its shape) on a stream of its own; with it, all
+ * shapes advance together on the caller's stream and each pass of an
+ * iteration is one launch over every active configuration (at most 8 shapes,
+ * x-y planes of at most 2048 sites; GF_ENOTSUP otherwise), the phases of
+ * GF_MIXED in step. The fused passes run the runtime-shaped FFT bodies: a
+ * configuration ends bitwise equal to a single context created with the same
+ * flags (GF_FLAG_BATCH_FUSED on a single context selects those bodies too).
  */
 
 /* Bytes of device workspace gf_init_batch needs (0 if the parameters are invalid). */

@@ -27,6 +27,7 @@
 #include "../../include/gf.h"
 #include "gf_fft_ct.hpp"
 #include "gf_fft_reg.hpp"
+#include "gf_batch.hpp"
 #include "gf_kernels.hpp"
 
 using namespace gf;
@@ -441,7 +442,7 @@ const cx<T>* twp(gf_ctx* c, int d) {
     X(48, 8, 16) X(32, 32, 4) X(32, 32, 8) X(32, 64, 4)
 #define GF_GAUGE_CASES(X) X(8, 8) X(12, 12) X(16, 16) X(24, 24) X(32, 32) X(48, 48)
 
-bool generic_fft(const gf_ctx* c) { return (c->p.flags & GF_FLAG_GENERIC_FFT) != 0; }
+bool generic_fft(const gf_ctx* c) { return (c->p.flags & (GF_FLAG_GENERIC_FFT | GF_FLAG_BATCH_FUSED)) != 0; }
 
 template <typename T, bool INV>
 bool launch_xy_ct(gf_ctx* c, const void* src, void* dst, int force, bool loop_reduce) {
@@ -1334,9 +1335,18 @@ struct BatchState {
     gf_params p{};
     size_t total = 0;
     std::vector<BatchGroup> g;
+    // GF_FLAG_BATCH_FUSED: one launch per pass over every active configuration
+    bool fused = false;
+    size_t off_grp[2] = {0, 0}, off_seg = 0;  // workspace: shape tables per phase, segment table
+    void* d_grp[2] = {nullptr, nullptr};
+    int* d_seg = nullptr;  // first[4][n + 1], group[n], cfg[n]
+    int* h_seg = nullptr;  // pinned staging of the segment table
+    int thr[3] = {64, 64, 64};   // block sizes of the (x, y), (z, t) and gauge passes (largest shape)
+    size_t lds[3] = {0, 0, 0};
 };
 
 void free_batch(BatchState* b) {
+    if (b->h_seg) (void)hipHostFree(b->h_seg);
     for (auto& g : b->g) {
         for (int p = 0; p < 2; ++p) {
             for (gf_ctx* v : g.view[p]) free_ctx(v);
@@ -1406,7 +1416,117 @@ gf_status plan_batch(int32_t n, const gf_params* params, BatchState& b, std::str
         g.off_heads = o;
         o = align_up(o + (size_t)ng * kHeadBytes, kAlign);
     }
+    b.fused = (p0.flags & GF_FLAG_BATCH_FUSED) != 0;
+    if (b.fused) {
+        if ((int)b.g.size() > kMaxFusedGroups) {
+            err = "GF_FLAG_BATCH_FUSED takes at most 8 lattice shapes";
+            return GF_ENOTSUP;
+        }
+        for (auto& g : b.g)
+            for (int ph = 0; ph < g.nphase; ++ph)
+                if (g.L[ph].eptC != kEPT) {
+                    err = "GF_FLAG_BATCH_FUSED: x-y planes too large for the fused inverse (x, y) pass";
+                    return GF_ENOTSUP;
+                }
+        for (int ph = 0; ph < 2; ++ph) {
+            b.off_grp[ph] = o;
+            o = align_up(o + kMaxFusedGroups * sizeof(FusedGroup<double>), kAlign);
+        }
+        b.off_seg = o;
+        o = align_up(o + (size_t)(4 * (n + 1) + 2 * n) * sizeof(int), kAlign);
+    }
     b.total = o;
+    return GF_OK;
+}
+
+// The per-shape tables of the fused passes (configuration 0 of each shape; the drivers' carved buffers).
+template <typename T>
+FusedGroup<T> fused_group(const BatchGroup& g, int ph) {
+    const gf_ctx* d = g.drv[ph];
+    const Layout& L = d->L;
+    FusedGroup<T> f{};
+    f.cs = g.cs[ph];
+    f.ctl = d->ctl;
+    f.part = d->part;
+    f.U0 = reinterpret_cast<const cx<T>*>(d->U0);
+    f.D = reinterpret_cast<cx<T>*>(d->D);
+    f.Q = reinterpret_cast<cx<T>*>(d->Q);
+    for (int i = 0; i < 2; ++i) f.H[i] = reinterpret_cast<cx<T>*>(d->Hb[i]);
+    f.sin2 = reinterpret_cast<const T*>(d->sin2);
+    for (int i = 0; i < 4; ++i) f.tw[i] = reinterpret_cast<const cx<T>*>(d->tw[i]);
+    f.ps = L.ps;
+    f.geom = d->geom;
+    for (int i = 0; i < 4; ++i) f.plan[i] = d->plan[i];
+    f.G = L.G;
+    f.rs = L.rs;
+    f.bx = L.bx;
+    f.tsp = L.tsp;
+    f.npart = L.nblk_fused;
+    const bool no_fa = (d->p.flags & GF_FLAG_NO_FA) != 0;
+    f.coef = 0.5 * d->p.alpha * (no_fa ? 1.0 : 16.0) / (double)L.vol;
+    f.inv3v = 1.0 / (3.0 * (double)L.vol);
+    f.inv12v = 1.0 / (12.0 * (double)L.vol);
+    f.blocks[0] = 4 * L.n[2] * L.n[3] / L.G;
+    f.blocks[1] = 4 * L.n[1] * (L.n[0] / L.bx);
+    f.blocks[2] = L.n[2] * L.n[3];
+    f.blocks[3] = L.nblk_fused;
+    return f;
+}
+
+void raise_lds_fused() {
+    static bool done = false;
+    if (done) return;
+    const int cap = (int)kLdsMax;
+    const void* fns[] = {
+        reinterpret_cast<const void*>(&k_fused_xy<double, kEPT>),
+        reinterpret_cast<const void*>(&k_fused_zt<double, kEPT>),
+        reinterpret_cast<const void*>(&k_fused_gauge<double, kEPT, 512>),
+        reinterpret_cast<const void*>(&k_fused_gauge<double, kEPT, 1024>),
+        reinterpret_cast<const void*>(&k_fused_xy<float, kEPT>),
+        reinterpret_cast<const void*>(&k_fused_zt<float, kEPT>),
+        reinterpret_cast<const void*>(&k_fused_gauge<float, kEPT, 512>),
+        reinterpret_cast<const void*>(&k_fused_gauge<float, kEPT, 1024>),
+    };
+    for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
+    (void)hipGetLastError();
+    done = true;
+}
+
+gf_status init_fused(gf_ctx* c, BatchState& b, unsigned char* ws) {
+    raise_lds_fused();
+    b.d_seg = reinterpret_cast<int*>(ws + b.off_seg);
+    if (hipHostMalloc(reinterpret_cast<void**>(&b.h_seg), (size_t)(4 * (b.n + 1) + 2 * b.n) * sizeof(int)) !=
+        hipSuccess) {
+        b.h_seg = nullptr;
+        return fail(c, GF_EDEVICE, "hipHostMalloc of the fused segment table failed");
+    }
+    for (auto& g : b.g)
+        for (int ph = 0; ph < g.nphase; ++ph) {
+            const Layout& L = g.drv[ph]->L;  // the tilings tuned for the shape
+            b.thr[0] = std::max(b.thr[0], L.thrA);
+            b.thr[1] = std::max(b.thr[1], L.thrB);
+            b.thr[2] = std::max(b.thr[2], L.thrC);
+            b.lds[0] = std::max(b.lds[0], L.ldsA);
+            b.lds[1] = std::max(b.lds[1], L.ldsB);
+            b.lds[2] = std::max(b.lds[2], L.ldsC);
+        }
+    const int nph = b.g.empty() ? 1 : b.g[0].nphase;
+    for (int ph = 0; ph < nph; ++ph) {
+        b.d_grp[ph] = ws + b.off_grp[ph];
+        const bool fp32 = b.g[0].L[ph].fp32;
+        std::vector<unsigned char> host(kMaxFusedGroups * sizeof(FusedGroup<double>), 0);
+        for (size_t i = 0; i < b.g.size(); ++i) {
+            if (fp32) {
+                const FusedGroup<float> f = fused_group<float>(b.g[i], ph);
+                std::memcpy(host.data() + i * sizeof(f), &f, sizeof(f));
+            } else {
+                const FusedGroup<double> f = fused_group<double>(b.g[i], ph);
+                std::memcpy(host.data() + i * sizeof(f), &f, sizeof(f));
+            }
+        }
+        GF_TRY_HIP(c, hipMemcpyAsync(b.d_grp[ph], host.data(), host.size(), hipMemcpyHostToDevice, c->st));
+        GF_TRY_HIP(c, hipStreamSynchronize(c->st));  // host goes away
+    }
     return GF_OK;
 }
 
@@ -1459,6 +1579,7 @@ gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned 
         }
         GF_TRY_HIP(c, hipStreamSynchronize(st));  // reports a failed upload (drain repeats it harmlessly)
     }
+    if (b.fused) return init_fused(c, b, ws);
     return GF_OK;
 }
 
@@ -1612,6 +1733,187 @@ gf_status absorb_group(gf_ctx* c, BatchGroup& g, std::vector<BatchOutcome>& out)
     g.act.swap(next);
     if (g.act.empty() || g.left <= 0) g.stage = BatchGroup::kEnd;
     return GF_OK;
+}
+
+// ---------------------------------------------------------------- fused batches
+// Read every configuration's control block of phase ph into its view (one gather per shape, one wait).
+gf_status fused_gather(gf_ctx* c, BatchState& b, int ph) {
+    for (auto& g : b.g) {
+        const int ng = (int)g.idx.size();
+        hipLaunchKernelGGL(k_gather_heads, dim3(ng), dim3(64), 0, c->st,
+                           reinterpret_cast<const unsigned char*>(g.view[ph][0]->ctl), g.cs[ph],
+                           (int)(kHeadBytes / 8), reinterpret_cast<unsigned long long*>(g.d_heads));
+        gf_status s = launched(c, "gather launch");
+        if (s != GF_OK) return s;
+        GF_TRY_HIP(c, hipMemcpyAsync(g.h_heads, g.d_heads, ng * kHeadBytes, hipMemcpyDeviceToHost, c->st));
+    }
+    GF_TRY_HIP(c, hipStreamSynchronize(c->st));
+    for (auto& g : b.g)
+        for (size_t i = 0; i < g.idx.size(); ++i) {
+            gf_ctx* v = g.view[ph][i];
+            std::memcpy(v->h_head, g.h_heads + i * kHeadBytes, kHeadBytes);
+            v->k_host = v->h_head->iters;
+        }
+    return GF_OK;
+}
+
+// The segment table of the active configurations act = [(group, slot)] -> device (staged in pinned memory).
+gf_status fused_table(gf_ctx* c, BatchState& b, int ph, const std::vector<std::pair<int, int>>& act, FusedTable& tb,
+                      int total[4]) {
+    const int n = (int)act.size();
+    int* first[4];
+    for (int p = 0; p < 4; ++p) first[p] = b.h_seg + p * (b.n + 1);
+    int* grp = b.h_seg + 4 * (b.n + 1);
+    int* cfg = grp + b.n;
+    for (int p = 0; p < 4; ++p) first[p][0] = 0;
+    for (int j = 0; j < n; ++j) {
+        const BatchGroup& g = b.g[act[j].first];
+        const Layout& L = g.drv[ph]->L;
+        const int blocks[4] = {4 * L.n[2] * L.n[3] / L.G, 4 * L.n[1] * (L.n[0] / L.bx), L.n[2] * L.n[3],
+                               L.nblk_fused};
+        for (int p = 0; p < 4; ++p) first[p][j + 1] = first[p][j] + blocks[p];
+        grp[j] = act[j].first;
+        cfg[j] = act[j].second;
+    }
+    for (int p = 0; p < 4; ++p) total[p] = first[p][n];
+    // the whole table in one copy (the previous chunk's kernels have finished: the host waited for them)
+    GF_TRY_HIP(c, hipMemcpyAsync(b.d_seg, b.h_seg, (size_t)(4 * (b.n + 1) + 2 * b.n) * sizeof(int),
+                                 hipMemcpyHostToDevice, c->st));
+    for (int p = 0; p < 4; ++p) tb.first[p] = b.d_seg + p * (b.n + 1);
+    tb.group = b.d_seg + 4 * (b.n + 1);
+    tb.cfg = tb.group + b.n;
+    tb.nseg = n;
+    return GF_OK;
+}
+
+// One iteration k -> k + 1 of every active configuration: four launches.
+template <typename T, int NE>
+void fused_iteration_t(gf_ctx* c, BatchState& b, int ph, const FusedTable& tb, const int total[4], long long k) {
+    const FusedGroup<T>* grp = reinterpret_cast<const FusedGroup<T>*>(b.d_grp[ph]);
+    const int hp = (int)(k & 1);
+    hipLaunchKernelGGL((k_fused_xy<T, kEPT>), dim3(total[0]), dim3(b.thr[0]), b.lds[0], c->st, grp, tb);
+    hipLaunchKernelGGL((k_fused_zt<T, kEPT>), dim3(total[1]), dim3(b.thr[1]), b.lds[1], c->st, grp, tb,
+                       (b.p.flags & GF_FLAG_NO_FA) ? 1 : 0);
+    const int exact = (b.p.flags & GF_FLAG_EXACT_EXP) ? 1 : 0;
+    if (b.thr[2] <= 512)
+        hipLaunchKernelGGL((k_fused_gauge<T, kEPT, 512>), dim3(total[2]), dim3(b.thr[2]), b.lds[2], c->st, grp, tb,
+                           hp, exact);
+    else
+        hipLaunchKernelGGL((k_fused_gauge<T, kEPT, 1024>), dim3(total[2]), dim3(b.thr[2]), b.lds[2], c->st, grp, tb,
+                           hp, exact);
+    hipLaunchKernelGGL((k_fused_loop<T, NE>), dim3(total[3]), dim3(kFusedThreads), 0, c->st, grp, tb, 1 - hp);
+}
+
+template <typename T>
+void fused_finalize_t(gf_ctx* c, BatchState& b, int ph, const FusedTable& tb) {
+    hipLaunchKernelGGL(k_fused_finalize<T>, dim3(tb.nseg), dim3(256), 0, c->st,
+                       reinterpret_cast<const FusedGroup<T>*>(b.d_grp[ph]), tb);
+}
+
+// Every configuration to completion with one launch per pass: the phases of GF_MIXED advance in step
+// (float until every configuration has reached switch_theta or stalled, then the hand-over, then double).
+gf_status run_batch_fused(gf_ctx* c, BatchState& b, double tol, int64_t max_iter, std::vector<BatchOutcome>& out) {
+    const int nph = b.g[0].nphase;
+    const bool mixed = nph == 2;
+    for (auto& g : b.g) {
+        g.it0.assign(g.idx.size(), 0);
+        g.stalled.assign(g.idx.size(), 0);
+    }
+    // everything below runs on the caller's stream, after the groups' set-up
+    for (auto& g : b.g) {
+        GF_TRY_HIP(c, hipEventRecord(g.ev, g.st));
+        GF_TRY_HIP(c, hipStreamWaitEvent(c->st, g.ev, 0));
+        for (int ph = 0; ph < nph; ++ph)
+            for (gf_ctx* v : g.view[ph]) v->st = c->st;
+    }
+    int64_t left = max_iter;
+    gf_status s = GF_OK;
+    for (int ph = 0; ph < nph && s == GF_OK; ++ph) {
+        const double tp = (mixed && ph == 0) ? std::max(c->p.switch_theta, tol) : tol;
+        for (auto& g : b.g) {
+            g.ph = ph;
+            for (size_t i = 0; i < g.idx.size() && s == GF_OK; ++i)
+                if (!out[g.idx[i]].finished) s = set_tol(g.view[ph][i], tp);
+        }
+        if (s == GF_OK) s = fused_gather(c, b, ph);
+        if (s != GF_OK) return s;
+        std::vector<std::pair<int, int>> act;
+        for (size_t gi = 0; gi < b.g.size(); ++gi) {
+            BatchGroup& g = b.g[gi];
+            g.tracker.assign(g.idx.size(), StallTracker{});
+            for (size_t i = 0; i < g.idx.size(); ++i) {
+                const Ctl* h = g.view[ph][i]->h_head;
+                g.tracker[i].best = h->theta;
+                if (!out[g.idx[i]].finished && !h->done) act.emplace_back((int)gi, (int)i);
+            }
+        }
+        long long k = 0;  // every configuration of a phase starts from its own count 0
+        while (!act.empty() && left > 0 && s == GF_OK) {
+            FusedTable tb{};
+            int total[4];
+            s = fused_table(c, b, ph, act, tb, total);
+            if (s != GF_OK) return s;
+            const int64_t n_it = std::min<int64_t>(left, c->p.check_every);
+            for (int64_t j = 0; j < n_it; ++j) {
+                if (b.g[0].L[ph].fp32) {
+                    if (b.g[0].L[ph].ne == 6) fused_iteration_t<float, 6>(c, b, ph, tb, total, k + j);
+                    else fused_iteration_t<float, 9>(c, b, ph, tb, total, k + j);
+                } else {
+                    if (b.g[0].L[ph].ne == 6) fused_iteration_t<double, 6>(c, b, ph, tb, total, k + j);
+                    else fused_iteration_t<double, 9>(c, b, ph, tb, total, k + j);
+                }
+            }
+            if (b.g[0].L[ph].fp32)
+                fused_finalize_t<float>(c, b, ph, tb);
+            else
+                fused_finalize_t<double>(c, b, ph, tb);
+            s = launched(c, "fused launch");
+            if (s == GF_OK) s = fused_gather(c, b, ph);
+            if (s != GF_OK) return s;
+            k += n_it;
+            left -= n_it;
+            std::vector<std::pair<int, int>> next;
+            for (const auto& a : act) {
+                BatchGroup& g = b.g[a.first];
+                const Ctl* h = g.view[ph][a.second]->h_head;
+                if (h->done || h->numeric) continue;
+                if (h->iters != k) return fail(c, GF_EDEVICE, "batch configurations fell out of step");
+                if (mixed && ph == 0) {
+                    g.stalled[a.second] = g.tracker[a.second].step(h->theta, n_it);
+                    if (g.stalled[a.second]) continue;
+                }
+                next.push_back(a);
+            }
+            act.swap(next);
+        }
+        // end of the phase: hand-over to double precision, or the results
+        for (auto& g : b.g) {
+            for (size_t i = 0; i < g.idx.size() && s == GF_OK; ++i) {
+                BatchOutcome& o = out[g.idx[i]];
+                if (o.finished) continue;
+                gf_ctx* v = g.view[ph][i];
+                const Ctl* h = v->h_head;
+                if (mixed && ph == 0) {
+                    g.it0[i] = h->iters;
+                    const bool reached = h->theta < tp;
+                    if (h->numeric || (tol > 0.0 && h->theta < tol) || (!reached && !g.stalled[i])) {
+                        s = finish_config(c, v, 0, 0, o, h->theta < tol);
+                        continue;
+                    }
+                    gf_ctx* w = g.view[1][i];
+                    hipLaunchKernelGGL(k_promote_h, dim3(w->L.nblk), dim3(kSiteThreads), 0, c->st,
+                                       reinterpret_cast<const cx<float>*>(v->Hb[cur(v)]), v->L.ps,
+                                       reinterpret_cast<cx<double>*>(w->Hb[cur(w)]), w->L.ps, w->L.vol);
+                    s = launched(w, "hand-over launch");
+                    if (s == GF_OK) s = launch_measure(w);
+                    if (s != GF_OK) return fail(c, s, w->err);
+                } else {
+                    s = finish_config(c, v, mixed ? 1 : (v->L.fp32 ? 0 : 1), mixed ? g.it0[i] : 0, o, h->done != 0);
+                }
+            }
+        }
+    }
+    return s;
 }
 
 // Every group to completion, side by side: queue each group's next piece of work on its stream,
@@ -1945,7 +2247,7 @@ gf_status gf_fix_until_batch(gf_ctx* c, double tol, int64_t max_iter, gf_result*
         const auto t0 = std::chrono::steady_clock::now();
         BatchState& b = *c->batch;
         std::vector<BatchOutcome> out(b.n);
-        gf_status s = run_batch(c, b, tol, max_iter, out);
+        gf_status s = b.fused ? run_batch_fused(c, b, tol, max_iter, out) : run_batch(c, b, tol, max_iter, out);
         if (s != GF_OK) return s;
         s = check_hip(c, hipStreamSynchronize(c->st), "sync");
         if (s != GF_OK) return s;

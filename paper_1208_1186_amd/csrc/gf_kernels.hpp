@@ -628,21 +628,12 @@ __global__ void __launch_bounds__(kSiteThreads) k_promote_h(const cx<float>* __r
 // along x then y, and writes them out. With part set, block 0 first reduces
 // the loop kernel's pending partials (npart of them) into the control block.
 template <typename T, int EPT, bool INV>
-__global__ void __launch_bounds__(1024) k_fft_xy(const cx<T>* src, cx<T>* dst, size_t zps, int nx, int ny,
-                                                 int nzt, int G, int rs, FftPlan px, FftPlan py,
-                                                 const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
-                                                 Ctl* ctl, int force, const double2* __restrict__ part, int npart,
-                                                 double inv3v, double inv12v, Batch bt) {
-    {
-        const size_t bo = boff(bt);
-        src = bshift(src, bo);
-        dst = bshift(dst, bo);
-        twgx = bshift(twgx, bo);
-        twgy = bshift(twgy, bo);
-        ctl = bshift(ctl, bo);
-        part = bshift(part, bo);
-    }
-    if (part != nullptr && blockIdx.x == 0 && ctl->pending) {
+__device__ __forceinline__ void fft_xy_body(const cx<T>* src, cx<T>* dst, size_t zps, int nx, int ny, int nzt,
+                                            int G, int rs, const FftPlan& px, const FftPlan& py,
+                                            const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
+                                            Ctl* ctl, int force, const double2* __restrict__ part, int npart,
+                                            double inv3v, double inv12v, int blk, bool first) {
+    if (part != nullptr && first && ctl->pending) {
         reduce_partials(part, npart, inv3v, inv12v, ctl, 1);
         __syncthreads();
     }
@@ -654,7 +645,7 @@ __global__ void __launch_bounds__(1024) k_fft_xy(const cx<T>* src, cx<T>* dst, s
     const int nthr = blockDim.x;
     for (int i = threadIdx.x; i < nx; i += nthr) twx[i] = twgx[i];
     for (int i = threadIdx.x; i < ny; i += nthr) twy[i] = twgy[i];
-    const int q0 = xcd_remap(blockIdx.x, gridDim.x) * G;
+    const int q0 = blk * G;
     const int f = q0 / nzt, zt0 = q0 - f * nzt;
     const size_t off = (size_t)f * zps + (size_t)zt0 * nx * ny;
     const cx<T>* gs = src + off;
@@ -673,25 +664,33 @@ __global__ void __launch_bounds__(1024) k_fft_xy(const cx<T>* src, cx<T>* dst, s
     }
 }
 
-// 2D FFT over (z, t) for bx consecutive x columns at one y of one field,
-// multiply every mode by coef / p^2(p) (coef = (alpha/2) p2max / V; zero mode
-// -> 0; coef alone when no_fa), then the inverse (z, t) transform, in place.
-// LDS element (xo, z, t) sits at t*tsp + z*bx + xo.
-template <typename T, int EPT>
-__global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, int nz, int nt,
-                                                 int bx, int tsp, FftPlan pz, FftPlan pt,
-                                                 const cx<T>* __restrict__ twgz, const cx<T>* __restrict__ twgt,
-                                                 const T* __restrict__ sin2, T coef, int no_fa,
-                                                 const Ctl* __restrict__ ctl, int force, const T* __restrict__ mtab,
-                                                 TupleGeom tg, cx<T>* __restrict__ spec, Batch bt) {
+template <typename T, int EPT, bool INV>
+__global__ void __launch_bounds__(1024) k_fft_xy(const cx<T>* src, cx<T>* dst, size_t zps, int nx, int ny,
+                                                 int nzt, int G, int rs, FftPlan px, FftPlan py,
+                                                 const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
+                                                 Ctl* ctl, int force, const double2* __restrict__ part, int npart,
+                                                 double inv3v, double inv12v, Batch bt) {
     {
         const size_t bo = boff(bt);
-        Z = bshift(Z, bo);
-        twgz = bshift(twgz, bo);
-        twgt = bshift(twgt, bo);
-        sin2 = bshift(sin2, bo);
+        src = bshift(src, bo);
+        dst = bshift(dst, bo);
+        twgx = bshift(twgx, bo);
+        twgy = bshift(twgy, bo);
         ctl = bshift(ctl, bo);
+        part = bshift(part, bo);
     }
+    fft_xy_body<T, EPT, INV>(src, dst, zps, nx, ny, nzt, G, rs, px, py, twgx, twgy, ctl, force, part, npart, inv3v,
+                             inv12v, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x == 0);
+}
+
+// 2D FFT over (z, t), filter and inverse (z, t) of block blk's bx columns (the body of k_fft_zt).
+template <typename T, int EPT>
+__device__ __forceinline__ void fft_zt_body(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, int nz, int nt,
+                                            int bx, int tsp, const FftPlan& pz, const FftPlan& pt,
+                                            const cx<T>* __restrict__ twgz, const cx<T>* __restrict__ twgt,
+                                            const T* __restrict__ sin2, T coef, int no_fa,
+                                            const Ctl* __restrict__ ctl, int force, const T* __restrict__ mtab,
+                                            const TupleGeom& tg, cx<T>* __restrict__ spec, int blk) {
     if (!force && ctl->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* twz = reinterpret_cast<cx<T>*>(smem);
@@ -701,7 +700,6 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
     for (int i = threadIdx.x; i < nz; i += nthr) twz[i] = twgz[i];
     for (int i = threadIdx.x; i < nt; i += nthr) twt[i] = twgt[i];
     const int nxb = nx / bx;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int xb = blk % nxb;
     const int rest = blk / nxb;
     const int y = rest % ny, f = rest / ny;
@@ -745,25 +743,40 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
     }
 }
 
+// 2D FFT over (z, t) for bx consecutive x columns at one y of one field,
+// multiply every mode by coef / p^2(p) (coef = (alpha/2) p2max / V; zero mode
+// -> 0; coef alone when no_fa), then the inverse (z, t) transform, in place.
+// LDS element (xo, z, t) sits at t*tsp + z*bx + xo.
+template <typename T, int EPT>
+__global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, int nz, int nt,
+                                                 int bx, int tsp, FftPlan pz, FftPlan pt,
+                                                 const cx<T>* __restrict__ twgz, const cx<T>* __restrict__ twgt,
+                                                 const T* __restrict__ sin2, T coef, int no_fa,
+                                                 const Ctl* __restrict__ ctl, int force, const T* __restrict__ mtab,
+                                                 TupleGeom tg, cx<T>* __restrict__ spec, Batch bt) {
+    {
+        const size_t bo = boff(bt);
+        Z = bshift(Z, bo);
+        twgz = bshift(twgz, bo);
+        twgt = bshift(twgt, bo);
+        sin2 = bshift(sin2, bo);
+        ctl = bshift(ctl, bo);
+    }
+    fft_zt_body<T, EPT>(Z, zps, nx, ny, nz, nt, bx, tsp, pz, pt, twgz, twgt, sin2, coef, no_fa, ctl, force, mtab, tg,
+                        spec, xcd_remap(blockIdx.x, gridDim.x));
+}
+
 // Inverse 2D FFT over (x, y) of all four packed fields of one (z, t) plane,
 // then g(x) = reunitarize(1 + (alpha/2) Delta~(x)) for every site of the
 // plane and the update of the stored transform, Hout = reunitarize(g Hin)
 // (rows 1-2, six planes gps apart); with Hin null, g itself goes to Hout.
 template <typename T, int EPT>
-__global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const cx<T>* __restrict__ Q, size_t zps,
-                                                       const cx<T>* __restrict__ Hin, cx<T>* __restrict__ Hout,
-                                                       size_t gps, int nx, int ny, int rs, FftPlan px, FftPlan py,
-                                                       const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
-                                                       const Ctl* __restrict__ ctl, int force, Batch bt, int exact) {
-    {
-        const size_t bo = boff(bt);
-        Q = bshift(Q, bo);
-        Hin = bshift(Hin, bo);
-        Hout = bshift(Hout, bo);
-        twgx = bshift(twgx, bo);
-        twgy = bshift(twgy, bo);
-        ctl = bshift(ctl, bo);
-    }
+__device__ __forceinline__ void fft_xy_gauge_body(const cx<T>* __restrict__ Q, size_t zps,
+                                                  const cx<T>* __restrict__ Hin, cx<T>* __restrict__ Hout,
+                                                  size_t gps, int nx, int ny, int rs, const FftPlan& px,
+                                                  const FftPlan& py, const cx<T>* __restrict__ twgx,
+                                                  const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
+                                                  int force, int exact, int blk) {
     if (!force && ctl->done) return;
     extern __shared__ __align__(16) unsigned char smem[];
     cx<T>* twx = reinterpret_cast<cx<T>*>(smem);
@@ -774,7 +787,7 @@ __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const c
     for (int i = threadIdx.x; i < ny; i += nthr) twy[i] = twgy[i];
     const int P = nx * ny;
     const int pl = ny * rs;  // LDS elements per field plane
-    const size_t base = (size_t)xcd_remap(blockIdx.x, gridDim.x) * P;
+    const size_t base = (size_t)blk * P;
     for (int e = threadIdx.x; e < 4 * P; e += nthr) {
         const int f = e / P, r = e - f * P;
         const int row = r / nx, x = r - row * nx;
@@ -796,6 +809,25 @@ __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const c
 #pragma unroll
         for (int k = 0; k < 6; ++k) Hout[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
     }
+}
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const cx<T>* __restrict__ Q, size_t zps,
+                                                       const cx<T>* __restrict__ Hin, cx<T>* __restrict__ Hout,
+                                                       size_t gps, int nx, int ny, int rs, FftPlan px, FftPlan py,
+                                                       const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
+                                                       const Ctl* __restrict__ ctl, int force, Batch bt, int exact) {
+    {
+        const size_t bo = boff(bt);
+        Q = bshift(Q, bo);
+        Hin = bshift(Hin, bo);
+        Hout = bshift(Hout, bo);
+        twgx = bshift(twgx, bo);
+        twgy = bshift(twgy, bo);
+        ctl = bshift(ctl, bo);
+    }
+    fft_xy_gauge_body<T, EPT>(Q, zps, Hin, Hout, gps, nx, ny, rs, px, py, twgx, twgy, ctl, force, exact,
+                              xcd_remap(blockIdx.x, gridDim.x));
 }
 
 }  // namespace gf

@@ -27,6 +27,7 @@ FLAG_GENERIC_FFT = 1 << 2
 FLAG_ACCUMULATE_GAUGE = 1 << 3
 FLAG_LEARNED = 1 << 4
 FLAG_RECORD_SPECTRA = 1 << 5
+FLAG_BATCH_FUSED = 1 << 6
 
 
 class gf_params(ctypes.Structure):
@@ -563,6 +564,9 @@ class BatchFixer:
             self.params.append(make_params((nx, ny, nz, nt), precision, alpha, switch_theta, check_every, flags))
         nbytes = gf_batch_workspace_bytes(self.params)
         if nbytes == 0:
+            # the parameters do not plan: gf_init_batch names the reason (and its status) before it
+            # touches any pointer
+            gf_init_batch(self.params, [t.data_ptr() for t in self.links], 0, 0)
             raise GfError(GF_EINVAL, "invalid batch parameters")
         dev = self.links[0].device
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)

@@ -121,6 +121,27 @@ def test_batch_rejects_bad_parameters_before_device(lib):
     assert lib.gf_fix_until_batch(None, 1e-15, 10, None) == gf.GF_EINVAL
 
 
+def test_fused_batch_limits_before_device(lib):
+    """GF_FLAG_BATCH_FUSED: at most eight lattice shapes, x-y planes of at most 2048 sites (GF_ENOTSUP)."""
+    fused = gf.FLAG_BATCH_FUSED
+    shapes = [(4, 4, z, t) for z in (4, 6, 8) for t in (4, 6, 8)]
+    nine = [gf.make_params(d, "mixed", flags=fused) for d in shapes]
+    assert gf.gf_batch_workspace_bytes(nine) == 0
+    st, ctx = _batch_init(lib, nine)
+    assert st == gf.GF_ENOTSUP and not ctx.value and "8" in gf.gf_last_error(None)
+    eight = nine[:8]
+    plain = [gf.make_params(d, "mixed") for d in shapes[:8]]
+    # the shape tables and the segment table come on top of the per-shape workspace
+    assert gf.gf_batch_workspace_bytes(eight) > gf.gf_batch_workspace_bytes(plain) > 0
+    assert gf.gf_batch_workspace_bytes([gf.make_params(d, "mixed") for d in shapes]) > 0
+    for dims in ((48, 48, 4, 4), (48, 48, 8, 6)):
+        big = [gf.make_params(dims, "fp64_18", flags=fused)]
+        assert gf.gf_batch_workspace_bytes(big) == 0
+        assert _batch_init(lib, big)[0] == gf.GF_ENOTSUP
+        assert gf.gf_batch_workspace_bytes([gf.make_params(dims, "fp64_18")]) > 0
+    assert gf.gf_batch_workspace_bytes([gf.make_params((32, 64, 4, 4), "fp64_18", flags=fused)]) > 0
+
+
 def test_state_calls_reject_null_context(lib):
     assert lib.gf_state_bytes(None) == 0
     assert lib.gf_get_state(None, gf._P(256), 1 << 20) == gf.GF_EINVAL
