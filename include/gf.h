@@ -217,11 +217,17 @@ gf_status gf_set_fft_tiling(gf_ctx* ctx, int32_t xy_planes, int32_t zt_columns);
  * of z_group planes inside the t loop, so that t neighbours are still cached.
  * z_group == 0 (t-march): each block owns 64 sites of the (x, y, z) volume and
  * steps through t, keeping its own updated U_t of one step for the divergence
- * of the next, so U_t(x - t) and g(x - t) are not fetched again. gf_init times
- * the traversals that fit the shape (1; 2, 4, 8 where they divide Nz and 64
- * divides Nx*Ny; 0 where 64 divides Nx*Ny*Nz, Nt >= 4 and there are >= 32
- * blocks) on the first context of a shape and precision in the process and
- * keeps the fastest. Partials are summed by site block, so every traversal
+ * of the next, so U_t(x - t) and g(x - t) are not fetched again.
+ * z_group == -1 (brick march): each block owns a brick of whole x rows (by rows
+ * in y, bz planes in z, Nx*by a multiple of 64) and steps through a segment of
+ * t; every link is formed once, by the lane that owns it, and the divergence
+ * takes the back links from LDS (from a halo lane where the back neighbour lies
+ * outside the brick). gf_init times the traversals that fit the shape (1; 2, 4,
+ * 8 where they divide Nz and 64 divides Nx*Ny; 0 where 64 divides Nx*Ny*Nz,
+ * Nt >= 4 and there are >= 32 blocks; -1 where a divisor by of Ny makes Nx*by a
+ * multiple of 64 with 4*Nx*by <= 1024 and the link arrays stay below 4 GiB) on
+ * the first context of a shape and precision in the process and keeps the
+ * fastest. Partials are summed by site block, so every traversal
  * gives bitwise the same results. gf_set_loop_traversal overrides the choice for
  * this context (a test and measurement aid); GF_EINVAL if z_group is not one
  * of the candidates. For GF_MIXED: the active phase.

@@ -84,8 +84,10 @@ struct Layout {
     size_t ps;        // plane stride (elements) of every SoA array
     int nblk;         // blocks of the one-site-per-thread kernels
     int nblk_fused;   // blocks of the loop kernel (kFusedSites sites each)
-    int zb = 1;       // loop-kernel traversal: z planes per group inside the t loop, or 0: blocks step
-                      // through t (autotuned)
+    int zb = 1;       // loop-kernel traversal: z planes per group inside the t loop, 0: blocks step
+                      // through t, -1: bricks step through t segments (autotuned)
+    BrickGeom bk{};   // brick march geometry (bk.by == 0: the shape has none)
+    int bk_threads = 0;
     bool fp32;
     int ne;           // 9 or 6 complex entries stored per link
     // forward / inverse (x, y) pass over single-field planes
@@ -145,6 +147,8 @@ int zt_reg_bx(const Layout& L) {
     return 0;
 }
 
+void plan_brick(Layout& L);
+
 gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     if (!p) {
         err = "params is NULL";
@@ -188,6 +192,7 @@ gf_status plan_plain(const gf_params* p, Layout& L, std::string& err) {
     L.ps = align_up((size_t)vol, 256) + kPlanePad;
     L.nblk = (int)((vol + kSiteThreads - 1) / kSiteThreads);
     L.nblk_fused = (int)((vol + kFusedSites - 1) / kFusedSites);
+    plan_brick(L);
     const int nx = L.n[0], ny = L.n[1], nz = L.n[2], nt = L.n[3];
     // (x, y) pass: G planes per block, enough work per block, never straddling a field.
     const int nzt = nz * nt;
@@ -506,7 +511,7 @@ bool launch_gauge_ct(gf_ctx* c, int force, const void* hin, void* hout) {
         hipLaunchKernelGGL((k_fft_xy_gauge_ct<T, A, B>), dim3(L.n[2] * L.n[3], c->nact),                       \
                            dim3(ct_threads(4 * A * B, gauge_ept(A, B))), gauge_ct_lds(A, B, sizeof(cx<T>)),    \
                            c->st, reinterpret_cast<const cx<T>*>(c->Q), L.ps,                                  \
-                           reinterpret_cast<const cx<T>*>(hin), cxp<T>(hout), L.ps, twp<T>(c, 0), twp<T>(c, 1), \
+                           reinterpret_cast<const cx<T>*>(hin), cxp<T>(hout), twp<T>(c, 0), twp<T>(c, 1),       \
                            c->ctl, force, bt(c), exact_exp(c));                                                \
         return true;                                                                                           \
     }
@@ -572,25 +577,79 @@ void launch_gauge_pass(gf_ctx* c, int force, const void* hin, void* hout) {
     const cx<T>* hi = reinterpret_cast<const cx<T>*>(hin);
     if (L.eptC == kEPT)
         hipLaunchKernelGGL((k_fft_xy_gauge<T, kEPT>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
-                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, hi, cxp<T>(hout), L.ps, L.n[0], L.n[1], L.rs,
+                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, hi, cxp<T>(hout), L.n[0], L.n[1], L.rs,
                            c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c),
                            exact_exp(c));
     else
         hipLaunchKernelGGL((k_fft_xy_gauge<T, 16>), dim3(L.n[2] * L.n[3], c->nact), dim3(L.thrC), L.ldsC, c->st,
-                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, hi, cxp<T>(hout), L.ps, L.n[0], L.n[1], L.rs,
+                           reinterpret_cast<const cx<T>*>(c->Q), L.ps, hi, cxp<T>(hout), L.n[0], L.n[1], L.rs,
                            c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force, bt(c),
                            exact_exp(c));
     tstop(c);
 }
 
-// Blocks of the loop kernel: one per site block, or (t-march) one per 64-site run of the (x, y, z) volume.
+// Blocks of the loop kernel: one per site block, (t-march) one per 64-site run of the (x, y, z) volume,
+// or (brick march) one per brick and t segment.
 int loop_blocks(const Layout& L) {
+    if (L.zb == -1) return L.bk.nby * L.bk.nbz * (L.n[3] / L.bk.lt);
     return L.zb == 0 ? (int)(L.vol / L.n[3] / kFusedSites) : L.nblk_fused;
+}
+
+// Brick march geometry of a shape, if it has one: rows in y the fewest that make Nx*by a multiple of 64,
+// planes in z the most that keep a brick at 512 threads (1024 if one plane already needs more than 512),
+// t segments short enough for 1024 blocks (at least 2 steps each).
+void plan_brick(Layout& L) {
+    L.bk = BrickGeom{};
+    L.bk_threads = 0;
+    const int nx = L.n[0], ny = L.n[1], nz = L.n[2], nt = L.n[3];
+    int by = 0;
+    for (int d = 1; d <= ny; ++d)
+        if (ny % d == 0 && (nx * d) % kFusedSites == 0) {
+            by = d;
+            break;
+        }
+    if (by == 0 || 4 * nx * by > 1024) return;
+    const int cap = 4 * nx * by > 512 ? 1024 : 512;
+    int bz = 1;
+    for (int d = 1; d <= nz; ++d)
+        if (nz % d == 0 && 4 * nx * by * d <= cap) bz = d;
+    const int bricks = (ny / by) * (nz / bz);
+    int lt = nt;
+    for (int d = nt; d >= 2; --d)
+        if (nt % d == 0) {
+            lt = d;
+            if (bricks * (nt / d) >= 1024) break;
+        }
+    if (lt < 2 || brick_lds(nx, ny, nz, by, bz, L.fp32 ? 4 : 8) > kLdsMax - 1024) return;
+    // 32-bit byte offsets into the link planes (4 * NE planes) and the divergence planes
+    if ((size_t)4 * L.ne * L.ps * (L.fp32 ? 8 : 16) >= ((size_t)1 << 32)) return;
+    L.bk = BrickGeom{by, bz, ny / by, nz / bz, lt};
+    L.bk_threads = 4 * nx * by * bz;
+}
+
+template <typename T, int NE>
+void launch_brick(gf_ctx* c, const void* h, int force, Ctl* ctl, void* dst, int nact) {
+    const Layout& L = c->L;
+    const size_t lds = brick_lds(L.n[0], L.n[1], L.n[2], L.bk.by, L.bk.bz, sizeof(T));
+#define GF_BRICK(NTB)                                                                                                case NTB:                                                                                                            hipLaunchKernelGGL((k_update_measure_brick<T, NE, NTB>), dim3(loop_blocks(L), nact), dim3(NTB), lds,                                c->st, links_of<T, NE>(c), reinterpret_cast<const cx<T>*>(h), cxp<T>(dst), L.ps,                                 c->geom, L.bk, c->part, ctl, bt(c), force);                                                   break;
+    switch (L.bk_threads) {
+        GF_BRICK(256)
+        GF_BRICK(512)
+        GF_BRICK(768)
+        GF_BRICK(1024)
+        default:
+            break;
+    }
+#undef GF_BRICK
 }
 
 template <typename T, int NE>
 void launch_loop_kernel(gf_ctx* c, const void* h, int force, Ctl* ctl, void* dst, int nact) {
     const Layout& L = c->L;
+    if (L.zb == -1) {
+        launch_brick<T, NE>(c, h, force, ctl, dst, nact);
+        return;
+    }
     auto kern = L.zb == 0 ? k_update_measure<T, NE, true> : k_update_measure<T, NE, false>;
     hipLaunchKernelGGL(kern, dim3(loop_blocks(L), nact), dim3(kFusedThreads), 0, c->st, links_of<T, NE>(c),
                        reinterpret_cast<const cx<T>*>(h), cxp<T>(dst), L.ps, c->geom, c->part, ctl, bt(c), L.zb,
@@ -615,7 +674,7 @@ void launch_update_t(gf_ctx* c) {
     const Layout& L = c->L;
     tstart(c, GF_K_UPDATE);
     hipLaunchKernelGGL(k_h_update<T>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st, reinterpret_cast<const cx<T>*>(c->Q),
-                       L.ps, cxp<T>(c->Hb[cur(c)]), L.ps, L.vol, exact_exp(c));
+                       L.ps, cxp<T>(c->Hb[cur(c)]), L.vol, exact_exp(c));
     tstop(c);
 }
 
@@ -705,6 +764,17 @@ gf_status unpack_links(gf_ctx* c, double* dst) {
 }
 
 // FFT kernels take more than 64 KB of dynamic LDS on large planes (gfx950 has 160 KB per CU).
+template <typename T, int NE>
+void raise_lds_brick() {
+    const void* fns[] = {
+        reinterpret_cast<const void*>(&k_update_measure_brick<T, NE, 256>),
+        reinterpret_cast<const void*>(&k_update_measure_brick<T, NE, 512>),
+        reinterpret_cast<const void*>(&k_update_measure_brick<T, NE, 768>),
+        reinterpret_cast<const void*>(&k_update_measure_brick<T, NE, 1024>),
+    };
+    for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsMax);
+}
+
 void raise_lds_limits() {
     static bool done = false;
     if (done) return;
@@ -724,6 +794,10 @@ void raise_lds_limits() {
     for (const void* f : fns) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
     raise_lds_ct<double>();
     raise_lds_ct<float>();
+    raise_lds_brick<double, 9>();
+    raise_lds_brick<double, 6>();
+    raise_lds_brick<float, 9>();
+    raise_lds_brick<float, 6>();
     (void)hipGetLastError();
     done = true;
 }
@@ -763,7 +837,7 @@ void field_unpack(gf_ctx* c, const void* src, void* dst) {
 template <typename T>
 void gauge_unpack(gf_ctx* c, const void* rows, void* dst) {
     hipLaunchKernelGGL(k_gauge_unpack<T>, dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st,
-                       reinterpret_cast<const cx<T>*>(rows), c->L.ps, reinterpret_cast<double*>(dst), c->L.vol);
+                       reinterpret_cast<const cx<T>*>(rows), reinterpret_cast<double*>(dst), c->L.vol);
 }
 
 // Forward FFT of Q, filter, and either the plain inverse (x, y) pass (gauge null) or the gauge pass writing
@@ -858,6 +932,7 @@ double time_pass(gf_ctx* c, bool xy) {
 // 32 blocks.
 std::vector<int> zb_candidates(const Layout& L) {
     std::vector<int> v{1};
+    if (L.bk_threads > 0) v.push_back(-1);
     const int64_t vs = (int64_t)L.n[0] * L.n[1] * L.n[2];
     if (vs % kFusedSites == 0 && L.n[3] >= 4 && vs / kFusedSites >= 32) v.push_back(0);
     if ((L.n[0] * L.n[1]) % kFusedSites != 0) return v;
@@ -1115,10 +1190,10 @@ gf_status init_plain(gf_ctx* c, const gf_params& p, const Layout& L, double* d_l
     if (s == GF_OK) {  // no update applied yet: H = 1 in buffer 0
         if (L.fp32)
             hipLaunchKernelGGL(k_gauge_identity<float>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st,
-                               cxp<float>(c->Hb[0]), L.ps, L.vol);
+                               cxp<float>(c->Hb[0]), L.vol);
         else
             hipLaunchKernelGGL(k_gauge_identity<double>, dim3(L.nblk), dim3(kSiteThreads), 0, c->st,
-                               cxp<double>(c->Hb[0]), L.ps, L.vol);
+                               cxp<double>(c->Hb[0]), L.vol);
         s = launched(c, "identity launch");
     }
     if (s == GF_OK && measure) s = launch_measure(c);
@@ -1214,8 +1289,8 @@ gf_status mixed_run(gf_ctx* c, double tol, int64_t max_iter, gf_result* r) {
         }
         // hand-over: the double child holds the input links; it takes over the float transform in double
         hipLaunchKernelGGL(k_promote_h, dim3(b->L.nblk), dim3(kSiteThreads), 0, b->st,
-                           reinterpret_cast<const cx<float>*>(a->Hb[cur(a)]), a->L.ps,
-                           reinterpret_cast<cx<double>*>(b->Hb[cur(b)]), b->L.ps, b->L.vol);
+                           reinterpret_cast<const cx<float>*>(a->Hb[cur(a)]),
+                           reinterpret_cast<cx<double>*>(b->Hb[cur(b)]), b->L.vol);
         s = launched(b, "hand-over launch");
         if (s == GF_OK) s = launch_measure(b);
         if (s == GF_OK) s = read_head(b);
@@ -1675,8 +1750,8 @@ gf_status advance_group(gf_ctx* c, BatchGroup& g, double tol, std::vector<BatchO
                     }
                     gf_ctx* w = g.view[1][i];
                     hipLaunchKernelGGL(k_promote_h, dim3(w->L.nblk), dim3(kSiteThreads), 0, w->st,
-                                       reinterpret_cast<const cx<float>*>(v->Hb[cur(v)]), v->L.ps,
-                                       reinterpret_cast<cx<double>*>(w->Hb[cur(w)]), w->L.ps, w->L.vol);
+                                       reinterpret_cast<const cx<float>*>(v->Hb[cur(v)]),
+                                       reinterpret_cast<cx<double>*>(w->Hb[cur(w)]), w->L.vol);
                     s = launched(w, "hand-over launch");
                     if (s == GF_OK) s = launch_measure(w);
                     if (s != GF_OK) return fail(c, s, w->err);
@@ -1902,8 +1977,8 @@ gf_status run_batch_fused(gf_ctx* c, BatchState& b, double tol, int64_t max_iter
                     }
                     gf_ctx* w = g.view[1][i];
                     hipLaunchKernelGGL(k_promote_h, dim3(w->L.nblk), dim3(kSiteThreads), 0, c->st,
-                                       reinterpret_cast<const cx<float>*>(v->Hb[cur(v)]), v->L.ps,
-                                       reinterpret_cast<cx<double>*>(w->Hb[cur(w)]), w->L.ps, w->L.vol);
+                                       reinterpret_cast<const cx<float>*>(v->Hb[cur(v)]),
+                                       reinterpret_cast<cx<double>*>(w->Hb[cur(w)]), w->L.vol);
                     s = launched(w, "hand-over launch");
                     if (s == GF_OK) s = launch_measure(w);
                     if (s != GF_OK) return fail(c, s, w->err);

@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(NTMAX) k_fused_gauge(const FusedGroup<T>* __re
     const int j = fused_segment(tb.first[2], tb.nseg, b);
     const FusedGroup<T>& g = grp[tb.group[j]];
     const size_t o = (size_t)tb.cfg[j] * g.cs;
-    fft_xy_gauge_body<T, EPT>(fshift(g.Q, o), g.ps, fshift(g.H[hp], o), fshift(g.H[1 - hp], o), g.ps, g.geom.n[0],
+    fft_xy_gauge_body<T, EPT>(fshift(g.Q, o), g.ps, fshift(g.H[hp], o), fshift(g.H[1 - hp], o), g.geom.n[0],
                               g.geom.n[1], g.rs, g.plan[0], g.plan[1], fshift(g.tw[0], o), fshift(g.tw[1], o),
                               fshift(g.ctl, o), 0, exact, b - tb.first[2][j]);
 }

@@ -145,7 +145,7 @@ constexpr int gauge_ept(int nx, int ny) { return 4 * nx * ny <= 8 * 1024 ? 8 : 1
 template <typename T, int NX, int NY>
 __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
     k_fft_xy_gauge_ct(const cx<T>* __restrict__ Q, size_t zps, const cx<T>* __restrict__ Hin,
-                      cx<T>* __restrict__ Hout, size_t gps, const cx<T>* __restrict__ twgx,
+                      cx<T>* __restrict__ Hout, const cx<T>* __restrict__ twgx,
                       const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl, int force, Batch bt, int exact) {
     constexpr int RS = NX + 1, P = NX * NY, PL = NY * RS, E = 4 * P;
     constexpr int NT = ct_threads(E, gauge_ept(NX, NY));
@@ -186,11 +186,11 @@ __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
             if (Hin != nullptr) {
                 su3<T> h;
 #pragma unroll
-                for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = Hin[(size_t)k * gps + base + r];
+                for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = Hin[tile_index(6, k, base + r)];
                 g = gauge_times(g, h);
             }
 #pragma unroll
-            for (int k = 0; k < 6; ++k) Hout[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
+            for (int k = 0; k < 6; ++k) Hout[tile_index(6, k, base + r)] = g.e[k / 3][k % 3];
         }
     }
 }

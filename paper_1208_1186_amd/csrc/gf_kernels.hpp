@@ -98,27 +98,27 @@ __global__ void __launch_bounds__(kSiteThreads) k_field_unpack(const cx<T>* __re
 }
 
 // ------------------------------------------------------------ gauge field g
-// g(x) is stored as its first two rows (six complex planes, gps apart); the
-// third row follows from unitarity.
+// g(x) and the transform H(x) are stored as their first two rows (six complex entries per site, in
+// tiles of 64 sites); the third row follows from unitarity.
 template <typename T>
-__device__ __forceinline__ su3<T> g_rows_at(const cx<T>* __restrict__ G, size_t gps, int64_t s) {
+__device__ __forceinline__ su3<T> g_rows_at(const cx<T>* __restrict__ G, int64_t s) {
     su3<T> g;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) g.e[k / 3][k % 3] = G[(size_t)k * gps + s];
+    for (int k = 0; k < 6; ++k) g.e[k / 3][k % 3] = G[tile_index(6, k, s)];
     third_row(g.e[0], g.e[1], g.e[2]);
     return g;
 }
 
 // Stored g rows -> canonical matrix field.
 template <typename T>
-__global__ void __launch_bounds__(kSiteThreads) k_gauge_unpack(const cx<T>* __restrict__ G, size_t gps,
-                                                               double* __restrict__ f, int64_t vol) {
+__global__ void __launch_bounds__(kSiteThreads) k_gauge_unpack(const cx<T>* __restrict__ G, double* __restrict__ f,
+                                                               int64_t vol) {
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
     if (s >= vol) return;
     su3<double> g;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const cx<T> e = G[(size_t)k * gps + s];
+        const cx<T> e = G[tile_index(6, k, s)];
         g.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
     }
     third_row(g.e[0], g.e[1], g.e[2]);
@@ -132,11 +132,11 @@ __global__ void __launch_bounds__(kSiteThreads) k_gauge_unpack(const cx<T>* __re
 
 // Row 1-2 planes of a transform at site s, promoted to double, row 3 rebuilt in double.
 template <typename T>
-__device__ __forceinline__ su3<double> rows_at_fp64(const cx<T>* __restrict__ G, size_t gps, int64_t s) {
+__device__ __forceinline__ su3<double> rows_at_fp64(const cx<T>* __restrict__ G, int64_t s) {
     su3<double> g;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const cx<T> e = G[(size_t)k * gps + s];
+        const cx<T> e = G[tile_index(6, k, s)];
         g.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
     }
     third_row(g.e[0], g.e[1], g.e[2]);
@@ -153,7 +153,7 @@ __global__ void __launch_bounds__(kSiteThreads) k_unpack_h(Links<T, NE> U0, cons
     if (s >= g.vol) return;
     int c[4];
     site_coords(g, s, c);
-    const su3<double> h0 = rows_at_fp64(H, U0.ps, s);
+    const su3<double> h0 = rows_at_fp64(H, s);
 #pragma unroll
     for (int mu = 0; mu < 4; ++mu) {
         su3<double> u;
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kSiteThreads) k_unpack_h(Links<T, NE> U0, cons
             u.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
         }
         if constexpr (NE == 6) third_row(u.e[0], u.e[1], u.e[2]);
-        const su3<double> h1 = rows_at_fp64(H, U0.ps, site_fwd(g, s, c, mu));
+        const su3<double> h1 = rows_at_fp64(H, site_fwd(g, s, c, mu));
         su3<double> v;
         if constexpr (NE == 6) {  // two-row storage: the third row of the result is rebuilt from its first two
             v = mul_adj<double, 2>(mul_rows<double, 2>(h0, u), h1);
@@ -253,7 +253,7 @@ template <typename T, int NE>
 __device__ __forceinline__ su3<T> link_h(const Links<T, NE>& U0, const cx<T>* __restrict__ H, int mu, int64_t y,
                                          int64_t yf) {
     const su3<T> u = U0.load(mu, y);
-    return mul_adj<T, 3>(mul(g_rows_at(H, U0.ps, y), u), g_rows_at(H, U0.ps, yf));
+    return mul_adj<T, 3>(mul(g_rows_at(H, y), u), g_rows_at(H, yf));
 }
 
 // y + d for a direction d known only at run time (a switch, so that no array is indexed by d).
@@ -370,15 +370,15 @@ __device__ __forceinline__ su3<T> gauge_times(const su3<T>& g, su3<T> h) {
 // single-stage entry point (the loop does the same in the inverse (x, y) pass).
 template <typename T>
 __global__ void __launch_bounds__(kSiteThreads) k_h_update(const cx<T>* __restrict__ Z, size_t zps, cx<T>* __restrict__ H,
-                                                           size_t hps, int64_t vol, int exact) {
+                                                           int64_t vol, int exact) {
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
     if (s >= vol) return;
     su3<T> h;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = H[(size_t)k * hps + s];
+    for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = H[tile_index(6, k, s)];
     const su3<T> r = gauge_times(g_at_packed(Z, zps, s, exact != 0), h);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) H[(size_t)k * hps + s] = r.e[k / 3][k % 3];
+    for (int k = 0; k < 6; ++k) H[tile_index(6, k, s)] = r.e[k / 3][k % 3];
 }
 
 // ------------------------------------------------ loop kernel: update + divergence
@@ -492,9 +492,9 @@ __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const G
         su3<T> h0, hfw, hb, u, ub;
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            h0.e[k / 3][k % 3] = io.H[(size_t)k * ps + s];
-            hfw.e[k / 3][k % 3] = io.H[(size_t)k * ps + sfw];
-            hb.e[k / 3][k % 3] = io.H[(size_t)k * ps + sld];
+            h0.e[k / 3][k % 3] = io.H[tile_index(6, k, s)];
+            hfw.e[k / 3][k % 3] = io.H[tile_index(6, k, sfw)];
+            hb.e[k / 3][k % 3] = io.H[tile_index(6, k, sld)];
         }
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
@@ -593,32 +593,298 @@ __global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE
     if (threadIdx.x == 0 && b == 0) ctl->pending = 1;
 }
 
+// ------------------------------------------------ loop kernel, brick march
+// Bricks of the (x, y, z) volume: whole x rows, by rows in y and bz planes in z (Nx*by a multiple of 64,
+// so that every 64-site block of the canonical order lies in one brick), each stepping through a segment
+// of lt values of t. Every lane (site, direction mu) forms the one link it owns, U_mu(x), and puts its
+// anti-Hermitian part in LDS; the divergence at x then takes that of the back link U_mu(x - mu) from the
+// lane that owns it: the same brick at this step (x, and y or z inside the brick), the previous step
+// (t), or a halo lane that forms the links entering the brick from below in y and z (and in t at the
+// segment's first step). Links are formed once each instead of twice, and the back links' U0 and H are
+// fetched only for the halo. The arithmetic of every link and of the divergence is that of the other
+// traversals and the partials are summed by 64-site block in the same order, so the results are the
+// same bits.
+struct BrickGeom {
+    int by, bz;    // rows in y, planes in z per brick
+    int nby, nbz;  // bricks along y and z
+    int lt;        // t steps per segment
+};
+
+// Nine planes of n anti-Hermitian parts in LDS (structure of arrays).
+template <typename T>
+struct AhPlanes {
+    T* p;
+    int n;
+    __device__ __forceinline__ void put(int i, const AhAcc<T>& a) const {
+        p[i] = a.o01.re;
+        p[n + i] = a.o01.im;
+        p[2 * n + i] = a.o02.re;
+        p[3 * n + i] = a.o02.im;
+        p[4 * n + i] = a.o12.re;
+        p[5 * n + i] = a.o12.im;
+        p[6 * n + i] = a.d0;
+        p[7 * n + i] = a.d1;
+        p[8 * n + i] = a.d2;
+    }
+    __device__ __forceinline__ AhAcc<T> get(int i) const {
+        AhAcc<T> a;
+        a.o01 = {p[i], p[n + i]};
+        a.o02 = {p[2 * n + i], p[3 * n + i]};
+        a.o12 = {p[4 * n + i], p[5 * n + i]};
+        a.d0 = p[6 * n + i];
+        a.d1 = p[7 * n + i];
+        a.d2 = p[8 * n + i];
+        return a;
+    }
+};
+
+// Element at a 32-bit byte offset from a wave-uniform base: the scalar-base form of the global memory
+// instructions, one offset register per lane for every plane instead of a 64-bit address per load.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* base, uint32_t off, const T& v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
+// Anti-Hermitian part of U_m(xb) = H(xb) U0_m(xb) H(x)^dag, xb the back neighbour of x along m (site
+// indices below 2^32 / 16; the caller checks the lattice fits).
+template <typename T, int NE>
+__device__ __forceinline__ AhAcc<T> back_link_ah(const LoopIO<T, NE>& io, int m, uint32_t x, uint32_t xb) {
+    constexpr uint32_t E = sizeof(cx<T>);
+    su3<T> hb, ub, h0;
+    const uint32_t ob = tile_byte_offset<cx<T>>(6, xb), ox = tile_byte_offset<cx<T>>(6, x);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        hb.e[k / 3][k % 3] = ld_off(io.H + k * kTileSites, ob);
+        h0.e[k / 3][k % 3] = ld_off(io.H + k * kTileSites, ox);
+    }
+    const uint32_t ou = tile_byte_offset<cx<T>>(4 * NE, xb) + (uint32_t)(m * NE * kTileSites) * E;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) ub.e[k / 3][k % 3] = ld_off(io.U0.p + k * kTileSites, ou);
+    third_row(hb.e[0], hb.e[1], hb.e[2]);
+    third_row(h0.e[0], h0.e[1], h0.e[2]);
+    if constexpr (NE == 6) third_row(ub.e[0], ub.e[1], ub.e[2]);
+    AhAcc<T> a;
+    a.set(updated_link(hb, ub, h0));
+    return a;
+}
+
+// LDS bytes of one brick: own links (4 per site), the previous step's t links, the y and z halos.
+__host__ __device__ constexpr size_t brick_lds(int nx, int ny, int nz, int by, int bz, size_t tsz) {
+    return (size_t)9 * tsz *
+           (5 * (size_t)nx * by * bz + (by < ny ? (size_t)nx * bz : 0) + (bz < nz ? (size_t)nx * by : 0));
+}
+
+// NTB = 4 * Nx * by * bz threads; grid = bricks * segments.
+template <typename T, int NE, int NTB>
+__global__ void __launch_bounds__(NTB) k_update_measure_brick(Links<T, NE> U0, const cx<T>* __restrict__ H,
+                                                              cx<T>* __restrict__ D, size_t ps, Geom g,
+                                                              BrickGeom bg, double2* __restrict__ part, Ctl* ctl,
+                                                              Batch bt, int force) {
+    LoopIO<T, NE> io{U0, H, D, ps};
+    {
+        const size_t bo = boff(bt);
+        io.U0.p = bshift(io.U0.p, bo);
+        io.H = bshift(io.H, bo);
+        io.D = bshift(io.D, bo);
+        part = bshift(part, bo);
+        ctl = bshift(ctl, bo);
+    }
+    if (!force && ctl->done) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double sa[NTB / 64], sb[NTB / 64];
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2], nt = g.n[3];
+    const int R = NTB / 4;  // sites per brick
+    const int hy = bg.by < ny ? nx * bg.bz : 0, hz = bg.bz < nz ? nx * bg.by : 0;
+    T* lds = reinterpret_cast<T*>(smem);
+    // LDS planes: own links (entry mu * R + r), the previous step's t links (R), y halo (hy), z halo (hz)
+    const AhPlanes<T> own{lds, 4 * R};
+    const AhPlanes<T> prev{lds + 9 * 4 * R, R};
+
+    const int b = xcd_remap(blockIdx.x, gridDim.x);
+    const int nbr = bg.nby * bg.nbz;
+    const int brick = b % nbr, seg = b / nbr;
+    const int y0 = (brick % bg.nby) * bg.by, z0 = (brick / bg.nby) * bg.bz;
+    const int t0 = seg * bg.lt;
+    const int64_t sy = nx, sz = (int64_t)nx * ny, vs = sz * nz;
+
+    const int lane = threadIdx.x & 63;
+    const int mu = lane >> 4;
+    const int r = (threadIdx.x >> 6) * 16 + (lane & 15);  // brick site of this lane
+    const int xl = r % nx, yl = (r / nx) % bg.by, zl = r / (nx * bg.by);
+    const int64_t sxy = xl + sy * (y0 + yl) + sz * (z0 + zl);
+    const int cm = mu == 0 ? xl : mu == 1 ? y0 + yl : z0 + zl;  // coordinate along mu (spatial mu)
+    const int nm = mu == 0 ? nx : mu == 1 ? ny : nz;
+    const int64_t sm = mu == 0 ? 1 : mu == 1 ? sy : sz;
+    const int64_t dfw_sp = cm == nm - 1 ? -(int64_t)(nm - 1) * sm : sm;
+    // where this lane finds the anti-Hermitian part of its back link: planes (offset in T, length) and
+    // slot; one read through a per-lane choice of planes, not one read per source
+    int bk_off = 0, bk_n = 4 * R, bk_i = 0;
+    if (mu == 0) {
+        bk_i = xl == 0 ? r + nx - 1 : r - 1;
+    } else if (mu == 1) {
+        if (yl > 0) bk_i = R + r - nx;
+        else if (hy == 0) bk_i = R + r + nx * (bg.by - 1);
+        else {
+            bk_off = 9 * 5 * R;
+            bk_n = hy;
+            bk_i = xl + nx * zl;
+        }
+    } else if (mu == 2) {
+        if (zl > 0) bk_i = 2 * R + r - nx * bg.by;
+        else if (hz == 0) bk_i = 2 * R + r + nx * bg.by * (bg.bz - 1);
+        else {
+            bk_off = 9 * (5 * R + hy);
+            bk_n = hz;
+            bk_i = xl + nx * yl;
+        }
+    } else {
+        bk_off = 9 * 4 * R;
+        bk_n = R;
+        bk_i = r;
+    }
+    const AhPlanes<T> back{lds + bk_off, bk_n};
+    // this thread's halo task: a y, z or (first step) t link entering the brick from below
+    const int task = threadIdx.x;
+    int hm = 0;
+    int64_t hxy = 0, hdb = 0;  // halo site (spatial) and the offset to its back neighbour
+    int hslot = 0, h_off = 0, h_n = 1;
+    if (task < hy) {
+        hm = 1;
+        const int hx = task % nx, hzl = task / nx;
+        hxy = hx + sy * y0 + sz * (z0 + hzl);
+        hdb = y0 == 0 ? (int64_t)(ny - 1) * sy : -sy;
+        hslot = task;
+        h_off = 9 * 5 * R;
+        h_n = hy;
+    } else if (task < hy + hz) {
+        hm = 2;
+        const int j = task - hy;
+        const int hx = j % nx, hyl = j / nx;
+        hxy = hx + sy * (y0 + hyl) + sz * z0;
+        hdb = z0 == 0 ? (int64_t)(nz - 1) * sz : -sz;
+        hslot = j;
+        h_off = 9 * (5 * R + hy);
+        h_n = hz;
+    } else if (task < hy + hz + R) {
+        hm = 3;  // first step only
+        const int j = task - hy - hz;
+        const int jx = j % nx, jy = (j / nx) % bg.by, jz = j / (nx * bg.by);
+        hxy = jx + sy * (y0 + jy) + sz * (z0 + jz);
+        hdb = t0 == 0 ? (int64_t)(nt - 1) * vs : -vs;
+        hslot = j;
+        h_off = 9 * 4 * R;
+        h_n = R;
+    }
+    const AhPlanes<T> hdst{lds + h_off, h_n};
+    const int gi = threadIdx.x >> 8;  // 64-site block of this thread within the brick
+#pragma unroll 1
+    for (int tt = t0; tt < t0 + bg.lt; ++tt) {
+        // t through a wave-uniform intrinsic: addresses are recomputed from it each step rather than
+        // carried as one induction pointer per load (which took the registers of a second wave)
+        const int t = __builtin_amdgcn_readfirstlane(tt);
+        // the halo first, so that none of this lane's own link is held meanwhile
+        if (hm == 1 || hm == 2 || (hm == 3 && t == t0)) {
+            const int64_t hs = hxy + vs * t;
+            hdst.put(hslot, back_link_ah<T, NE>(io, hm, (uint32_t)hs, (uint32_t)(hs + hdb)));
+        }
+        const int64_t s = sxy + vs * t;
+        const int64_t sfw = mu == 3 ? (t == nt - 1 ? s - (int64_t)(nt - 1) * vs : s + vs) : s + dfw_sp;
+        constexpr uint32_t E = sizeof(cx<T>);
+        const uint32_t os = tile_byte_offset<cx<T>>(6, (uint32_t)s), ofw = tile_byte_offset<cx<T>>(6, (uint32_t)sfw);
+        const uint32_t ou = tile_byte_offset<cx<T>>(4 * NE, (uint32_t)s) + (uint32_t)(mu * NE * kTileSites) * E;
+        su3<T> h0, hfw, u;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            h0.e[k / 3][k % 3] = ld_off(io.H + k * kTileSites, os);
+            hfw.e[k / 3][k % 3] = ld_off(io.H + k * kTileSites, ofw);
+        }
+#pragma unroll
+        for (int k = 0; k < NE; ++k) u.e[k / 3][k % 3] = ld_off(io.U0.p + k * kTileSites, ou);
+        third_row(h0.e[0], h0.e[1], h0.e[2]);
+        third_row(hfw.e[0], hfw.e[1], hfw.e[2]);
+        if constexpr (NE == 6) third_row(u.e[0], u.e[1], u.e[2]);
+        const su3<T> un = updated_link(h0, u, hfw);  // U_mu(x)
+        double fsum = (double)un.e[0][0].re + (double)un.e[1][1].re + (double)un.e[2][2].re;
+        AhAcc<T> mine;
+        mine.set(un);
+        own.put(mu * R + r, mine);
+        __syncthreads();
+        AhAcc<T> acc = back.get(bk_i);
+        acc.sub(mine);
+        if (mu == 3) prev.put(r, mine);  // the back t link of the next step (only this lane uses the slot)
+        acc.o01.re = xor_sum4(acc.o01.re);
+        acc.o01.im = xor_sum4(acc.o01.im);
+        acc.o02.re = xor_sum4(acc.o02.re);
+        acc.o02.im = xor_sum4(acc.o02.im);
+        acc.o12.re = xor_sum4(acc.o12.re);
+        acc.o12.im = xor_sum4(acc.o12.im);
+        acc.d0 = xor_sum4(acc.d0);
+        acc.d1 = xor_sum4(acc.d1);
+        acc.d2 = xor_sum4(acc.d2);
+        double tsum = 0.0;
+        {
+            const T tr = (acc.d0 + acc.d1 + acc.d2) / T(3);
+            const T d0 = T(2) * (acc.d0 - tr), d1 = T(2) * (acc.d1 - tr);
+            const cx<T> z0c = acc.o01, z1c = acc.o02, z2c = acc.o12;
+            const cx<T> out = mu == 0 ? z0c : mu == 1 ? z1c : mu == 2 ? z2c : cx<T>{d0, d1};
+            st_off(io.D, ((uint32_t)mu * (uint32_t)ps + (uint32_t)s) * E, out);
+            if (mu == 0) {
+                const double e0 = norm2(z0c), e1 = norm2(z1c), e2 = norm2(z2c);
+                const double dd0 = d0, dd1 = d1;
+                tsum = 2.0 * (e0 + e1 + e2) + dd0 * dd0 + dd1 * dd1 + (dd0 + dd1) * (dd0 + dd1);
+            }
+        }
+        // partial sums of each 64-site block (four waves, in the order of the other traversals)
+        fsum = wave_sum(fsum);
+        tsum = wave_sum(tsum);
+        if (lane == 0) {
+            sa[threadIdx.x >> 6] = fsum;
+            sb[threadIdx.x >> 6] = tsum;
+        }
+        __syncthreads();
+        if ((threadIdx.x & 255) == 0) {
+            double ta = 0.0, tb = 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                ta += sa[4 * gi + i];
+                tb += sb[4 * gi + i];
+            }
+            part[s / kFusedSites] = make_double2(ta, tb);  // this thread's site opens the 64-site block
+        }
+    }
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->pending = 1;
+}
+
 // ------------------------------------------------ mixed-precision hand-over
 // Rows 1-2 of the identity in the six planes of a transform.
 template <typename T>
-__global__ void __launch_bounds__(kSiteThreads) k_gauge_identity(cx<T>* __restrict__ A, size_t ps, int64_t vol) {
+__global__ void __launch_bounds__(kSiteThreads) k_gauge_identity(cx<T>* __restrict__ A, int64_t vol) {
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
     if (s >= vol) return;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) A[(size_t)k * ps + s] = {(k == 0 || k == 4) ? T(1) : T(0), T(0)};
+    for (int k = 0; k < 6; ++k) A[tile_index(6, k, s)] = {(k == 0 || k == 4) ? T(1) : T(0), T(0)};
 }
 
 // The float transform accumulated by the bulk iterations, promoted to double and re-orthonormalised in
 // double: the double-precision phase continues from the same links, H U0 H(x+mu)^dag, with U0 the
 // untouched input in double.
-__global__ void __launch_bounds__(kSiteThreads) k_promote_h(const cx<float>* __restrict__ A, size_t aps,
-                                                            cx<double>* __restrict__ B, size_t bps, int64_t vol) {
+__global__ void __launch_bounds__(kSiteThreads) k_promote_h(const cx<float>* __restrict__ A, cx<double>* __restrict__ B,
+                                                            int64_t vol) {
     const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
     if (s >= vol) return;
     su3<double> m;
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-        const cx<float> e = A[(size_t)k * aps + s];
+        const cx<float> e = A[tile_index(6, k, s)];
         m.e[k / 3][k % 3] = {(double)e.re, (double)e.im};
     }
     reunitarize(m);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) B[(size_t)k * bps + s] = m.e[k / 3][k % 3];
+    for (int k = 0; k < 6; ++k) B[tile_index(6, k, s)] = m.e[k / 3][k % 3];
 }
 
 // --------------------------------------------------------------------- FFT
@@ -769,11 +1035,11 @@ __global__ void __launch_bounds__(1024) k_fft_zt(cx<T>* __restrict__ Z, size_t z
 // Inverse 2D FFT over (x, y) of all four packed fields of one (z, t) plane,
 // then g(x) = reunitarize(1 + (alpha/2) Delta~(x)) for every site of the
 // plane and the update of the stored transform, Hout = reunitarize(g Hin)
-// (rows 1-2, six planes gps apart); with Hin null, g itself goes to Hout.
+// (rows 1-2, in tiles of 64 sites); with Hin null, g itself goes to Hout.
 template <typename T, int EPT>
 __device__ __forceinline__ void fft_xy_gauge_body(const cx<T>* __restrict__ Q, size_t zps,
                                                   const cx<T>* __restrict__ Hin, cx<T>* __restrict__ Hout,
-                                                  size_t gps, int nx, int ny, int rs, const FftPlan& px,
+                                                  int nx, int ny, int rs, const FftPlan& px,
                                                   const FftPlan& py, const cx<T>* __restrict__ twgx,
                                                   const cx<T>* __restrict__ twgy, const Ctl* __restrict__ ctl,
                                                   int force, int exact, int blk) {
@@ -803,18 +1069,18 @@ __device__ __forceinline__ void fft_xy_gauge_body(const cx<T>* __restrict__ Q, s
         if (Hin != nullptr) {
             su3<T> h;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = Hin[(size_t)k * gps + base + r];
+            for (int k = 0; k < 6; ++k) h.e[k / 3][k % 3] = Hin[tile_index(6, k, base + r)];
             g = gauge_times(g, h);
         }
 #pragma unroll
-        for (int k = 0; k < 6; ++k) Hout[(size_t)k * gps + base + r] = g.e[k / 3][k % 3];
+        for (int k = 0; k < 6; ++k) Hout[tile_index(6, k, base + r)] = g.e[k / 3][k % 3];
     }
 }
 
 template <typename T, int EPT>
 __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const cx<T>* __restrict__ Q, size_t zps,
                                                        const cx<T>* __restrict__ Hin, cx<T>* __restrict__ Hout,
-                                                       size_t gps, int nx, int ny, int rs, FftPlan px, FftPlan py,
+                                                       int nx, int ny, int rs, FftPlan px, FftPlan py,
                                                        const cx<T>* __restrict__ twgx, const cx<T>* __restrict__ twgy,
                                                        const Ctl* __restrict__ ctl, int force, Batch bt, int exact) {
     {
@@ -826,7 +1092,7 @@ __global__ void __launch_bounds__(EPT == 16 ? 640 : 1024) k_fft_xy_gauge(const c
         twgy = bshift(twgy, bo);
         ctl = bshift(ctl, bo);
     }
-    fft_xy_gauge_body<T, EPT>(Q, zps, Hin, Hout, gps, nx, ny, rs, px, py, twgx, twgy, ctl, force, exact,
+    fft_xy_gauge_body<T, EPT>(Q, zps, Hin, Hout, nx, ny, rs, px, py, twgx, twgy, ctl, force, exact,
                               xcd_remap(blockIdx.x, gridDim.x));
 }
 

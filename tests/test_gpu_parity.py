@@ -315,11 +315,14 @@ def test_plaquette_matches_oracle_and_is_invariant(dims, precision):
 
 def traversals(dims):
     """Loop-kernel traversals the library accepts on this shape: z groupings 1, 2, 4, 8 (a divisor of Nz
-    below Nz, 64 dividing Nx*Ny) and 0, the t-march (64 dividing Nx*Ny*Nz, Nt >= 4, >= 32 blocks)."""
+    below Nz, 64 dividing Nx*Ny), 0, the t-march (64 dividing Nx*Ny*Nz, Nt >= 4, >= 32 blocks), and -1,
+    the brick march (a divisor by of Ny with 64 dividing Nx*by and 4*Nx*by <= 1024)."""
     nx, ny, nz, nt = dims
     out = [1] + [z for z in (2, 4, 8) if (nx * ny) % 64 == 0 and nz % z == 0 and nz > z]
     if (nx * ny * nz) % 64 == 0 and nt >= 4 and nx * ny * nz // 64 >= 32:
         out.append(0)
+    if any(ny % d == 0 and (nx * d) % 64 == 0 and 4 * nx * d <= 1024 for d in range(1, ny + 1)):
+        out.append(-1)
     return out
 
 
@@ -357,12 +360,13 @@ def test_loop_traversal_does_not_change_results(dims, prec):
 @pytest.mark.parametrize("dims,prec", [((32, 32, 32, 32), "fp64_18"), ((32, 32, 32, 32), "fp32_12"),
                                        ((48, 48, 48, 8), "fp64_18"), ((48, 48, 48, 8), "fp32_12")])
 def test_loop_traversals_full_size(dims, prec):
-    """The workload lattices: the t-march and the plain sweep agree bitwise over three updates (the
-    oracle's trajectory at 32^4 is checked in test_gpu_headline.py with the traversal the autotuner keeps)."""
+    """The workload lattices: the t-march, the brick march and the plain sweep agree bitwise over three
+    updates (the oracle's trajectory at 32^4 is checked in test_gpu_headline.py with the traversal the
+    autotuner keeps)."""
     print(f"traversals full size {dims} {prec}", flush=True)
     u = synth.make_config(dims, 0)
     runs = []
-    for zb in (1, 0):
+    for zb in (1, 0, -1):
         links = torch.from_numpy(u).cuda()
         fx = gf.GaugeFixer(links, prec, check_every=3)
         fx.set_loop_traversal(zb)
@@ -370,8 +374,9 @@ def test_loop_traversals_full_size(dims, prec):
         runs.append((links.cpu(), fx.history(4)))
         fx.close()
         del links
-    assert torch.equal(runs[0][0], runs[1][0])
-    assert np.array_equal(runs[0][1][0], runs[1][1][0]) and np.array_equal(runs[0][1][1], runs[1][1][1])
+    for other in runs[1:]:
+        assert torch.equal(runs[0][0], other[0])
+        assert np.array_equal(runs[0][1][0], other[1][0]) and np.array_equal(runs[0][1][1], other[1][1])
 
 
 @pytest.mark.parametrize("dims,precision,alpha", [((8, 8, 8, 8), "fp64_18", 0.08), ((12, 6, 4, 8), "fp64_18", 1.5),
