@@ -1390,7 +1390,7 @@ struct BatchGroup {
     int* h_act = nullptr;              // pinned
     unsigned char* h_heads = nullptr;  // pinned
     std::vector<unsigned char> h_views[2];  // the configurations' control-block heads (host)
-    hipStream_t st = nullptr;          // the group's own stream: groups run side by side
+    hipStream_t st = nullptr;          // the group's stream (shared when there are more groups than streams)
     hipEvent_t ev = nullptr;           // end of the group's last queued read-back
     // progress of gf_fix_until_batch
     enum Stage { kStart, kRun, kEnd, kDone } stage = kStart;
@@ -1418,7 +1418,12 @@ struct BatchState {
     int* h_seg = nullptr;  // pinned staging of the segment table
     int thr[3] = {64, 64, 64};   // block sizes of the (x, y), (z, t) and gauge passes (largest shape)
     size_t lds[3] = {0, 0, 0};
+    std::vector<hipStream_t> streams;  // the groups' streams, owned here
 };
+
+// Streams of a batch's shape groups: as many as the hardware queues a process gets besides the caller's
+// stream (4 by default), so that the groups' streams are not multiplexed onto fewer queues than streams.
+constexpr int kBatchStreams = 3;
 
 void free_batch(BatchState* b) {
     if (b->h_seg) (void)hipHostFree(b->h_seg);
@@ -1430,10 +1435,10 @@ void free_batch(BatchState* b) {
         if (g.h_act) (void)hipHostFree(g.h_act);
         if (g.h_heads) (void)hipHostFree(g.h_heads);
         if (g.ev) (void)hipEventDestroy(g.ev);
-        if (g.st) {
-            (void)hipStreamSynchronize(g.st);
-            (void)hipStreamDestroy(g.st);
-        }
+    }
+    for (hipStream_t st : b->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
     }
     delete b;
 }
@@ -1609,11 +1614,17 @@ gf_status init_batch(gf_ctx* c, BatchState& b, double* const* d_links, unsigned 
     hipEvent_t ready = nullptr;  // the caller's links are written on its stream
     GF_TRY_HIP(c, hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     gf_status rs = check_hip(c, hipEventRecord(ready, caller), "event record");
-    for (auto& g : b.g) {
-        if (rs != GF_OK) break;
-        rs = check_hip(c, hipStreamCreateWithFlags(&g.st, hipStreamNonBlocking), "stream create");
-        if (rs == GF_OK) rs = check_hip(c, hipEventCreateWithFlags(&g.ev, hipEventDisableTiming), "event create");
-        if (rs == GF_OK) rs = check_hip(c, hipStreamWaitEvent(g.st, ready, 0), "stream wait");
+    const int nst = std::min<int>(kBatchStreams, (int)b.g.size());
+    for (int i = 0; i < nst && rs == GF_OK; ++i) {
+        hipStream_t st = nullptr;
+        rs = check_hip(c, hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "stream create");
+        if (rs == GF_OK) b.streams.push_back(st);
+        if (rs == GF_OK) rs = check_hip(c, hipStreamWaitEvent(st, ready, 0), "stream wait");
+    }
+    for (size_t i = 0; i < b.g.size() && rs == GF_OK; ++i) {
+        BatchGroup& g = b.g[i];
+        g.st = b.streams[i % b.streams.size()];
+        rs = check_hip(c, hipEventCreateWithFlags(&g.ev, hipEventDisableTiming), "event create");
     }
     (void)hipEventDestroy(ready);
     if (rs != GF_OK) return rs;
