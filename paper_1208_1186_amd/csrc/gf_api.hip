@@ -927,9 +927,9 @@ double time_pass(gf_ctx* c, bool xy) {
     return ms;
 }
 
-// Traversals the loop kernel can take on this shape: z groupings (1 always), and 0 (blocks step through
-// t) when the (x, y, z) volume is a multiple of 64 sites, t has at least 4 steps and there are at least
-// 32 blocks.
+// Traversals the loop kernel can take on this shape: z groupings (1 always), 0 (blocks step through t)
+// when the (x, y, z) volume is a multiple of 64 sites, t has at least 4 steps and there are at least 32
+// blocks, and -1 (bricks) where the shape has a brick geometry.
 std::vector<int> zb_candidates(const Layout& L) {
     std::vector<int> v{1};
     if (L.bk_threads > 0) v.push_back(-1);
@@ -2432,8 +2432,9 @@ gf_status gf_set_loop_traversal(gf_ctx* c, int32_t z_group) {
     const std::vector<int> v = zb_candidates(a->L);
     if (std::find(v.begin(), v.end(), (int)z_group) == v.end())
         return fail(c, GF_EINVAL,
-                    "z_group must be 1, a divisor 2, 4, 8 of Nz below Nz (64 dividing Nx*Ny), or 0 (t-march: 64 "
-                    "dividing Nx*Ny*Nz, Nt >= 4, at least 32 blocks)");
+                    "z_group must be 1, a divisor 2, 4, 8 of Nz below Nz (64 dividing Nx*Ny), 0 (t-march: 64 "
+                    "dividing Nx*Ny*Nz, Nt >= 4, at least 32 blocks) or -1 (brick march, where the shape has "
+                    "bricks)");
     a->L.zb = z_group;
     return GF_OK;
 }
