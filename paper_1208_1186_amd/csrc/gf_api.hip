@@ -688,13 +688,13 @@ void launch_fused_t(gf_ctx* c, long long k) {
 
 template <typename T, int NE>
 void launch_pack_t(gf_ctx* c, const double* src) {
-    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, src, links_of<T, NE>(c),
-                       c->L.vol, sizeof(T) == 4 ? 1 : 0);
+    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk_fused), dim3(kSiteThreads), 0, c->st, src,
+                       links_of<T, NE>(c), c->L.vol, sizeof(T) == 4 ? 1 : 0);
 }
 template <typename T, int NE>
 void launch_unpack_t(gf_ctx* c, double* dst) {
-    hipLaunchKernelGGL((k_unpack_h<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, links_of<T, NE>(c),
-                       reinterpret_cast<const cx<T>*>(c->Hb[cur(c)]), c->geom, dst);
+    hipLaunchKernelGGL((k_unpack_h<T, NE>), dim3(c->L.nblk_fused), dim3(kSiteThreads), 0, c->st,
+                       links_of<T, NE>(c), reinterpret_cast<const cx<T>*>(c->Hb[cur(c)]), c->geom, dst);
 }
 
 #define GF_DISPATCH(c, fn, ...)                                                                  \

@@ -33,26 +33,36 @@ namespace gf {
 constexpr int kSiteThreads = 256;
 
 // ------------------------------------------------------------ layout kernels
-// Canonical links (complex double [s][mu][3][3]) -> SoA planes. If reunit is
-// set the matrix is first re-orthonormalised in double (used before rounding
-// to float).
+// Ingress and egress move 64 sites per block through LDS: the block reads or writes the sites' 64 x 576
+// contiguous bytes of canonical links with consecutive lanes on consecutive words, and lane (site, mu)
+// converts one link (mu is the wave's). A site's row in LDS is 73 doubles (72 + 1), so that the 64
+// lanes of a wave reading or writing their links do not meet on the same banks.
+constexpr int kIoSites = 64;
+constexpr int kIoRow = 73;
+
+// Canonical links (complex double [s][mu][3][3]) -> the tiled input links. If reunit is set the matrix is
+// first re-orthonormalised in double (used before rounding to float).
 template <typename T, int NE>
 __global__ void __launch_bounds__(kSiteThreads) k_pack(const double* __restrict__ canon, Links<T, NE> L,
                                                        int64_t vol, int reunit) {
-    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
-    if (s >= vol) return;
+    __shared__ double row[kIoSites * kIoRow];
+    const int64_t s0 = (int64_t)blockIdx.x * kIoSites;
+    const int nsite = (int)(vol - s0 < kIoSites ? vol - s0 : kIoSites);
+    const double* src = canon + s0 * 72;
+    for (int i = threadIdx.x; i < nsite * 72; i += kSiteThreads) row[(i / 72) * kIoRow + i % 72] = src[i];
+    __syncthreads();
+    const int q = threadIdx.x & (kIoSites - 1);
+    const int mu = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kIoSites);
+    if (q >= nsite) return;
+    const double* m = row + q * kIoRow + mu * 18;
+    su3<double> u;
 #pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
-        const double* src = canon + (s * 4 + mu) * 18;
-        su3<double> u;
+    for (int k = 0; k < 9; ++k) u.e[k / 3][k % 3] = {m[2 * k], m[2 * k + 1]};
+    if (reunit) reunitarize(u);
+    su3<T> v;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) u.e[k / 3][k % 3] = {src[2 * k], src[2 * k + 1]};
-        if (reunit) reunitarize(u);
-        su3<T> v;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) v.e[k / 3][k % 3] = {(T)u.e[k / 3][k % 3].re, (T)u.e[k / 3][k % 3].im};
-        L.store(mu, s, v);
-    }
+    for (int k = 0; k < 9; ++k) v.e[k / 3][k % 3] = {(T)u.e[k / 3][k % 3].re, (T)u.e[k / 3][k % 3].im};
+    L.store(mu, s0 + q, v);
 }
 
 // Canonical matrix field (complex double [s][3][3]) -> four packed fields, times scale.
@@ -145,17 +155,21 @@ __device__ __forceinline__ su3<double> rows_at_fp64(const cx<T>* __restrict__ G,
 
 // Egress: the current links U_mu(x) = H(x) U0_mu(x) H(x+mu)^dag -> canonical links (complex double
 // [s][mu][3][3]), formed in double from the stored factors (float factors promoted exactly); with
-// two-row storage rows 1-2 are formed and row 3 is rebuilt from them, as for the stored links.
+// two-row storage rows 1-2 are formed and row 3 is rebuilt from them, as for the stored links. Lane
+// (site, mu) forms one link; the block writes its 64 sites' links from LDS as one contiguous run.
 template <typename T, int NE>
 __global__ void __launch_bounds__(kSiteThreads) k_unpack_h(Links<T, NE> U0, const cx<T>* __restrict__ H, Geom g,
                                                            double* __restrict__ canon) {
-    const int64_t s = (int64_t)blockIdx.x * kSiteThreads + threadIdx.x;
-    if (s >= g.vol) return;
-    int c[4];
-    site_coords(g, s, c);
-    const su3<double> h0 = rows_at_fp64(H, s);
-#pragma unroll
-    for (int mu = 0; mu < 4; ++mu) {
+    __shared__ double row[kIoSites * kIoRow];
+    const int64_t s0 = (int64_t)blockIdx.x * kIoSites;
+    const int nsite = (int)(g.vol - s0 < kIoSites ? g.vol - s0 : kIoSites);
+    const int q = threadIdx.x & (kIoSites - 1);
+    const int mu = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kIoSites);
+    if (q < nsite) {
+        const int64_t s = s0 + q;
+        int c[4];
+        site_coords(g, s, c);
+        const su3<double> h0 = rows_at_fp64(H, s);
         su3<double> u;
 #pragma unroll
         for (int k = 0; k < NE; ++k) {
@@ -171,13 +185,16 @@ __global__ void __launch_bounds__(kSiteThreads) k_unpack_h(Links<T, NE> U0, cons
         } else {
             v = mul_adj<double, 3>(mul(h0, u), h1);
         }
-        double* dst = canon + (s * 4 + mu) * 18;
+        double* m = row + q * kIoRow + mu * 18;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            dst[2 * k] = v.e[k / 3][k % 3].re;
-            dst[2 * k + 1] = v.e[k / 3][k % 3].im;
+            m[2 * k] = v.e[k / 3][k % 3].re;
+            m[2 * k + 1] = v.e[k / 3][k % 3].im;
         }
     }
+    __syncthreads();
+    double* dst = canon + s0 * 72;
+    for (int i = threadIdx.x; i < nsite * 72; i += kSiteThreads) dst[i] = row[(i / 72) * kIoRow + i % 72];
 }
 
 // ------------------------------------------------------------ reductions
