@@ -688,8 +688,8 @@ void launch_fused_t(gf_ctx* c, long long k) {
 
 template <typename T, int NE>
 void launch_pack_t(gf_ctx* c, const double* src) {
-    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk_fused), dim3(kSiteThreads), 0, c->st, src,
-                       links_of<T, NE>(c), c->L.vol, sizeof(T) == 4 ? 1 : 0);
+    hipLaunchKernelGGL((k_pack<T, NE>), dim3(c->L.nblk), dim3(kSiteThreads), 0, c->st, src, links_of<T, NE>(c),
+                       c->L.vol, sizeof(T) == 4 ? 1 : 0);
 }
 template <typename T, int NE>
 void launch_unpack_t(gf_ctx* c, double* dst) {
