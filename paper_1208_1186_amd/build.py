@@ -8,12 +8,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgf.so")
 SOURCES = ["gf_api.hip", "gf_wilson_api.hip", "gf_mc_api.hip"]
-HEADERS = ["gf_device.hpp", "gf_fft.hpp", "gf_fft_ct.hpp", "gf_kernels.hpp", "gf_learn.hpp", "gf_wilson.hpp", "gf_mc.hpp"]
+HEADERS = ["gf_device.hpp", "gf_fft.hpp", "gf_fft_ct.hpp", "gf_fft_reg.hpp", "gf_kernels.hpp", "gf_batch.hpp",
+           "gf_learn.hpp", "gf_wilson.hpp", "gf_mc.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
-    # Packed FP32 instructions stay off (they are never emitted by this build).
+    # Packed FP32 arithmetic stays off: float kernels use single-lane FP32 instructions only.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
