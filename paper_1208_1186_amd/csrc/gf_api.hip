@@ -440,11 +440,13 @@ const cx<T>* twp(gf_ctx* c, int d) {
     X(16, 16, 8) X(24, 24, 1) X(24, 24, 2) X(24, 24, 4) X(32, 32, 1) X(32, 32, 2) X(32, 32, 4) X(48, 48, 1)    \
     X(48, 48, 2)
 #define GF_ZT_CASES_F64(X)                                                                                     \
-    X(8, 8, 4) X(8, 8, 8) X(12, 12, 4) X(16, 16, 4) X(16, 16, 8) X(16, 16, 16) X(24, 8, 8) X(32, 4, 8)         \
-    X(32, 4, 16) X(48, 8, 8) X(48, 8, 16) X(32, 32, 2) X(32, 32, 4) X(32, 64, 2)
+    X(8, 8, 4) X(8, 8, 8) X(12, 12, 2) X(12, 12, 4) X(16, 16, 4) X(16, 16, 8) X(16, 16, 16) X(24, 8, 4)        \
+    X(24, 8, 8) X(32, 4, 4) X(32, 4, 8) X(32, 4, 16) X(48, 8, 2) X(48, 8, 4) X(48, 8, 8) X(48, 8, 16)         \
+    X(32, 32, 2) X(32, 32, 4) X(32, 64, 2)
 #define GF_ZT_CASES_F32(X)                                                                                     \
-    X(8, 8, 8) X(12, 12, 4) X(16, 16, 8) X(16, 16, 16) X(24, 8, 8) X(32, 4, 16) X(32, 4, 32) X(48, 8, 8)       \
-    X(48, 8, 16) X(32, 32, 4) X(32, 32, 8) X(32, 64, 4)
+    X(8, 8, 4) X(8, 8, 8) X(12, 12, 4) X(16, 16, 4) X(16, 16, 8) X(16, 16, 16) X(24, 8, 4) X(24, 8, 8)        \
+    X(32, 4, 8) X(32, 4, 16) X(32, 4, 32) X(48, 8, 4) X(48, 8, 8) X(48, 8, 16) X(32, 32, 4) X(32, 32, 8)      \
+    X(32, 64, 2) X(32, 64, 4)
 #define GF_GAUGE_CASES(X) X(8, 8) X(12, 12) X(16, 16) X(24, 24) X(32, 32) X(48, 48)
 
 bool generic_fft(const gf_ctx* c) { return (c->p.flags & (GF_FLAG_GENERIC_FFT | GF_FLAG_BATCH_FUSED)) != 0; }
