@@ -491,6 +491,7 @@ bool launch_zt_ct(gf_ctx* c, void* Z, T coef, int no_fa, int force, const T* mta
         GF_ZT_REG_F32(GF_X)
     }
 #undef GF_X
+    if (L.n[0] > kZtMaxXY || L.n[1] > kZtMaxXY) return false;
 #define GF_X(A, B, BB)                                                                                     \
     if (L.n[2] == A && L.n[3] == B && L.bx == BB) {                                                        \
         hipLaunchKernelGGL((k_fft_zt_ct<T, A, B, BB>), dim3(4 * L.n[1] * (L.n[0] / BB), c->nact),           \

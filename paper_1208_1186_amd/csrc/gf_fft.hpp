@@ -3,7 +3,8 @@
 // A length-N transform (N = 2^a 3^b) is a sequence of radix-R stages. With
 // p the product of the radices already applied and m = N/R, butterfly i of a
 // row reads x[i + j*m] (j < R), multiplies input j by W_{pR}^{j*(i mod p)},
-// takes an R-point DFT and writes output j to y[(i - i mod p)*R + i mod p + j*p].
+// takes an R-point DFT and writes output j to y[(i - i mod p)*R + i mod p + j*p]
+// (the first stage, p = 1, has no twiddles: they are all 1).
 // The result comes out in natural order (self-sorting). A stage works in
 // place: every thread first loads all its butterflies into registers, the
 // block synchronises, then every thread writes its outputs.
@@ -100,11 +101,13 @@ __device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int N, in
 #pragma unroll
             for (int j = 0; j < R; ++j) v[it][j] = buf[base + (i + j * m) * es];
             obase[it] = base + ((i - k) * R + k) * es;
+            if (p > 1) {  // the first stage's twiddles are all 1
 #pragma unroll
-            for (int j = 1; j < R; ++j) {
-                cx<T> t = tw[j * k * twstep];
-                if (INV) t.im = -t.im;
-                v[it][j] = cmul(v[it][j], t);
+                for (int j = 1; j < R; ++j) {
+                    cx<T> t = tw[j * k * twstep];
+                    if (INV) t.im = -t.im;
+                    v[it][j] = cmul(v[it][j], t);
+                }
             }
         }
     }
@@ -201,52 +204,118 @@ struct Rows {
     static constexpr int nrows = NROWS, es = ES, n0 = N0, s0 = S0, s1 = S1;
 };
 
+// Where a stage reads its inputs and puts its outputs: element e of row b. The LDS forms address
+// row b at (b % n0)*s0 + (b / n0)*s1 with elements es apart.
+template <class RW, typename T>
+struct LdsIo {
+    cx<T>* buf;
+    static constexpr bool lds_in = true, lds_out = true;
+    __device__ __forceinline__ int at(int b, int e) const {
+        return (b % RW::n0) * RW::s0 + (b / RW::n0) * RW::s1 + e * RW::es;
+    }
+    __device__ __forceinline__ cx<T> ld(int b, int e) const { return buf[at(b, e)]; }
+    __device__ __forceinline__ void st(int b, int e, cx<T> v) const { buf[at(b, e)] = v; }
+};
+
+// One radix-R stage in three steps, on the butterflies thread tid takes (PER of them): load the
+// inputs of each from IN, multiply them by the twiddles, then take the R-point DFTs and put the
+// outputs to OUT.
+template <int N, int R, class RW, int NT>
+struct StageShape {
+    static constexpr int M = N / R, ITEMS = RW::nrows * M, PER = (ITEMS + NT - 1) / NT;
+    __device__ __forceinline__ static bool valid(int tid, int it) { return ITEMS % NT == 0 || tid + it * NT < ITEMS; }
+    __device__ __forceinline__ static int row(int tid, int it) { return (tid + it * NT) % RW::nrows; }
+    __device__ __forceinline__ static int item(int tid, int it) { return (tid + it * NT) / RW::nrows; }
+};
+
+// A thread's butterfly inputs for one stage.
+template <int N, int R, class RW, int NT, typename T>
+using StageRegs = cx<T>[StageShape<N, R, RW, NT>::PER][R];
+
+template <int N, int R, class RW, int NT, typename T, class IN>
+__device__ __forceinline__ void stage_load(const IN& in, StageRegs<N, R, RW, NT, T>& v, int tid) {
+    using SS = StageShape<N, R, RW, NT>;
+#pragma unroll
+    for (int it = 0; it < SS::PER; ++it) {
+        if (SS::valid(tid, it)) {
+            const int b = SS::row(tid, it), i = SS::item(tid, it);
+#pragma unroll
+            for (int j = 0; j < R; ++j) v[it][j] = in.ld(b, i + j * SS::M);
+        }
+    }
+}
+
 template <int N, int R, int P, class RW, int NT, typename T, bool INV>
-__device__ __forceinline__ void fft_stage_ct(cx<T>* buf, const cx<T>* tw) {
-    constexpr int M = N / R;
-    constexpr int ITEMS = RW::nrows * M;
-    constexpr int PER = (ITEMS + NT - 1) / NT;
-    constexpr int TWSTEP = N / (P * R);
-    cx<T> v[PER][R];
-    int ob[PER];
+__device__ __forceinline__ void stage_twiddle(const cx<T>* tw, StageRegs<N, R, RW, NT, T>& v, int tid) {
+    using SS = StageShape<N, R, RW, NT>;
+    if constexpr (P > 1) {  // the first stage's twiddles are all 1
+        constexpr int TWSTEP = N / (P * R);
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
-        const int w = threadIdx.x + it * NT;
-        if (ITEMS % NT == 0 || w < ITEMS) {
-            const int b = w % RW::nrows, i = w / RW::nrows;
-            const int base = (b % RW::n0) * RW::s0 + (b / RW::n0) * RW::s1;
-            const int k = i % P;
+        for (int it = 0; it < SS::PER; ++it) {
+            if (SS::valid(tid, it)) {
+                const int k = SS::item(tid, it) % P;
 #pragma unroll
-            for (int j = 0; j < R; ++j) v[it][j] = buf[base + (i + j * M) * RW::es];
-            ob[it] = base + ((i - k) * R + k) * RW::es;
-#pragma unroll
-            for (int j = 1; j < R; ++j) {
-                cx<T> t = tw[j * k * TWSTEP];
-                if (INV) t.im = -t.im;
-                v[it][j] = cmul(v[it][j], t);
+                for (int j = 1; j < R; ++j) {
+                    cx<T> t = tw[j * k * TWSTEP];
+                    if (INV) t.im = -t.im;
+                    v[it][j] = cmul(v[it][j], t);
+                }
             }
         }
     }
-    __syncthreads();
+}
+
+template <int N, int R, int P, class RW, int NT, typename T, bool INV, class OUT>
+__device__ __forceinline__ void stage_store(StageRegs<N, R, RW, NT, T>& v, const OUT& out, int tid) {
+    using SS = StageShape<N, R, RW, NT>;
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
-        const int w = threadIdx.x + it * NT;
-        if (ITEMS % NT == 0 || w < ITEMS) {
+    for (int it = 0; it < SS::PER; ++it) {
+        if (SS::valid(tid, it)) {
+            const int b = SS::row(tid, it), i = SS::item(tid, it);
+            const int k = i % P;
             dft_small<R, T, INV>(v[it]);
 #pragma unroll
-            for (int j = 0; j < R; ++j) buf[ob[it] + j * P * RW::es] = v[it][j];
+            for (int j = 0; j < R; ++j) out.st(b, (i - k) * R + k + j * P, v[it][j]);
         }
     }
-    __syncthreads();
+}
+
+// The whole stage. A block barrier separates the reads from the writes only when both are in
+// LDS, and follows the writes only when they go to LDS.
+template <int N, int R, int P, class RW, int NT, typename T, bool INV, class IN, class OUT>
+__device__ __forceinline__ void fft_stage_io(const cx<T>* tw, const IN& in, const OUT& out, int tid) {
+    StageRegs<N, R, RW, NT, T> v;
+    stage_load<N, R, RW, NT, T>(in, v, tid);
+    stage_twiddle<N, R, P, RW, NT, T, INV>(tw, v, tid);
+    if constexpr (IN::lds_in && OUT::lds_out) __syncthreads();
+    stage_store<N, R, P, RW, NT, T, INV>(v, out, tid);
+    if constexpr (OUT::lds_out) __syncthreads();
+}
+
+// All stages of a batch of rows: the first stage reads from FIRST, the last writes to LAST, the
+// others work in LDS.
+template <int N, int S, int P, class RW, int NT, typename T, bool INV, class FIRST, class LAST>
+__device__ __forceinline__ void fft_rows_io(cx<T>* buf, const cx<T>* tw, const FIRST& first, const LAST& last,
+                                            int tid) {
+    if constexpr (S < ct_nst(N)) {
+        constexpr int R = ct_rad(N, S);
+        const LdsIo<RW, T> lds{buf};
+        if constexpr (S == 0 && S + 1 == ct_nst(N))
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, first, last, tid);
+        else if constexpr (S == 0)
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, first, lds, tid);
+        else if constexpr (S + 1 == ct_nst(N))
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, lds, last, tid);
+        else
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, lds, lds, tid);
+        fft_rows_io<N, S + 1, P * R, RW, NT, T, INV>(buf, tw, first, last, tid);
+    }
 }
 
 template <int N, int S, int P, class RW, int NT, typename T, bool INV>
 __device__ __forceinline__ void fft_rows_ct(cx<T>* buf, const cx<T>* tw) {
-    if constexpr (S < ct_nst(N)) {
-        constexpr int R = ct_rad(N, S);
-        fft_stage_ct<N, R, P, RW, NT, T, INV>(buf, tw);
-        fft_rows_ct<N, S + 1, P * R, RW, NT, T, INV>(buf, tw);
-    }
+    const LdsIo<RW, T> lds{buf};
+    fft_rows_io<N, S, P, RW, NT, T, INV>(buf, tw, lds, lds, threadIdx.x);
 }
 
 }  // namespace gf

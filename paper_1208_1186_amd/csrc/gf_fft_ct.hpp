@@ -15,6 +15,15 @@ constexpr int ct_threads(int elems, int ept) {
     return r < 64 ? 64 : (r > 1024 ? 1024 : r);
 }
 
+// Row b of the y transforms of a block's planes is column b % NX of plane b / NX; the last y
+// stage writes element e (its y) straight to memory, a run of NX consecutive sites per plane row.
+template <typename T, int NX, int NY>
+struct XyOut {
+    cx<T>* gd;
+    static constexpr bool lds_in = false, lds_out = false;
+    __device__ __forceinline__ void st(int b, int e, cx<T> v) const { gd[(b / NX) * (NX * NY) + e * NX + b % NX] = v; }
+};
+
 // (x, y) pass over G single-field planes per block, src -> dst.
 template <typename T, int NX, int NY, int G, bool INV>
 __global__ void __launch_bounds__(ct_threads(G * NX * NY, 8))
@@ -51,15 +60,56 @@ __global__ void __launch_bounds__(ct_threads(G * NX * NY, 8))
     }
     __syncthreads();
     fft_rows_ct<NX, 0, 1, Rows<G * NY, 1, G * NY, RS, 0>, NT, T, INV>(buf, twx);
-    fft_rows_ct<NY, 0, 1, Rows<G * NX, RS, NX, 1, NY * RS>, NT, T, INV>(buf, twy);
-#pragma unroll
-    for (int e0 = 0; e0 < E; e0 += NT) {
-        const int e = e0 + threadIdx.x;
-        if (E % NT == 0 || e < E) gd[e] = buf[(e / NX) * RS + e % NX];
-    }
+    using RY = Rows<G * NX, RS, NX, 1, NY * RS>;
+    fft_rows_io<NY, 0, 1, RY, NT, T, INV>(buf, twy, LdsIo<RY, T>{buf}, XyOut<T, NX, NY>{gd}, threadIdx.x);
 }
 
-// (z, t) pass with the filter, BX x columns per block, in place.
+// Global side of the (z, t) pass: row b of the z transforms is the column (x0 + b % BX, y) at
+// t = b / BX, element e its z; the block's first z stage reads from here and its last inverse z
+// stage writes back here.
+template <typename T, int NZ, int BX>
+struct ZtGlobal {
+    cx<T>* gp;
+    int pstep;
+    static constexpr bool lds_in = false, lds_out = false;
+    __device__ __forceinline__ int at(int b, int e) const { return b % BX + (e + NZ * (b / BX)) * pstep; }
+    __device__ __forceinline__ cx<T> ld(int b, int e) const { return gp[at(b, e)]; }
+    __device__ __forceinline__ void st(int b, int e, cx<T> v) const { gp[at(b, e)] = v; }
+};
+
+// Output of the last forward t stage: the spectrum at (x0 + xo, y, z, t) (row b = z*BX + xo,
+// element e = t) is recorded when asked, multiplied by the filter and put back in LDS. The sin^2
+// tables are in LDS (filled before the block's first barrier, read only after it).
+template <typename T, int NZ, int BX, int TSP>
+struct ZtFilter {
+    cx<T>* buf;
+    cx<T>* spec;  // spectrum record at the block's first column, or null
+    const T *sx, *sy, *sz, *stt;  // sin^2 tables along x (from x0), y, z and t
+    const T* mtab;
+    TupleGeom tg;
+    T coef;
+    int no_fa, x0, y, pstep;
+    static constexpr bool lds_in = true, lds_out = true;
+    __device__ __forceinline__ void st(int b, int e, cx<T> v) const {
+        const int xo = b % BX, z = b / BX, t = e;
+        if (spec) spec[xo + (z + NZ * t) * pstep] = v;
+        T mult;
+        if (mtab) {
+            mult = mtab[tuple_index(tg, x0 + xo, y, z, t)];
+        } else {
+            const T p2 = sx[xo] + sy[y] + sz[z] + stt[t];
+            mult = p2 > T(0) ? (no_fa ? coef : coef / p2) : T(0);
+        }
+        buf[b + e * TSP] = cscale(v, mult);
+    }
+};
+
+// Largest x or y extent the compile-time (z, t) passes take (their sin^2 tables sit in LDS).
+constexpr int kZtMaxXY = 64;
+
+// (z, t) pass with the filter, BX x columns per block, in place. The first z stage reads the
+// columns from memory and the last inverse z stage writes them back; the filter is applied as the
+// last forward t stage puts its outputs in LDS.
 template <typename T, int NZ, int NTT, int BX>
 __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     k_fft_zt_ct(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, const cx<T>* __restrict__ twgz,
@@ -71,6 +121,8 @@ __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     // slots; a pitch of NZ*BX + 1 put the lanes of neighbouring t rows on the same slots when BX > 1
     // (measured: the pass 2-3 us faster at 32^4 and 48^3x8).
     constexpr int TSP = NZ * BX + BX, E = BX * NZ * NTT, NT = ct_threads(E, 8);
+    using RZ = Rows<NTT * BX, BX, BX, 1, TSP>;
+    using RT = Rows<NZ * BX, TSP, NZ * BX, 1, 0>;
     {
         const size_t bo = boff(bt);
         Z = bshift(Z, bo);
@@ -81,61 +133,31 @@ __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     }
     if (!force && ctl->done) return;
     __shared__ cx<T> twz[NZ], twt[NTT], buf[NTT * TSP];
+    __shared__ T s2[2 * kZtMaxXY + NZ + NTT];  // sin^2 along x, y, z, t
     for (int i = threadIdx.x; i < NZ; i += NT) twz[i] = twgz[i];
     for (int i = threadIdx.x; i < NTT; i += NT) twt[i] = twgt[i];
+    for (int i = threadIdx.x; i < nx; i += NT) s2[i] = sin2[i];
+    for (int i = threadIdx.x; i < ny; i += NT) s2[kZtMaxXY + i] = sin2[nx + i];
+    for (int i = threadIdx.x; i < NZ + NTT; i += NT) s2[2 * kZtMaxXY + i] = sin2[nx + ny + i];
     const int nxb = nx / BX;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int xb = blk % nxb;
     const int rest = blk / nxb;
     const int y = rest % ny, f = rest / ny;
     const int x0 = xb * BX;
-    cx<T>* gp = Z + (size_t)f * zps + x0 + (size_t)nx * y;
-    const size_t pstep = (size_t)nx * ny;
-#pragma unroll
-    for (int e0 = 0; e0 < E; e0 += NT) {
-        const int e = e0 + threadIdx.x;
-        if (E % NT == 0 || e < E) {
-            const int xo = e % BX, zt = e / BX;
-            buf[(zt / NZ) * TSP + (zt % NZ) * BX + xo] = gp[xo + zt * pstep];
-        }
-    }
-    __syncthreads();
-    fft_rows_ct<NZ, 0, 1, Rows<NTT * BX, BX, BX, 1, TSP>, NT, T, false>(buf, twz);
-    fft_rows_ct<NTT, 0, 1, Rows<NZ * BX, TSP, NZ * BX, 1, 0>, NT, T, false>(buf, twt);
-    const T* sx = sin2;
-    const T* sy = sin2 + nx;
-    const T* sz = sy + ny;
-    const T* st = sz + NZ;
-    const T sxy = sy[y];
-#pragma unroll
-    for (int e0 = 0; e0 < E; e0 += NT) {
-        const int e = e0 + threadIdx.x;
-        if (E % NT == 0 || e < E) {
-            const int xo = e % BX, zt = e / BX;
-            const int z = zt % NZ, t = zt / NZ;
-            const int li = t * TSP + z * BX + xo;
-            if (spec) spec[xo + zt * pstep + (gp - Z)] = buf[li];
-            T mult;
-            if (mtab) {
-                mult = mtab[tuple_index(tg, x0 + xo, y, z, t)];
-            } else {
-                const T p2 = sx[x0 + xo] + sxy + sz[z] + st[t];
-                mult = p2 > T(0) ? (no_fa ? coef : coef / p2) : T(0);
-            }
-            buf[li] = cscale(buf[li], mult);
-        }
-    }
-    __syncthreads();
-    fft_rows_ct<NTT, 0, 1, Rows<NZ * BX, TSP, NZ * BX, 1, 0>, NT, T, true>(buf, twt);
-    fft_rows_ct<NZ, 0, 1, Rows<NTT * BX, BX, BX, 1, TSP>, NT, T, true>(buf, twz);
-#pragma unroll
-    for (int e0 = 0; e0 < E; e0 += NT) {
-        const int e = e0 + threadIdx.x;
-        if (E % NT == 0 || e < E) {
-            const int xo = e % BX, zt = e / BX;
-            gp[xo + zt * pstep] = buf[(zt / NZ) * TSP + (zt % NZ) * BX + xo];
-        }
-    }
+    const size_t goff = (size_t)f * zps + x0 + (size_t)nx * y;
+    const int pstep = nx * ny;
+    const int tid = threadIdx.x;
+    const ZtGlobal<T, NZ, BX> col{Z + goff, pstep};
+    const LdsIo<RZ, T> lds_z{buf};
+    const LdsIo<RT, T> lds_t{buf};
+    const ZtFilter<T, NZ, BX, TSP> filt{buf, spec ? spec + goff : nullptr, s2 + x0, s2 + kZtMaxXY, s2 + 2 * kZtMaxXY,
+                                        s2 + 2 * kZtMaxXY + NZ, mtab, tg, coef, no_fa,
+                                        x0, y, pstep};
+    fft_rows_io<NZ, 0, 1, RZ, NT, T, false>(buf, twz, col, lds_z, tid);
+    fft_rows_io<NTT, 0, 1, RT, NT, T, false>(buf, twt, lds_t, filt, tid);
+    fft_rows_io<NTT, 0, 1, RT, NT, T, true>(buf, twt, lds_t, lds_t, tid);
+    fft_rows_io<NZ, 0, 1, RZ, NT, T, true>(buf, twz, lds_z, col, tid);
 }
 
 // Inverse (x, y) pass of the four fields of one (z, t) plane, then g and the update of the stored
