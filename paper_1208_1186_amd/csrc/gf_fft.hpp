@@ -292,30 +292,78 @@ __device__ __forceinline__ void fft_stage_io(const cx<T>* tw, const IN& in, cons
     if constexpr (OUT::lds_out) __syncthreads();
 }
 
+// Radix of stage S of a length-N transform whose radices are taken in the order ct_rad gives
+// (REV false) or in the reverse order (REV true). Either order is a valid Stockham sequence.
+template <int N, bool REV>
+constexpr int stage_radix(int S) {
+    return ct_rad(N, REV ? ct_nst(N) - 1 - S : S);
+}
+
+// Stages S .. SEND-1 of a batch of rows (P the product of the radices before S): stage S0 (the
+// first of the range) reads from FIRST, stage SEND-1 writes to LAST, the others work in LDS.
+template <int N, int S0, int S, int SEND, int P, bool REV, class RW, int NT, typename T, bool INV, class FIRST,
+          class LAST>
+__device__ __forceinline__ void fft_stages_io(cx<T>* buf, const cx<T>* tw, const FIRST& first, const LAST& last,
+                                              int tid) {
+    if constexpr (S < SEND) {
+        constexpr int R = stage_radix<N, REV>(S);
+        const LdsIo<RW, T> lds{buf};
+        if constexpr (S == S0 && S + 1 == SEND)
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, first, last, tid);
+        else if constexpr (S == S0)
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, first, lds, tid);
+        else if constexpr (S + 1 == SEND)
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, lds, last, tid);
+        else
+            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, lds, lds, tid);
+        fft_stages_io<N, S0, S + 1, SEND, P * R, REV, RW, NT, T, INV>(buf, tw, first, last, tid);
+    }
+}
+
 // All stages of a batch of rows: the first stage reads from FIRST, the last writes to LAST, the
 // others work in LDS.
 template <int N, int S, int P, class RW, int NT, typename T, bool INV, class FIRST, class LAST>
 __device__ __forceinline__ void fft_rows_io(cx<T>* buf, const cx<T>* tw, const FIRST& first, const LAST& last,
                                             int tid) {
-    if constexpr (S < ct_nst(N)) {
-        constexpr int R = ct_rad(N, S);
-        const LdsIo<RW, T> lds{buf};
-        if constexpr (S == 0 && S + 1 == ct_nst(N))
-            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, first, last, tid);
-        else if constexpr (S == 0)
-            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, first, lds, tid);
-        else if constexpr (S + 1 == ct_nst(N))
-            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, lds, last, tid);
-        else
-            fft_stage_io<N, R, P, RW, NT, T, INV>(tw, lds, lds, tid);
-        fft_rows_io<N, S + 1, P * R, RW, NT, T, INV>(buf, tw, first, last, tid);
-    }
+    fft_stages_io<N, S, S, ct_nst(N), P, false, RW, NT, T, INV>(buf, tw, first, last, tid);
 }
 
 template <int N, int S, int P, class RW, int NT, typename T, bool INV>
 __device__ __forceinline__ void fft_rows_ct(cx<T>* buf, const cx<T>* tw) {
     const LdsIo<RW, T> lds{buf};
     fft_rows_io<N, S, P, RW, NT, T, INV>(buf, tw, lds, lds, threadIdx.x);
+}
+
+// Forward transform of a batch of rows in LDS, a per-element map F on the spectrum, and the
+// inverse transform back into LDS. The inverse takes the radices in the reverse order: its first
+// stage then reads exactly the elements the forward's last stage leaves in a thread's registers
+// (stage with p*R = N writes element i + j*p of its butterfly i, and the reversed first stage,
+// m = N/R = p, reads element i + j*m), so F and that stage run on those registers and the two
+// stages share one LDS exchange. F is called as F.apply(row, element, value).
+template <int N, class RW, int NT, typename T, class F>
+__device__ __forceinline__ void fft_rows_map_inverse(cx<T>* buf, const cx<T>* tw, const F& fmap, int tid) {
+    constexpr int NS = ct_nst(N), RL = ct_rad(N, NS - 1), PL = N / RL;
+    using SS = StageShape<N, RL, RW, NT>;
+    const LdsIo<RW, T> lds{buf};
+    fft_stages_io<N, 0, 0, NS - 1, 1, false, RW, NT, T, false>(buf, tw, lds, lds, tid);
+    StageRegs<N, RL, RW, NT, T> v;
+    stage_load<N, RL, RW, NT, T>(lds, v, tid);
+    stage_twiddle<N, RL, PL, RW, NT, T, false>(tw, v, tid);
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SS::PER; ++it) {
+        if (SS::valid(tid, it)) {
+            const int b = SS::row(tid, it), i = SS::item(tid, it);
+            dft_small<RL, T, false>(v[it]);
+#pragma unroll
+            for (int j = 0; j < RL; ++j) v[it][j] = fmap.apply(b, i + j * PL, v[it][j]);
+            dft_small<RL, T, true>(v[it]);
+#pragma unroll
+            for (int j = 0; j < RL; ++j) lds.st(b, i * RL + j, v[it][j]);
+        }
+    }
+    __syncthreads();
+    fft_stages_io<N, 1, 1, NS, RL, true, RW, NT, T, true>(buf, tw, lds, lds, tid);
 }
 
 }  // namespace gf

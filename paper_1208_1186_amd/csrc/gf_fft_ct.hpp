@@ -77,20 +77,18 @@ struct ZtGlobal {
     __device__ __forceinline__ void st(int b, int e, cx<T> v) const { gp[at(b, e)] = v; }
 };
 
-// Output of the last forward t stage: the spectrum at (x0 + xo, y, z, t) (row b = z*BX + xo,
-// element e = t) is recorded when asked, multiplied by the filter and put back in LDS. The sin^2
-// tables are in LDS (filled before the block's first barrier, read only after it).
-template <typename T, int NZ, int BX, int TSP>
+// The filter on the spectrum at (x0 + xo, y, z, t) (row b = z*BX + xo of the t transforms,
+// element e = t), which it records first when asked. The sin^2 tables are in LDS (filled before
+// the block's first barrier, read only after it).
+template <typename T, int NZ, int BX>
 struct ZtFilter {
-    cx<T>* buf;
     cx<T>* spec;  // spectrum record at the block's first column, or null
     const T *sx, *sy, *sz, *stt;  // sin^2 tables along x (from x0), y, z and t
     const T* mtab;
     TupleGeom tg;
     T coef;
     int no_fa, x0, y, pstep;
-    static constexpr bool lds_in = true, lds_out = true;
-    __device__ __forceinline__ void st(int b, int e, cx<T> v) const {
+    __device__ __forceinline__ cx<T> apply(int b, int e, cx<T> v) const {
         const int xo = b % BX, z = b / BX, t = e;
         if (spec) spec[xo + (z + NZ * t) * pstep] = v;
         T mult;
@@ -100,7 +98,7 @@ struct ZtFilter {
             const T p2 = sx[xo] + sy[y] + sz[z] + stt[t];
             mult = p2 > T(0) ? (no_fa ? coef : coef / p2) : T(0);
         }
-        buf[b + e * TSP] = cscale(v, mult);
+        return cscale(v, mult);
     }
 };
 
@@ -108,8 +106,8 @@ struct ZtFilter {
 constexpr int kZtMaxXY = 64;
 
 // (z, t) pass with the filter, BX x columns per block, in place. The first z stage reads the
-// columns from memory and the last inverse z stage writes them back; the filter is applied as the
-// last forward t stage puts its outputs in LDS.
+// columns from memory and the last inverse z stage writes them back; the filter and the first
+// inverse t stage work on the last forward t stage's registers.
 template <typename T, int NZ, int NTT, int BX>
 __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     k_fft_zt_ct(cx<T>* __restrict__ Z, size_t zps, int nx, int ny, const cx<T>* __restrict__ twgz,
@@ -150,18 +148,27 @@ __global__ void __launch_bounds__(ct_threads(BX * NZ * NTT, 8))
     const int tid = threadIdx.x;
     const ZtGlobal<T, NZ, BX> col{Z + goff, pstep};
     const LdsIo<RZ, T> lds_z{buf};
-    const LdsIo<RT, T> lds_t{buf};
-    const ZtFilter<T, NZ, BX, TSP> filt{buf, spec ? spec + goff : nullptr, s2 + x0, s2 + kZtMaxXY, s2 + 2 * kZtMaxXY,
+    const ZtFilter<T, NZ, BX> filt{spec ? spec + goff : nullptr, s2 + x0, s2 + kZtMaxXY, s2 + 2 * kZtMaxXY,
                                         s2 + 2 * kZtMaxXY + NZ, mtab, tg, coef, no_fa,
                                         x0, y, pstep};
     fft_rows_io<NZ, 0, 1, RZ, NT, T, false>(buf, twz, col, lds_z, tid);
-    fft_rows_io<NTT, 0, 1, RT, NT, T, false>(buf, twt, lds_t, filt, tid);
-    fft_rows_io<NTT, 0, 1, RT, NT, T, true>(buf, twt, lds_t, lds_t, tid);
+    fft_rows_map_inverse<NTT, RT, NT, T>(buf, twt, filt, tid);
     fft_rows_io<NZ, 0, 1, RZ, NT, T, true>(buf, twz, lds_z, col, tid);
 }
 
-// Inverse (x, y) pass of the four fields of one (z, t) plane, then g and the update of the stored
-// transform, Hout = reunitarize(g Hin) (rows 1-2); with Hin null, g itself goes to Hout.
+// Row b of the y transforms of one (z, t) plane's four fields is column b % NX of field b / NX;
+// the first y stage reads element e (its y) straight from memory, runs of NX consecutive sites.
+template <typename T, int NX>
+struct PlaneIn {
+    const cx<T>* q;  // the plane's first site in field 0
+    size_t zps;      // field stride
+    static constexpr bool lds_in = false, lds_out = false;
+    __device__ __forceinline__ cx<T> ld(int b, int e) const { return q[(size_t)(b / NX) * zps + e * NX + b % NX]; }
+};
+
+// Inverse (x, y) pass of the four fields of one (z, t) plane (y transforms first, read from
+// memory), then g and the update of the stored transform, Hout = reunitarize(g Hin) (rows 1-2);
+// with Hin null, g itself goes to Hout.
 constexpr int gauge_ept(int nx, int ny) { return 4 * nx * ny <= 8 * 1024 ? 8 : 16; }
 
 template <typename T, int NX, int NY>
@@ -188,17 +195,10 @@ __global__ void __launch_bounds__(ct_threads(4 * NX * NY, gauge_ept(NX, NY)))
     for (int i = threadIdx.x; i < NX; i += NT) twx[i] = twgx[i];
     for (int i = threadIdx.x; i < NY; i += NT) twy[i] = twgy[i];
     const size_t base = (size_t)xcd_remap(blockIdx.x, gridDim.x) * P;
-#pragma unroll
-    for (int e0 = 0; e0 < E; e0 += NT) {
-        const int e = e0 + threadIdx.x;
-        if (E % NT == 0 || e < E) {
-            const int f = e / P, r = e % P;
-            buf[f * PL + (r / NX) * RS + r % NX] = Q[(size_t)f * zps + base + r];
-        }
-    }
-    __syncthreads();
+    using RY = Rows<4 * NX, RS, NX, 1, PL>;
+    fft_rows_io<NY, 0, 1, RY, NT, T, true>(buf, twy, PlaneIn<T, NX>{Q + base, zps}, LdsIo<RY, T>{buf},
+                                           threadIdx.x);
     fft_rows_ct<NX, 0, 1, Rows<4 * NY, 1, 4 * NY, RS, 0>, NT, T, true>(buf, twx);
-    fft_rows_ct<NY, 0, 1, Rows<4 * NX, RS, NX, 1, PL>, NT, T, true>(buf, twy);
 #pragma unroll
     for (int r0 = 0; r0 < P; r0 += NT) {
         const int r = r0 + threadIdx.x;
