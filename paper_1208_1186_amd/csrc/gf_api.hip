@@ -436,8 +436,9 @@ const cx<T>* twp(gf_ctx* c, int d) {
 // (Nz, Nt, bx) for the (z, t) pass at each precision, (Nx, Ny) for the gauge pass.
 // Several entries per shape are the alternatives the autotuner times. 32 x 32 planes have no
 // one-plane (x, y) tiling: timed on its own it came out fastest (23 against 29 us at 32^4 in double)
-// and the autotuner kept it on most runs, but inside the loop, after the loop kernel, it took 34.5-35 us
-// against 30-31 us for two planes per block, whichever way the trials were ordered.
+// and the autotuner kept it on most runs, but inside the loop, after the loop kernel, it took 31 us
+// against 27 us for two planes per block (34.5-35 against 30-31 while one of its blocks also reduced
+// the loop kernel's partials), whichever way the trials were ordered.
 #define GF_XY_CASES(X)                                                                                         \
     X(8, 8, 8) X(8, 8, 16) X(8, 8, 32) X(12, 12, 4) X(12, 12, 8) X(12, 12, 16) X(16, 16, 2) X(16, 16, 4)       \
     X(16, 16, 8) X(24, 24, 1) X(24, 24, 2) X(24, 24, 4) X(32, 32, 2) X(32, 32, 4) X(48, 48, 1)                \
@@ -462,7 +463,7 @@ bool launch_xy_ct(gf_ctx* c, const void* src, void* dst, int force, bool loop_re
     const double2* part = loop_reduce ? c->part : nullptr;
 #define GF_X(A, B, GG)                                                                                          \
     if (L.n[0] == A && L.n[1] == B && L.G == GG) {                                                              \
-        hipLaunchKernelGGL((k_fft_xy_ct<T, A, B, GG, INV>), dim3(4 * nzt / GG, c->nact),                          \
+        hipLaunchKernelGGL((k_fft_xy_ct<T, A, B, GG, INV>), dim3(4 * nzt / GG + (part ? 1 : 0), c->nact),         \
                            dim3(ct_threads(GG * A * B, 8)), 0, c->st, s, cxp<T>(dst), L.ps, nzt, twp<T>(c, 0),  \
                            twp<T>(c, 1), c->ctl, force, part, L.nblk_fused, inv3v(c), inv12v(c), bt(c));       \
         return true;                                                                                            \

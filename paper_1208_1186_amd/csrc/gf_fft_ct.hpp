@@ -24,7 +24,7 @@ struct XyOut {
     __device__ __forceinline__ void st(int b, int e, cx<T> v) const { gd[(b / NX) * (NX * NY) + e * NX + b % NX] = v; }
 };
 
-// (x, y) pass over G single-field planes per block, src -> dst.
+// (x, y) pass over G single-field planes per block, src -> dst (one more block when part is set).
 template <typename T, int NX, int NY, int G, bool INV>
 __global__ void __launch_bounds__(ct_threads(G * NX * NY, 8))
     k_fft_xy_ct(const cx<T>* src, cx<T>* dst, size_t zps, int nzt, const cx<T>* __restrict__ twgx,
@@ -40,15 +40,18 @@ __global__ void __launch_bounds__(ct_threads(G * NX * NY, 8))
         ctl = bshift(ctl, bo);
         part = bshift(part, bo);
     }
-    if (part != nullptr && blockIdx.x == 0 && ctl->pending) {
-        reduce_partials(part, npart, inv3v, inv12v, ctl, 1);
-        __syncthreads();
+    // With part set, block 0 (dispatched first) only reduces the loop kernel's pending partials and
+    // the other blocks transform: a block that did both ended last on small tilings.
+    const int red = part != nullptr ? 1 : 0;
+    if (red && blockIdx.x == 0) {
+        if (ctl->pending) reduce_partials(part, npart, inv3v, inv12v, ctl, 1);
+        return;
     }
     if (!force && ctl->done) return;
     __shared__ cx<T> twx[NX], twy[NY], buf[G * NY * RS];
     for (int i = threadIdx.x; i < NX; i += NT) twx[i] = twgx[i];
     for (int i = threadIdx.x; i < NY; i += NT) twy[i] = twgy[i];
-    const int q0 = xcd_remap(blockIdx.x, gridDim.x) * G;
+    const int q0 = xcd_remap(blockIdx.x - red, gridDim.x - red) * G;
     const int f = q0 / nzt, zt0 = q0 - f * nzt;
     const size_t off = (size_t)f * zps + (size_t)zt0 * NX * NY;
     const cx<T>* gs = src + off;

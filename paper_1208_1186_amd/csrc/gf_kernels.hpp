@@ -206,15 +206,15 @@ __device__ __forceinline__ void reduce_partials(const double2* __restrict__ part
     __shared__ double ra[256], rb[256];
     for (int vt = threadIdx.x; vt < 256; vt += blockDim.x) {
         double a = 0.0, b = 0.0;
-        for (int i0 = vt; i0 < n; i0 += 8 * 256) {
-            double2 p[8];
+        for (int i0 = vt; i0 < n; i0 += 16 * 256) {
+            double2 p[16];  // 16 loads in flight: the chain waits on memory latency, not on the adds
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < 16; ++k) {
                 const int i = i0 + k * 256;
                 p[k] = i < n ? part[i] : make_double2(0.0, 0.0);
             }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < 16; ++k) {
                 a += p[k].x;
                 b += p[k].y;
             }
