@@ -64,9 +64,11 @@ PMC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles
 KERNEL_SOURCES = ["paper_1208_1186_amd/csrc/gf_device.hpp", "paper_1208_1186_amd/csrc/gf_kernels.hpp"]
 
 
-def counted_traffic(prec, dims):
+def counted_traffic(prec, dims, traversal=None):
     """HBM bytes per launch of the loop kernel from the committed rocprofv3 FETCH/WRITE passes, scaled by
-    the copy calibration; None if there is no such profile or the kernel sources changed since."""
+    the copy calibration; None if there is no such profile or the kernel sources changed since. The
+    traversal's own counter lines (`fetch_kib_per_dispatch_z<traversal>:`) are taken when the profile
+    has them, else the generic ones."""
     import hashlib
     import re
     path = PMC_PROFILE.format(prec=prec, dims="x".join(str(d) for d in dims))
@@ -81,7 +83,10 @@ def counted_traffic(prec, dims):
         return None
     vals = {}
     for key in ["fetch_scale", "write_scale", "fetch_kib_per_dispatch", "write_kib_per_dispatch"]:
-        m = re.search(rf"^{key}:\s*([0-9.eE+-]+)", text, re.M)
+        m = None
+        if traversal is not None and key.endswith("per_dispatch"):
+            m = re.search(rf"^{key}_z{traversal}:\s*([0-9.eE+-]+)", text, re.M)
+        m = m or re.search(rf"^{key}:\s*([0-9.eE+-]+)", text, re.M)
         if not m:
             return None
         vals[key] = float(m.group(1))
@@ -603,7 +608,7 @@ def main():
     avg_dom = ms_dom / n_dom
     by_dom = kernel_bytes(dom, vol, L, S, nblk)
     achieved = round(by_dom / (avg_dom * 1e-3) / 1e9, 1)
-    traffic = counted_traffic(prec, dims) if dom == "update_measure" else None
+    traffic = counted_traffic(prec, dims, TILINGS.get(prec, (None,) * 3)[2]) if dom == "update_measure" else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "bytes_per_launch": by_dom, "avg_launch_ms": round(avg_dom, 5), "launches_timed": n_dom}

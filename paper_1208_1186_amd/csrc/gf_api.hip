@@ -546,7 +546,8 @@ void launch_xy(gf_ctx* c, const void* src, void* dst, int force, bool loop_reduc
         tstop(c);
         return;
     }
-    hipLaunchKernelGGL((k_fft_xy<T, kEPT, INV>), dim3(4 * nzt / L.G, c->nact), dim3(L.thrA), L.ldsA, c->st,
+    hipLaunchKernelGGL((k_fft_xy<T, kEPT, INV>), dim3(4 * nzt / L.G + (loop_reduce ? 1 : 0), c->nact), dim3(L.thrA),
+                       L.ldsA, c->st,
                        reinterpret_cast<const cx<T>*>(src), cxp<T>(dst), L.ps, L.n[0], L.n[1], nzt, L.G, L.rs,
                        c->plan[0], c->plan[1], twp<T>(c, 0), twp<T>(c, 1), c->ctl, force,
                        loop_reduce ? c->part : nullptr, L.nblk_fused, inv3v(c), inv12v(c), bt(c));

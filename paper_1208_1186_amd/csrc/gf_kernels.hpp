@@ -960,8 +960,14 @@ __global__ void __launch_bounds__(1024) k_fft_xy(const cx<T>* src, cx<T>* dst, s
         ctl = bshift(ctl, bo);
         part = bshift(part, bo);
     }
-    fft_xy_body<T, EPT, INV>(src, dst, zps, nx, ny, nzt, G, rs, px, py, twgx, twgy, ctl, force, part, npart, inv3v,
-                             inv12v, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x == 0);
+    // With part set, block 0 (dispatched first) only reduces the pending partials; the others transform.
+    const int red = part != nullptr ? 1 : 0;
+    if (red && blockIdx.x == 0) {
+        if (ctl->pending) reduce_partials(part, npart, inv3v, inv12v, ctl, 1);
+        return;
+    }
+    fft_xy_body<T, EPT, INV>(src, dst, zps, nx, ny, nzt, G, rs, px, py, twgx, twgy, ctl, force, nullptr, 0, inv3v,
+                             inv12v, xcd_remap(blockIdx.x - red, gridDim.x - red), false);
 }
 
 // 2D FFT over (z, t), filter and inverse (z, t) of block blk's bx columns (the body of k_fft_zt).
