@@ -639,7 +639,12 @@ template <typename T, int NE>
 void launch_brick(gf_ctx* c, const void* h, int force, Ctl* ctl, void* dst, int nact) {
     const Layout& L = c->L;
     const size_t lds = brick_lds(L.n[0], L.n[1], L.n[2], L.bk.by, L.bk.bz, sizeof(T));
-#define GF_BRICK(NTB)                                                                                                case NTB:                                                                                                            hipLaunchKernelGGL((k_update_measure_brick<T, NE, NTB>), dim3(loop_blocks(L), nact), dim3(NTB), lds,                                c->st, links_of<T, NE>(c), reinterpret_cast<const cx<T>*>(h), cxp<T>(dst), L.ps,                                 c->geom, L.bk, c->part, ctl, bt(c), force);                                                   break;
+#define GF_BRICK(NTB)                                                                                  \
+    case NTB:                                                                                          \
+        hipLaunchKernelGGL((k_update_measure_brick<T, NE, NTB>), dim3(loop_blocks(L), nact), dim3(NTB), lds, \
+                           c->st, links_of<T, NE>(c), reinterpret_cast<const cx<T>*>(h), cxp<T>(dst), L.ps,   \
+                           c->geom, L.bk, c->part, ctl, bt(c), force);                                  \
+        break;
     switch (L.bk_threads) {
         GF_BRICK(256)
         GF_BRICK(512)
@@ -658,7 +663,10 @@ void launch_loop_kernel(gf_ctx* c, const void* h, int force, Ctl* ctl, void* dst
         launch_brick<T, NE>(c, h, force, ctl, dst, nact);
         return;
     }
-    auto kern = L.zb == 0 ? k_update_measure<T, NE, true> : k_update_measure<T, NE, false>;
+    // 32-bit load offsets while the links' array spans less than 4 GiB (the transform's array is smaller)
+    const bool o32 = (size_t)4 * NE * L.ps * sizeof(cx<T>) < ((size_t)1 << 32);
+    auto kern = L.zb == 0 ? (o32 ? k_update_measure<T, NE, true, true> : k_update_measure<T, NE, true, false>)
+                          : (o32 ? k_update_measure<T, NE, false, true> : k_update_measure<T, NE, false, false>);
     hipLaunchKernelGGL(kern, dim3(loop_blocks(L), nact), dim3(kFusedThreads), 0, c->st, links_of<T, NE>(c),
                        reinterpret_cast<const cx<T>*>(h), cxp<T>(dst), L.ps, c->geom, c->part, ctl, bt(c), L.zb,
                        force);

@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kFusedThreads, 2) k_fused_loop(const FusedGrou
     const int mu = lane >> 4;
     const int64_t s = (int64_t)sb * kFusedSites + (threadIdx.x >> 6) * 16 + (lane & 15);
     double fsum, tsum;
-    loop_site_block<T, NE>(io, g.geom, s, s < g.geom.vol, mu, false, nullptr, fsum, tsum);
+    loop_site_block<T, NE, false>(io, g.geom, s, s < g.geom.vol, mu, false, nullptr, fsum, tsum);
     if (threadIdx.x == 0) {
         fshift(g.part, o)[sb] = make_double2(fsum, tsum);
         if (sb == 0) ctl->pending = 1;

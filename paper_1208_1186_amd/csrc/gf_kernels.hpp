@@ -468,6 +468,17 @@ __device__ __forceinline__ double xor_sum4(double v) {
 constexpr int kFusedThreads = 256;
 constexpr int kFusedSites = kFusedThreads / 4;
 
+// Element at a 32-bit byte offset from a wave-uniform base: the scalar-base form of the global memory
+// instructions, one offset register per lane for every plane instead of a 64-bit address per load.
+template <typename T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <typename T>
+__device__ __forceinline__ void st_off(T* base, uint32_t off, const T& v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
+}
+
 template <typename T, int NE>
 struct LoopIO {
     Links<T, NE> U0;
@@ -479,8 +490,11 @@ struct LoopIO {
 // One site block: site s of this lane (valid if inside the lattice), direction mu. With keep set
 // (t-march), the lane of direction t stores its own anti-Hermitian part there (an LDS slot of its site),
 // and with reuse (after the block's first step) it takes the back neighbour's from there first. Returns
-// this block's partial sums in thread 0.
-template <typename T, int NE>
+// this block's partial sums in thread 0. O32: the arrays of U0 and H span less than 4 GiB, so every
+// load takes a 32-bit byte offset from the array's base (one register per lane and array instead of a
+// 64-bit address). Measured: the FP64-18 sweep fits 128 VGPRs with it (four waves per SIMD instead of
+// three) but runs no faster at 32^4; the float sweep at 32^3 x 64 went from 189 to 183 us.
+template <typename T, int NE, bool O32>
 __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const Geom& g, int64_t s, bool valid,
                                                 int mu, bool reuse, AhAcc<T>* keep, double& fsum,
                                                 double& tsum) {
@@ -505,16 +519,37 @@ __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const G
         // already on their way for its own link and H, so no extra traffic, and no branch around the loads)
         const int64_t sld = reuse ? s : sbk;
         su3<T> h0, hfw, hb, u, ub;
+        if constexpr (O32) {
+            constexpr uint32_t E = sizeof(cx<T>);
+            const uint32_t oh0 = tile_byte_offset<cx<T>>(6, (uint32_t)s);
+            const uint32_t ohf = tile_byte_offset<cx<T>>(6, (uint32_t)sfw);
+            const uint32_t ohb = tile_byte_offset<cx<T>>(6, (uint32_t)sld);
+            const uint32_t om = (uint32_t)(mu * NE * kTileSites) * E;
+            const uint32_t ou0 = tile_byte_offset<cx<T>>(4 * NE, (uint32_t)s) + om;
+            const uint32_t oub = tile_byte_offset<cx<T>>(4 * NE, (uint32_t)sld) + om;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            h0.e[k / 3][k % 3] = io.H[tile_index(6, k, s)];
-            hfw.e[k / 3][k % 3] = io.H[tile_index(6, k, sfw)];
-            hb.e[k / 3][k % 3] = io.H[tile_index(6, k, sld)];
-        }
+            for (int k = 0; k < 6; ++k) {
+                h0.e[k / 3][k % 3] = ld_off(io.H + k * kTileSites, oh0);
+                hfw.e[k / 3][k % 3] = ld_off(io.H + k * kTileSites, ohf);
+                hb.e[k / 3][k % 3] = ld_off(io.H + k * kTileSites, ohb);
+            }
 #pragma unroll
-        for (int k = 0; k < NE; ++k) {
-            u.e[k / 3][k % 3] = io.U0.p[io.U0.at(mu, k, s)];
-            ub.e[k / 3][k % 3] = io.U0.p[io.U0.at(mu, k, sld)];
+            for (int k = 0; k < NE; ++k) {
+                u.e[k / 3][k % 3] = ld_off(io.U0.p + k * kTileSites, ou0);
+                ub.e[k / 3][k % 3] = ld_off(io.U0.p + k * kTileSites, oub);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                h0.e[k / 3][k % 3] = io.H[tile_index(6, k, s)];
+                hfw.e[k / 3][k % 3] = io.H[tile_index(6, k, sfw)];
+                hb.e[k / 3][k % 3] = io.H[tile_index(6, k, sld)];
+            }
+#pragma unroll
+            for (int k = 0; k < NE; ++k) {
+                u.e[k / 3][k % 3] = io.U0.p[io.U0.at(mu, k, s)];
+                ub.e[k / 3][k % 3] = io.U0.p[io.U0.at(mu, k, sld)];
+            }
         }
         third_row(h0.e[0], h0.e[1], h0.e[2]);
         third_row(hfw.e[0], hfw.e[1], hfw.e[2]);
@@ -559,8 +594,8 @@ __device__ __forceinline__ void loop_site_block(const LoopIO<T, NE>& io, const G
 
 // force: measure even when the control block says the loop has stopped (a standalone measurement).
 // TM: the t-march traversal (zb is then ignored); its own instantiation, so that the other traversals
-// keep their register budget.
-template <typename T, int NE, bool TM>
+// keep their register budget. O32: 32-bit load offsets (arrays below 4 GiB).
+template <typename T, int NE, bool TM, bool O32>
 __global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE> U0, const cx<T>* __restrict__ H,
                                                                      cx<T>* __restrict__ D, size_t ps, Geom g,
                                                                      double2* __restrict__ part, Ctl* ctl, Batch bt,
@@ -588,7 +623,7 @@ __global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE
 #pragma unroll 1
         for (int t = 0; t < g.n[3]; ++t) {
             const int64_t s = (int64_t)b * kFusedSites + in_block + vs * t;
-            loop_site_block<T, NE>(io, g, s, true, mu, t > 0 && mu == 3, &keep[in_block], fsum, tsum);
+            loop_site_block<T, NE, O32>(io, g, s, true, mu, t > 0 && mu == 3, &keep[in_block], fsum, tsum);
             if (threadIdx.x == 0) part[b + sbt * t] = make_double2(fsum, tsum);
             __syncthreads();  // the block sum's LDS slots are written again in the next step
         }
@@ -602,7 +637,7 @@ __global__ void __launch_bounds__(kFusedThreads, 2) k_update_measure(Links<T, NE
             sb = (z + g.n[2] * t) * bpp + off;
         }
         const int64_t s = (int64_t)sb * kFusedSites + in_block;
-        loop_site_block<T, NE>(io, g, s, s < g.vol, mu, false, nullptr, fsum, tsum);
+        loop_site_block<T, NE, O32>(io, g, s, s < g.vol, mu, false, nullptr, fsum, tsum);
         if (threadIdx.x == 0) part[sb] = make_double2(fsum, tsum);
     }
     if (threadIdx.x == 0 && b == 0) ctl->pending = 1;
@@ -652,17 +687,6 @@ struct AhPlanes {
         return a;
     }
 };
-
-// Element at a 32-bit byte offset from a wave-uniform base: the scalar-base form of the global memory
-// instructions, one offset register per lane for every plane instead of a 64-bit address per load.
-template <typename T>
-__device__ __forceinline__ T ld_off(const T* base, uint32_t off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
-}
-template <typename T>
-__device__ __forceinline__ void st_off(T* base, uint32_t off, const T& v) {
-    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off) = v;
-}
 
 // Anti-Hermitian part of U_m(xb) = H(xb) U0_m(xb) H(x)^dag, xb the back neighbour of x along m (site
 // indices below 2^32 / 16; the caller checks the lattice fits).
