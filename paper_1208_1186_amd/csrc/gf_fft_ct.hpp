@@ -1,8 +1,11 @@
 // FFT pass kernels specialised at compile time for the plane shapes of the
 // standard workloads (x-y planes 8^2 .. 48^2, z-t planes of the 8^4, 12^4,
-// 16^4, 24^3x8, 32^3x4, 48^3x8, 32^4 and 32^3x64 lattices). They compute
-// exactly what the runtime-shaped kernels in gf_kernels.hpp compute; other
-// shapes use those.
+// 16^4, 24^3x8, 32^3x4, 48^3x8, 32^4 and 32^3x64 lattices). They compute the
+// same transforms as the runtime-shaped kernels in gf_kernels.hpp (which
+// other shapes use), with some stages reading or writing memory directly; the
+// inverse t transform takes its radices in the reverse order and the inverse
+// (x, y) pass transforms y first, so the two families agree to rounding, and
+// all tilings of one family bitwise.
 #pragma once
 
 #include "gf_kernels.hpp"
