@@ -546,7 +546,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the lattice would shard in t-slabs with halo exchange and FFT transposes; not built).",
               file=sys.stderr)
         sys.exit(2)

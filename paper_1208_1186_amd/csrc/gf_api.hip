@@ -1535,7 +1535,8 @@ gf_status plan_batch(int32_t n, const gf_params* params, BatchState& b, std::str
     return GF_OK;
 }
 
-// The per-shape tables of the fused passes (configuration 0 of each shape; the drivers' carved buffers).
+// The per-shape tables of the fused passes (configuration 0 of each shape: the buffers carved for the
+// group's launching context, drv).
 template <typename T>
 FusedGroup<T> fused_group(const BatchGroup& g, int ph) {
     const gf_ctx* d = g.drv[ph];
