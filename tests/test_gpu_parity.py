@@ -238,6 +238,27 @@ def test_workload_shapes_filter_and_gauge(dims, generic, precision):
     assert np.max(np.abs(out.cpu().numpy() - g_want)) < (1e-13 if precision.startswith("fp64") else 2e-6)
 
 
+@pytest.mark.parametrize("dims", [(64, 8, 8, 8), (8, 64, 8, 8)])
+@pytest.mark.parametrize("precision", ["fp64_18", "fp32_12"])
+def test_widest_planes_with_a_compile_time_zt_shape(dims, precision):
+    """x or y at the largest extent the library takes (64), on (z, t) planes with a compile-time pass: its
+    sin^2 tables in LDS are then full; the filter and gauge stage match the oracle."""
+    print(f"widest plane {dims} {precision}", flush=True)
+    u = synth.make_config(dims, 12)
+    d = landau.divergence(u)
+    dt = landau.fa_filter(d)
+    fx, _ = fixer_for(u, precision)
+    d_dev = to_dev(d)
+    out = torch.empty_like(d_dev)
+    gf.gf_stage_filter(fx.ctx, d_dev.data_ptr(), out.data_ptr())
+    want = 0.5 * ALPHA * dt
+    fp64 = precision.startswith("fp64")
+    assert np.max(np.abs(out.cpu().numpy() - want)) <= (1e-12 if fp64 else 3e-6) * np.max(np.abs(want))
+    gf.gf_stage_gauge(fx.ctx, d_dev.data_ptr(), out.data_ptr())
+    g_want = landau.gauge_from_delta(dt, ALPHA)
+    assert np.max(np.abs(out.cpu().numpy() - g_want)) < (1e-13 if fp64 else 2e-6)
+
+
 def compiled_tilings(fx):
     """(xy_planes, zt_columns) compiled for the context's shape and precision, from the refusal of an
     impossible pair (its message lists them)."""
