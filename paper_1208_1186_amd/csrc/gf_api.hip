@@ -128,7 +128,8 @@ void set_zt_tile(Layout& L, int bx) {
 }
 
 // (z, t) planes whose pass holds whole lines in registers (k_fft_zt_reg, BX columns per block); for these
-// shapes it replaces the LDS Stockham tilings. Measured at 32^4: float 23.9 against 32.1 us; in double the
+// shapes it replaces the LDS Stockham tilings. Measured at 32^4: float 23.9 against 32.1 us (21.0-21.2
+// against 21.3-21.4 once the LDS stages read and wrote memory directly and shared the filter stage); in double the
 // 32-point lines take all 256 registers (one wave per SIMD) and the pass was slower (47.7 against 43.6 us),
 // as was float on 32 x 64 planes (103 against 71 us), so those keep the LDS passes.
 #define GF_ZT_REG_F64(X)
