@@ -64,22 +64,32 @@ PMC_PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles
 KERNEL_SOURCES = ["paper_1208_1186_amd/csrc/gf_device.hpp", "paper_1208_1186_amd/csrc/gf_kernels.hpp"]
 
 
+def kernel_source_digest(root=None):
+    """sha256 of the loop kernel's sources with comments and blank lines removed: the code the committed
+    counter summaries were taken on (a comment edit leaves it unchanged)."""
+    import hashlib
+    import re
+    root = root or os.path.dirname(os.path.abspath(__file__))
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        text = open(os.path.join(root, f)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(l.rstrip() for l in text.splitlines() if l.strip()).encode())
+    return h.hexdigest()
+
+
 def counted_traffic(prec, dims, traversal=None):
     """HBM bytes per launch of the loop kernel from the committed rocprofv3 FETCH/WRITE passes, scaled by
-    the copy calibration; None if there is no such profile or the kernel sources changed since. The
+    the copy calibration; None if there is no such profile or the kernel code changed since. The
     traversal's own counter lines (`fetch_kib_per_dispatch_z<traversal>:`) are taken when the profile
     has them, else the generic ones."""
-    import hashlib
     import re
     path = PMC_PROFILE.format(prec=prec, dims="x".join(str(d) for d in dims))
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    h = hashlib.sha256()
-    root = os.path.dirname(os.path.abspath(__file__))
-    for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(root, f), "rb").read())
-    if h.hexdigest() not in text:
+    if kernel_source_digest() not in text:
         return None
     vals = {}
     for key in ["fetch_scale", "write_scale", "fetch_kib_per_dispatch", "write_kib_per_dispatch"]:

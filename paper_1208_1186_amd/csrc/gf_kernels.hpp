@@ -7,8 +7,9 @@
 // site written instead of the 576 of four FP64 links (the iteration is
 // memory-bound). One loop iteration, from k to k + 1 applied updates (paper,
 // Section 1 for the method, Section 2.2 for the per-element FFT split 2D + 2D):
-//   k_fft_xy<fwd>   Delta (buffer D) -> 2D FFT over (x, y) -> buffer Q; block 0
-//                   also reduces the theta/F partials left by the loop kernel
+//   k_fft_xy<fwd>   Delta (buffer D) -> 2D FFT over (x, y) -> buffer Q; one more
+//                   block, dispatched first, reduces the theta/F partials left by
+//                   the loop kernel
 //   k_fft_zt        in Q: 2D FFT over (z, t), times (alpha/2) K(p) / V, inverse
 //   k_fft_xy_gauge  Q -> inverse 2D FFT over (x, y) -> g = reunitarize(1 +
 //                   (alpha/2) Delta~), H_{k+1} = reunitarize(g H_k) -> the
@@ -930,8 +931,10 @@ __global__ void __launch_bounds__(kSiteThreads) k_promote_h(const cx<float>* __r
 // 2D FFT over the (x, y) plane, src -> dst (may alias). Each block takes G
 // consecutive planes of one field (flattened plane index = field * Nz*Nt +
 // z + Nz*t), stages them in LDS with rows padded to rs elements, transforms
-// along x then y, and writes them out. With part set, block 0 first reduces
-// the loop kernel's pending partials (npart of them) into the control block.
+// along x then y, and writes them out. With part set and first true, the block
+// first reduces the loop kernel's pending partials (npart of them) into the
+// control block (the fused batch's first block of a configuration; the
+// per-shape kernels give the reduction a block of its own).
 template <typename T, int EPT, bool INV>
 __device__ __forceinline__ void fft_xy_body(const cx<T>* src, cx<T>* dst, size_t zps, int nx, int ny, int nzt,
                                             int G, int rs, const FftPlan& px, const FftPlan& py,
