@@ -271,10 +271,11 @@ def compiled_tilings(fx):
     return xs, zs
 
 
-@pytest.mark.parametrize("dims", CT_SHAPES + [(48, 48, 48, 8), (32, 32, 32, 32)])
+@pytest.mark.parametrize("dims", CT_SHAPES + [(48, 48, 48, 8), (32, 32, 32, 32), (8, 8, 32, 64)])
 @pytest.mark.parametrize("precision", ["fp64_18", "fp32_12"])
 def test_every_compiled_tiling(dims, precision):
-    """Every compile-time FFT tiling of the workload shapes, not only the one the autotuner keeps."""
+    """Every compile-time FFT tiling of the workload shapes, not only the one the autotuner keeps (8 x 8 x 32
+    x 64 carries the (z, t) planes of the 32^3 x 64 lattice)."""
     u = synth.make_config(dims, 11)
     d = landau.divergence(u)
     dt = landau.fa_filter(d)
